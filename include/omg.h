@@ -1,0 +1,194 @@
+/*
+ * omg.h -- C ABI of the MI355X orthonormalization-multigrid (OrthoMG) library.
+ *
+ * The library solves A x = b for a symmetric positive definite block-sparse
+ * A (one dense bs x bs block per cell of a Cartesian grid) with the K-cycle
+ * orthonormalization multigrid of the paper: residual minimisation by modified
+ * Gram-Schmidt (Algorithm 1, Sec. 3.1) inside the multiplicative cycle
+ * (Algorithm 2, Sec. 3.1) or the semi-asynchronous cycle (Algorithm 5, Sec. 4,
+ * in a deterministic form), damped block-Jacobi smoothing (Algorithm 4,
+ * Sec. 3.3), 2x2x2 agglomeration transfers with Galerkin coarse operators,
+ * level-local stopping rules (Sec. 4.2) and a dense Cholesky solve on the
+ * coarsest level.
+ *
+ * Conventions
+ *   - Pointers are DEVICE pointers (hipMalloc'd, or torch CUDA tensors) unless
+ *     a comment says "host".
+ *   - Vectors are FP64 in cell-major DOF order: entry k of cell c is at
+ *     c*bs + k. Cells are numbered i + nx*(j + ny*k), x fastest.
+ *   - Basis per cell (used by omg_setup_sip and by the transfers): orthonormal
+ *     total-degree-p Legendre products h^{-3/2} psi_a psi_b psi_c,
+ *     psi_m(t) = sqrt(2m+1) P_m(2t-1), ordered by total degree then (a,b,c)
+ *     lexicographically descending: (000),(100),(010),(001),(200),...
+ *     bs = (p+1)(p+2)(p+3)/6.
+ *   - Every call is ordered on the hip stream given at setup (NULL = default
+ *     stream). The host blocks only to read residual norms for stopping tests.
+ *   - Every function returns a status and never throws across the ABI.
+ *   - One host thread per solver. Solvers are independent.
+ */
+#ifndef OMG_H
+#define OMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OMG_OK = 0,
+    OMG_EINVAL = -1,       /* bad argument, malformed matrix, NaN/Inf input */
+    OMG_ENOMEM = -2,       /* device or host allocation failed */
+    OMG_EHIP = -3,         /* a HIP runtime call failed */
+    OMG_ENOTSPD = -4,      /* a diagonal block or the coarsest operator is not SPD */
+    OMG_ENOCONV = -5,      /* max_iter reached; x holds the best iterate */
+    OMG_EBREAKDOWN = -6,   /* reserved: every direction of a solve broke down */
+    OMG_EUNSUPPORTED = -7  /* operation not available for this solver */
+} omg_status;
+
+enum { OMG_SYNC_MULT = 0, OMG_OVERLAP_DET = 1 };               /* cycle variant */
+enum { OMG_FP64 = 0, OMG_MIXED_IR = 1, OMG_MIXED_FLEX = 2 };    /* precision */
+enum { OMG_MAX_LEVELS = 16 };
+
+typedef struct omg_solver omg_solver; /* opaque, library-owned */
+
+/* Cartesian grid and hierarchy: nx*ny*nz cubes of side h, polynomial degree
+ * p, n_levels agglomeration levels (level l has nx>>l cells per side; every
+ * coarsened side must be even). penalty_c scales the SIP penalty
+ * penalty_c (p+1)(p+3)/h (omg_setup_sip only). */
+typedef struct {
+    int32_t nx, ny, nz, p, n_levels;
+    int32_t pad;
+    double h, penalty_c;
+} omg_grid;
+
+/* Block sparse matrix, HOST pointers: row_ptr[n_cells+1], col_idx[nnzb]
+ * (sorted, in range, diagonal present), val[nnzb][bs][bs] row-major FP64.
+ * Copied at setup; the caller may free it afterwards. */
+typedef struct {
+    int32_t n_cells, bs;
+    int64_t nnzb;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} omg_bsr;
+
+typedef struct {
+    int32_t variant;      /* OMG_SYNC_MULT (Algorithm 2) or OMG_OVERLAP_DET (Algorithm 5, deterministic) */
+    int32_t coarse_sync;  /* OVERLAP_DET: 1 = levels >= 1 run the multiplicative cycle */
+    int32_t s_pre;        /* block-Jacobi iterations per pre-smoother call */
+    int32_t s_post;       /* block-Jacobi iterations per post-smoother call */
+    int32_t n_s;          /* OVERLAP_DET: smoother+RM steps per cycle */
+    int32_t max_iter;     /* finest-level cycles before OMG_ENOCONV */
+    int32_t precision;    /* OMG_FP64, OMG_MIXED_IR (FP32 inner + FP64 refinement), OMG_MIXED_FLEX */
+    int32_t max_outer;    /* OMG_MIXED_IR: refinement steps */
+    int32_t overlap_streams; /* OVERLAP_DET: 1 = coarse path on a second stream, 0 = one stream */
+    int32_t trace;        /* 1 = record the finest-level residual after every RM (extra syncs) */
+    double omega;         /* block-Jacobi damping */
+    double inner_tol;     /* OMG_MIXED_IR: relative tolerance of each inner solve */
+    double breakdown;     /* RM drops a direction when ||w_out|| <= breakdown * ||w_in|| */
+    double crit_rel[OMG_MAX_LEVELS]; /* level l>=1: stop when ||r|| <= crit_rel[l-1]*||r0|| (<0: off) */
+    int32_t crit_max[OMG_MAX_LEVELS];/* level l>=1: stop after crit_max[l-1] iterations */
+} omg_options;
+
+typedef struct {
+    int32_t status;
+    int32_t iters_fine;     /* finest-level cycles (summed over refinement steps) */
+    int32_t n_dirs_fine;    /* directions stored on the finest level */
+    int32_t n_breakdowns;   /* directions dropped by RM, all levels */
+    int32_t outer_iters;    /* OMG_MIXED_IR refinement steps */
+    int32_t n_visits;       /* entries in the visit log (omg_get_visits) */
+    int32_t n_trace;        /* entries in the residual trace (omg_get_trace) */
+    int32_t pad;
+    double rel_res_rec;     /* recursive ||r||/||b|| on the finest level */
+    double rel_res_true;    /* ||b - A x||/||b|| recomputed in FP64 */
+    double t_solve_ms;      /* wall time of the solve (host clock, stream synchronised) */
+} omg_report;
+
+/* Defaults: SYNC_MULT, s_pre = s_post = 1, n_s = 1, omega = 0.7,
+ * max_iter = 1000, FP64, level criteria of Sec. 4.2 (level 1: 0.1 or 20
+ * iterations; level 2: 0.5 or 2; deeper: 1 iteration), breakdown 1e-14. */
+void omg_default_options(omg_options *opt);
+
+/* Setup from an assembled fine operator (Algorithm 2's A). Builds the
+ * hierarchy of the grid (2x2x2 agglomeration, P = L2 embedding of coarse
+ * polynomials, R = P^T, Galerkin A_{l+1} = P^T A_l P), the block-diagonal
+ * inverses of Algorithm 4 and the dense Cholesky factor of the coarsest level.
+ * A->bs must equal the basis size of grid->p; A->n_cells = nx*ny*nz.
+ * hip_stream: hipStream_t (NULL = default). Errors: OMG_EINVAL (shape,
+ * pattern, non-finite values), OMG_ENOTSPD, OMG_ENOMEM, OMG_EHIP. */
+omg_status omg_setup(const omg_bsr *A, const omg_grid *grid, const omg_options *opt, void *hip_stream,
+                     omg_solver **out);
+
+/* Setup with the operator assembled on the device from a per-cell coefficient
+ * nu[n_cells] (DEVICE pointer, FP64, > 0): symmetric interior penalty DG for
+ * -div(nu grad u) = f on the grid (Sec. 2), face terms weighted by the
+ * harmonic mean 2 nu- nu+ / (nu- + nu+), penalty penalty_c (p+1)(p+3)/h,
+ * Nitsche Dirichlet faces weighted by the cell's nu. Enables
+ * omg_solve_backward's g_nu. */
+omg_status omg_setup_sip(const omg_grid *grid, const double *nu, const omg_options *opt, void *hip_stream,
+                         omg_solver **out);
+
+/* (x, r) = MG(A, b, x0) (Algorithm 2 / 5): on entry x holds x0, on exit the
+ * solution with ||b - A x|| <= tol ||b|| (recursive residual; the true
+ * residual is reported). b is not written. r_out (nullable) receives the
+ * final recursive residual. rep (host, nullable) is filled. OMG_ENOCONV
+ * leaves the last iterate in x. b = 0 gives x = 0 at once. */
+omg_status omg_solve(omg_solver *s, const double *b, double *x, double tol, double *r_out, omg_report *rep);
+
+/* Batched solve. n_inst solvers (host array s[n_inst]), each with nrhs
+ * right-hand sides: b[i], x[i] are device arrays of shape (N_i, nrhs) with
+ * the RHS index fastest. Each column is the same solve as omg_solve on that
+ * column alone. rep: host array of n_inst*nrhs reports (nullable). */
+omg_status omg_solve_batched(omg_solver *const *s, int32_t n_inst, int32_t nrhs, const double *const *b,
+                             double *const *x, double tol, omg_report *rep);
+
+/* Gradient of a scalar loss L(u) with u = A(nu)^-1 f, given u and g_u = dL/du:
+ * lambda = A^-1 g_u (adjoint solve on the same hierarchy, A symmetric),
+ * g_f = lambda, g_nu[K] = -lambda^T (dA/dnu_K) u (per-cell contraction).
+ * g_f, g_nu nullable. g_nu needs a solver from omg_setup_sip
+ * (else OMG_EUNSUPPORTED). */
+omg_status omg_solve_backward(omg_solver *s, const double *u, const double *g_u, double *g_f, double *g_nu,
+                              double tol, omg_report *rep);
+
+void omg_destroy(omg_solver *s);
+const char *omg_strerror(omg_status st);
+
+/* ---- inspection (for tests and benchmarks) ------------------------------ */
+
+/* Level sizes: cells, stored blocks per row (ELL width), directions stored. */
+omg_status omg_level_info(const omg_solver *s, int32_t level, int32_t *n_cells, int32_t *ell_width,
+                          int32_t *k_dirs);
+/* Copy level l's operator out in BSR form (host arrays sized from
+ * omg_level_info: row_ptr[n+1], col_idx[n*width], val[n*width*bs*bs]);
+ * returns the number of stored blocks in *nnzb (explicit zero padding
+ * blocks are dropped). */
+omg_status omg_level_matrix(const omg_solver *s, int32_t level, int32_t *row_ptr, int32_t *col_idx, double *val,
+                            int64_t *nnzb);
+/* y = b - A_l x (b nullable: y = A_l x), FP64, cell-major device vectors. */
+omg_status omg_level_spmv(omg_solver *s, int32_t level, const double *x, const double *b, double *y);
+/* out = Smoother(A_l, r, 0) with `sweeps` block-Jacobi iterations (Algorithm 4). */
+omg_status omg_level_smoother(omg_solver *s, int32_t level, const double *r, int32_t sweeps, double *out);
+/* rc = P_l^T r (level l -> l+1) and z = P_l zc (level l+1 -> l). */
+omg_status omg_level_restrict(omg_solver *s, int32_t level, const double *r, double *rc);
+omg_status omg_level_prolong(omg_solver *s, int32_t level, const double *zc, double *z);
+/* x = A_c^-1 b on the coarsest level. */
+omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
+/* Stored directions of level l after the last solve (device, cell-major,
+ * [k][N] each); W or Z nullable. */
+omg_status omg_get_dirs(const omg_solver *s, int32_t level, double *W, double *Z);
+/* Visit log of the last solve: pairs (level, iterations) in visit order
+ * (host out[2*cap]); returns the count through *n. */
+omg_status omg_get_visits(const omg_solver *s, int32_t *out, int32_t cap, int32_t *n);
+/* Residual trace of the last solve (needs opt.trace): triples
+ * (step, ||r||, type: 0 initial, 1 smoother, 2 coarse, 3 final), host. */
+omg_status omg_get_trace(const omg_solver *s, double *out, int32_t cap, int32_t *n);
+/* Replay: make the next solve(s) use these per-visit iteration counts
+ * (host pairs (level, iterations), n entries) instead of the level tests;
+ * n = 0 switches replay off. */
+omg_status omg_set_replay(omg_solver *s, const int32_t *visits, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OMG_H */

@@ -1,0 +1,344 @@
+"""Python binding of the MI355X OrthoMG library (``libomg.so``).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels. torch supplies device memory (tensor ``data_ptr()``) and the current
+HIP stream. Importing this module does not load the library; the first use
+does, and raises if the built library is missing (no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libomg.so")
+MAX_LEVELS = 16
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+SYNC_MULT, OVERLAP_DET = 0, 1
+FP64, MIXED_IR, MIXED_FLEX = 0, 1, 2
+
+
+class OmgError(RuntimeError):
+    def __init__(self, status, what=""):
+        msg = lib().omg_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("pad", ctypes.c_int32), ("h", ctypes.c_double),
+                ("penalty_c", ctypes.c_double)]
+
+
+class Bsr(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32), ("bs", ctypes.c_int32), ("nnzb", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("coarse_sync", ctypes.c_int32), ("s_pre", ctypes.c_int32),
+                ("s_post", ctypes.c_int32), ("n_s", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("overlap_streams", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("inner_tol", ctypes.c_double), ("breakdown", ctypes.c_double),
+                ("crit_rel", ctypes.c_double * MAX_LEVELS), ("crit_max", ctypes.c_int32 * MAX_LEVELS)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters_fine", ctypes.c_int32), ("n_dirs_fine", ctypes.c_int32),
+                ("n_breakdowns", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("n_visits", ctypes.c_int32),
+                ("n_trace", ctypes.c_int32), ("pad", ctypes.c_int32), ("rel_res_rec", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "omg_solve_batched",
+           "omg_solve_backward", "omg_destroy", "omg_strerror", "omg_level_info", "omg_level_matrix",
+           "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
+           "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay"]
+
+
+def lib():
+    """Load libomg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_08728_amd/build.py "
+                              "(no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.omg_default_options.argtypes = [P]
+        L.omg_default_options.restype = None
+        L.omg_setup.argtypes = [P, P, P, P, ctypes.POINTER(P)]
+        L.omg_setup_sip.argtypes = [P, P, P, P, ctypes.POINTER(P)]
+        L.omg_solve.argtypes = [P, P, P, d, P, P]
+        L.omg_solve_batched.argtypes = [P, i32, i32, P, P, d, P]
+        L.omg_solve_backward.argtypes = [P, P, P, P, P, d, P]
+        L.omg_destroy.argtypes = [P]
+        L.omg_destroy.restype = None
+        L.omg_strerror.argtypes = [ctypes.c_int]
+        L.omg_strerror.restype = ctypes.c_char_p
+        L.omg_level_info.argtypes = [P, i32, P, P, P]
+        L.omg_level_matrix.argtypes = [P, i32, P, P, P, P]
+        L.omg_level_spmv.argtypes = [P, i32, P, P, P]
+        L.omg_level_smoother.argtypes = [P, i32, P, i32, P]
+        L.omg_level_restrict.argtypes = [P, i32, P, P]
+        L.omg_level_prolong.argtypes = [P, i32, P, P]
+        L.omg_coarse_solve.argtypes = [P, P, P]
+        L.omg_get_dirs.argtypes = [P, i32, P, P]
+        L.omg_get_visits.argtypes = [P, P, i32, P]
+        L.omg_get_trace.argtypes = [P, P, i32, P]
+        L.omg_set_replay.argtypes = [P, P, i32]
+        for name in EXPORTS:
+            if name not in ("omg_default_options", "omg_destroy", "omg_strerror"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != OK:
+        raise OmgError(st, what)
+
+
+def options(**kw) -> Options:
+    """omg_options with defaults; keyword names as in the struct. ``variant``
+    accepts 'sync'/'overlap', ``precision`` 'fp64'/'mixed_ir'/'mixed_flex', and
+    ``crit`` a list of (rel, max) pairs for levels 1, 2, ..."""
+    o = Options()
+    lib().omg_default_options(ctypes.byref(o))
+    names = {"sync": SYNC_MULT, "overlap": OVERLAP_DET, "fp64": FP64, "mixed_ir": MIXED_IR,
+             "mixed_flex": MIXED_FLEX}
+    crit = kw.pop("crit", None)
+    for k, v in kw.items():
+        if isinstance(v, str):
+            v = names[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    if crit is not None:
+        for l in range(MAX_LEVELS):
+            rel, mx = crit[l] if l < len(crit) else (-1.0, 1)
+            o.crit_rel[l] = rel
+            o.crit_max[l] = mx
+    return o
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Owns one library solver (hierarchy, factors, workspaces) on cuda:0."""
+
+    def __init__(self, handle, grid: Grid, has_sip: bool):
+        self._h = handle
+        self.grid = grid
+        self.bs = (grid.p + 1) * (grid.p + 2) * (grid.p + 3) // 6
+        self.n_cells = grid.nx * grid.ny * grid.nz
+        self.n = self.n_cells * self.bs
+        self.has_sip = has_sip
+        self.last_report = None
+
+    @staticmethod
+    def make_grid(nx, ny, nz, p, n_levels, h=None, penalty_c=4.0) -> Grid:
+        return Grid(nx, ny, nz, p, n_levels, 0, 1.0 / nx if h is None else h, penalty_c)
+
+    @classmethod
+    def from_bsr(cls, row_ptr, col_idx, val, grid: Grid, **opts):
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        bs = (grid.p + 1) * (grid.p + 2) * (grid.p + 3) // 6
+        A = Bsr(len(row_ptr) - 1, bs, len(col_idx), row_ptr.ctypes.data, col_idx.ctypes.data, val.ctypes.data)
+        h = ctypes.c_void_p()
+        o = options(**opts)
+        _check(lib().omg_setup(ctypes.byref(A), ctypes.byref(grid), ctypes.byref(o), _stream(), ctypes.byref(h)),
+               "omg_setup")
+        return cls(h, grid, False)
+
+    @classmethod
+    def from_sip(cls, grid: Grid, nu, **opts):
+        import torch
+        nu = torch.as_tensor(nu, dtype=torch.float64, device="cuda").contiguous()
+        h = ctypes.c_void_p()
+        o = options(**opts)
+        _check(lib().omg_setup_sip(ctypes.byref(grid), _ptr(nu), ctypes.byref(o), _stream(), ctypes.byref(h)),
+               "omg_setup_sip")
+        return cls(h, grid, True)
+
+    def close(self):
+        if self._h:
+            lib().omg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, x=None, tol=1e-10, check=True, r_out=None):
+        import torch
+        b = torch.as_tensor(b, dtype=torch.float64, device="cuda").contiguous()
+        x = torch.zeros_like(b) if x is None else torch.as_tensor(x, dtype=torch.float64, device="cuda").clone()
+        rep = Report()
+        st = lib().omg_solve(self._h, _ptr(b), _ptr(x), tol, None if r_out is None else _ptr(r_out),
+                             ctypes.byref(rep))
+        self.last_report = rep.as_dict()
+        if check and st != OK:
+            raise OmgError(st, "omg_solve")
+        return x
+
+    def backward(self, u, g_u, tol=1e-10, want_nu=True):
+        import torch
+        u = torch.as_tensor(u, dtype=torch.float64, device="cuda").contiguous()
+        g_u = torch.as_tensor(g_u, dtype=torch.float64, device="cuda").contiguous()
+        g_f = torch.empty_like(u)
+        g_nu = torch.empty(self.n_cells, dtype=torch.float64, device="cuda") if want_nu else None
+        rep = Report()
+        st = lib().omg_solve_backward(self._h, _ptr(u), _ptr(g_u), _ptr(g_f), None if g_nu is None else _ptr(g_nu),
+                                      tol, ctypes.byref(rep))
+        self.last_report = rep.as_dict()
+        if st not in (OK, ENOCONV):
+            raise OmgError(st, "omg_solve_backward")
+        return g_f, g_nu
+
+    # ---- inspection -------------------------------------------------------
+    def level_info(self, l):
+        n, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().omg_level_info(self._h, l, ctypes.byref(n), ctypes.byref(w), ctypes.byref(k)), "level_info")
+        return n.value, w.value, k.value
+
+    def level_matrix(self, l):
+        n, w, _ = self.level_info(l)
+        rp = np.zeros(n + 1, dtype=np.int32)
+        ci = np.zeros(n * w, dtype=np.int32)
+        v = np.zeros((n * w, self.bs, self.bs))
+        nnzb = ctypes.c_int64()
+        _check(lib().omg_level_matrix(self._h, l, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, ctypes.byref(nnzb)),
+               "level_matrix")
+        return rp, ci[:nnzb.value], v[:nnzb.value]
+
+    def level_spmv(self, l, x, b=None):
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().omg_level_spmv(self._h, l, _ptr(x), None if b is None else _ptr(b), _ptr(y)), "level_spmv")
+        return y
+
+    def level_smoother(self, l, r, sweeps):
+        import torch
+        out = torch.empty_like(r)
+        _check(lib().omg_level_smoother(self._h, l, _ptr(r), sweeps, _ptr(out)), "level_smoother")
+        return out
+
+    def level_restrict(self, l, r):
+        import torch
+        nc, _, _ = self.level_info(l + 1)
+        rc = torch.empty(nc * self.bs, dtype=torch.float64, device="cuda")
+        _check(lib().omg_level_restrict(self._h, l, _ptr(r), _ptr(rc)), "level_restrict")
+        return rc
+
+    def level_prolong(self, l, zc):
+        import torch
+        nf, _, _ = self.level_info(l)
+        z = torch.empty(nf * self.bs, dtype=torch.float64, device="cuda")
+        _check(lib().omg_level_prolong(self._h, l, _ptr(zc), _ptr(z)), "level_prolong")
+        return z
+
+    def coarse_solve(self, b):
+        import torch
+        x = torch.empty_like(b)
+        _check(lib().omg_coarse_solve(self._h, _ptr(b), _ptr(x)), "coarse_solve")
+        return x
+
+    def dirs(self, l=0):
+        import torch
+        n, _, k = self.level_info(l)
+        W = torch.empty((k, n * self.bs), dtype=torch.float64, device="cuda")
+        Z = torch.empty_like(W)
+        _check(lib().omg_get_dirs(self._h, l, _ptr(W), _ptr(Z)), "get_dirs")
+        return W, Z
+
+    def visits(self):
+        n = ctypes.c_int32()
+        lib().omg_get_visits(self._h, None, 0, ctypes.byref(n))
+        out = np.zeros(2 * max(n.value, 1), dtype=np.int32)
+        lib().omg_get_visits(self._h, out.ctypes.data, n.value, ctypes.byref(n))
+        return out[: 2 * n.value].reshape(-1, 2)
+
+    def trace(self):
+        n = ctypes.c_int32()
+        lib().omg_get_trace(self._h, None, 0, ctypes.byref(n))
+        out = np.zeros(3 * max(n.value, 1))
+        lib().omg_get_trace(self._h, out.ctypes.data, n.value, ctypes.byref(n))
+        return out[: 3 * n.value].reshape(-1, 3)
+
+    def set_replay(self, visits):
+        v = np.ascontiguousarray(np.asarray(visits, dtype=np.int32).reshape(-1))
+        _check(lib().omg_set_replay(self._h, v.ctypes.data if len(v) else None, len(v) // 2), "set_replay")
+
+
+def solve_batched(solvers, bs_list, xs_list=None, tol=1e-10, nrhs=1):
+    """Batched solve: ``bs_list[i]`` is an (N_i, nrhs) CUDA tensor (RHS index
+    fastest) for solver i. Returns the solutions and the per-column reports."""
+    import torch
+    n = len(solvers)
+    bs_list = [torch.as_tensor(b, dtype=torch.float64, device="cuda").contiguous() for b in bs_list]
+    xs = [torch.zeros_like(b) for b in bs_list] if xs_list is None else [x.clone() for x in xs_list]
+    harr = (ctypes.c_void_p * n)(*[s._h.value for s in solvers])
+    barr = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs_list])
+    xarr = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    reps = (Report * (n * nrhs))()
+    st = lib().omg_solve_batched(harr, n, nrhs, barr, xarr, tol, reps)
+    if st not in (OK,):
+        raise OmgError(st, "omg_solve_batched")
+    return xs, [r.as_dict() for r in reps]
+
+
+def _autograd():
+    import torch
+
+    class SolveFn(torch.autograd.Function):
+        """u = A(exp(log_nu))^-1 f on the SIP operator. Forward: omg_setup_sip +
+        omg_solve; backward: omg_solve_backward (adjoint solve + per-cell
+        contraction). Only (f, log_nu) are saved; the hierarchy is rebuilt in
+        backward (checkpointed forward state)."""
+
+        @staticmethod
+        def forward(ctx, f, log_nu, grid, tol, opts):
+            nu = torch.exp(log_nu.detach()).to(torch.float64).contiguous()
+            s = Solver.from_sip(grid, nu, **(opts or {}))
+            u = s.solve(f.detach(), tol=tol)
+            s.close()
+            ctx.save_for_backward(f, log_nu, u)
+            ctx.grid, ctx.tol, ctx.opts = grid, tol, opts
+            return u
+
+        @staticmethod
+        def backward(ctx, g_u):
+            f, log_nu, u = ctx.saved_tensors
+            nu = torch.exp(log_nu.detach()).to(torch.float64).contiguous()
+            s = Solver.from_sip(ctx.grid, nu, **(ctx.opts or {}))
+            g_f, g_nu = s.backward(u, g_u.contiguous(), tol=ctx.tol)
+            s.close()
+            return g_f, g_nu * nu, None, None, None
+
+    return SolveFn
+
+
+def solve_fn():
+    """The torch.autograd.Function wrapping the differentiable solve."""
+    return _autograd()

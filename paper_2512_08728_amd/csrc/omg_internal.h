@@ -1,0 +1,155 @@
+// Internal declarations of the MI355X OrthoMG library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/omg.h"
+
+namespace omg {
+
+// Threads per block of every streaming kernel, and the fixed grid of the
+// deterministic two-stage reductions (partials are always summed in the same
+// order, so a result does not depend on timing).
+constexpr int kThreads = 256;
+constexpr int kMaxRedBlocks = 1024;
+
+// Device-resident scalars of one level (indices into Level::scal).
+enum Scal : int {
+    S_RNORM = 0,      // ||r|| after the last update
+    S_BREAKDOWNS = 1, // directions dropped by RM on this level
+    S_TMP = 2,
+    S_COUNT = 8
+};
+
+// One level of the hierarchy. Vectors are stored component-major inside the
+// library ("SoA"): entry k of cell c at k*n + c, so that a wavefront of
+// consecutive cells reads consecutive addresses.
+// The operator is stored in an ELL-of-blocks layout: `width` block slots per
+// cell; slot j of cell i holds column cell col[j*n+i] (padding slots point to
+// the cell itself with zero values). Values are interleaved by column pairs:
+// element (slot j, row r, column 2cp+h) of cell i is component h of the
+// 2-vector at index ((j*bs + r)*bsh + cp)*n + i, bsh = ceil(bs/2).
+struct Level {
+    int nx = 0, ny = 0, nz = 0, n = 0; // cells
+    int64_t N = 0;                     // DOFs = n*bs
+    int width = 0;                     // ELL block slots per cell
+    int coarsest = 0;
+    int G = 1;                         // reduction grid for this level
+
+    int* col = nullptr;                // [width][n]
+    double* val = nullptr;             // pairs, see above
+    float* val32 = nullptr;            // FP32 copy (mixed precision)
+    double* dinv = nullptr;            // [bs][bsh][n] pairs: block-diagonal inverses
+    float* dinv32 = nullptr;
+    double* ainv = nullptr;            // coarsest: dense inverse, [np][np] SoA DOF order
+    int np = 0;                        // padded dense order
+
+    std::vector<int> hcol;             // host copy of col (Galerkin symbolic phase)
+    int* dslot = nullptr;              // [n] slot of the diagonal block of each cell
+
+    // work vectors (SoA, N each)
+    double *b = nullptr, *r = nullptr, *x = nullptr, *z = nullptr, *w = nullptr;
+    double *t = nullptr, *t2 = nullptr, *zcor = nullptr, *xout = nullptr;
+    // reduction partials
+    double* part = nullptr;            // [8][kMaxRedBlocks]
+    double* scal = nullptr;            // [S_COUNT]
+
+    // residual-minimisation storage: pointers to direction vectors
+    int k = 0;
+    std::vector<double*> W, Z;         // size = allocated capacity
+    std::vector<double*> chunks;       // backing allocations
+};
+
+struct Trace {
+    double step, rnorm, type;
+};
+
+} // namespace omg
+
+struct omg_solver {
+    omg_options opt;
+    omg_grid grid;
+    int bs = 0, bsh = 0, p = 0, nlev = 0;
+    hipStream_t stream = nullptr;      // caller's stream
+    hipStream_t cstream = nullptr;     // coarse-path stream (OVERLAP_DET)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<omg::Level> lev;
+    double* E = nullptr;               // [8][bs][bs] embedding blocks (device)
+    float* E32 = nullptr;
+    std::vector<double> hE;            // host copy
+    // SIP data (omg_setup_sip)
+    int has_sip = 0;
+    double* nu = nullptr;              // [n_cells] device
+    double* refm = nullptr;            // reference matrices: S, F[3][2][2], B[3][2] (device)
+    // external <-> internal layout buffers (fine level)
+    double *bufA = nullptr, *bufB = nullptr;
+    double* host_scal = nullptr;       // pinned
+    int* err_flag = nullptr;           // device error flag (setup kernels)
+    // logs of the last solve
+    std::vector<int> visits;
+    std::vector<omg::Trace> trace;
+    std::vector<int> replay;
+    size_t replay_pos = 0;
+    int mode32 = 0;                    // 0 FP64, 1 FP32 everywhere, 2 FP32 except finest-level RM
+    int step = 0;
+    int status = 0;
+};
+
+namespace omg {
+
+// ---------------------------------------------------------------- kernels
+// (omg_kernels.hip). Every launcher enqueues on `st` and returns the launch
+// status.
+hipError_t launch_to_soa(const double* in, double* out, int n, int bs, hipStream_t st);
+hipError_t launch_from_soa(const double* in, double* out, int n, int bs, hipStream_t st);
+hipError_t launch_spmv(const Level& L, int bs, bool fp32, const double* x, const double* b, double* y,
+                       hipStream_t st);
+hipError_t launch_bj_first(const Level& L, int bs, bool fp32, double omega, const double* r, double* x,
+                           hipStream_t st);
+hipError_t launch_bj_sweep(const Level& L, int bs, bool fp32, double omega, const double* r, const double* xin,
+                           double* xout, hipStream_t st);
+hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
+                           const double* r, double* rc, hipStream_t st);
+hipError_t launch_prolong(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
+                          const double* zc, double* z, hipStream_t st);
+hipError_t launch_gemv(const Level& L, const double* x, double* y, hipStream_t st);
+
+// reductions: partial sums into part[0..G) (deterministic fixed-order)
+hipError_t launch_dot2(int64_t N, int G, const double* a, const double* b, double* part_ab, const double* c,
+                       double* part_cc, hipStream_t st);
+hipError_t launch_mgs_step(int64_t N, int G, const double* part_in, const double* Wi, const double* Zi, double* w,
+                           double* z, const double* Wnext, double* part_out, hipStream_t st);
+hipError_t launch_rm_normalize(int64_t N, int G, const double* part_nin, const double* part_nout,
+                               double breakdown, const double* w, const double* z, double* Wk, double* Zk,
+                               const double* r, double* part_alpha, double* scal, hipStream_t st);
+hipError_t launch_rm_update(int64_t N, int G, const double* part_alpha, const double* Wk, const double* Zk,
+                            double* x, double* r, double* part_rn, hipStream_t st);
+hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_t st);
+hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st);
+hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st);
+hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStream_t st);
+
+// ---------------------------------------------------------------- setup
+// (omg_setup.hip)
+int reduction_blocks(int64_t N);
+void basis_orders(int p, std::vector<int>& a, std::vector<int>& b, std::vector<int>& c);
+void embedding_blocks(int p, std::vector<double>& E);
+void reference_matrices(int p, double h, double penalty_c, std::vector<double>& out);
+
+} // namespace omg
+
+// error helpers
+#define OMG_TRY_HIP(expr)                                  \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return OMG_EHIP;             \
+    } while (0)
+#define OMG_TRY(expr)                                      \
+    do {                                                   \
+        omg_status s_ = (expr);                            \
+        if (s_ != OMG_OK) return s_;                       \
+    } while (0)

@@ -1,0 +1,505 @@
+// Streaming kernels of the OrthoMG solve for gfx950 (CDNA4, 64-wide waves).
+//
+// Every kernel here is HBM-bound (block SpMV and smoother ~0.25 flop/byte in
+// FP64, vector updates 0.125): one thread owns one cell, reads its block row
+// with 16-byte loads that are coalesced across the wavefront (the ELL layout
+// is interleaved by cell), and keeps the cell's bs outputs in registers.
+// Reductions are deterministic: a fixed grid writes one partial per block,
+// and every consumer sums the partials in the same fixed order.
+#include "omg_internal.h"
+
+namespace omg {
+
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
+// ----------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+    // butterfly: a + b == b + a exactly, so every lane ends with the same value
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block in a fixed order; every thread returns the same value.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// Sum of G partials, same order in every block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int G, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) v += part[i];
+    return block_sum(v, sh);
+}
+
+// ----------------------------------------------------------------- layout
+__global__ void k_to_soa(const double* __restrict__ in, double* __restrict__ out, int n, int bs) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * bs) return;
+    int c = (int)(e / bs), k = (int)(e % bs);
+    out[(int64_t)k * n + c] = in[e];
+}
+__global__ void k_from_soa(const double* __restrict__ in, double* __restrict__ out, int n, int bs) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * bs) return;
+    int c = (int)(e / bs), k = (int)(e % bs);
+    out[e] = in[(int64_t)k * n + c];
+}
+
+// ----------------------------------------------------------------- block SpMV
+// y = A x, or y = b - A x. Thread per cell; MT is the storage type of A and
+// the arithmetic type (FP32 mixed forms accumulate in float).
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_spmv(int n, int width, const int* __restrict__ col,
+                                                   const typename Pair<MT>::type* __restrict__ val,
+                                                   const double* __restrict__ x, const double* __restrict__ b,
+                                                   double* __restrict__ y) {
+    constexpr int BSH = (BS + 1) / 2;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    MT acc[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) acc[r] = MT(0);
+    for (int j = 0; j < width; ++j) {
+        const int c = col[(int64_t)j * n + i];
+        MT xv[2 * BSH];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xv[k] = (MT)x[(int64_t)k * n + c];
+        if (BS & 1) xv[BS] = MT(0);
+        const typename Pair<MT>::type* vj = val + (int64_t)j * BS * BSH * n + i;
+#pragma unroll
+        for (int r = 0; r < BS; ++r) {
+#pragma unroll
+            for (int cp = 0; cp < BSH; ++cp) {
+                const typename Pair<MT>::type a = vj[(int64_t)(r * BSH + cp) * n];
+                acc[r] = fma(a.x, xv[2 * cp], acc[r]);
+                acc[r] = fma(a.y, xv[2 * cp + 1], acc[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+        const int64_t o = (int64_t)r * n + i;
+        y[o] = b ? (double)((MT)b[o] - acc[r]) : (double)acc[r];
+    }
+}
+
+// ----------------------------------------------------------------- block-Jacobi
+// First iteration from x0 = 0: x = omega D^-1 r.
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_bj_first(int n, const typename Pair<MT>::type* __restrict__ dinv,
+                                                       MT omega, const double* __restrict__ r,
+                                                       double* __restrict__ x) {
+    constexpr int BSH = (BS + 1) / 2;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    MT rv[2 * BSH];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) rv[k] = (MT)r[(int64_t)k * n + i];
+    if (BS & 1) rv[BS] = MT(0);
+#pragma unroll
+    for (int rr = 0; rr < BS; ++rr) {
+        MT s = MT(0);
+#pragma unroll
+        for (int cp = 0; cp < BSH; ++cp) {
+            const typename Pair<MT>::type d = dinv[(int64_t)(rr * BSH + cp) * n + i];
+            s = fma(d.x, rv[2 * cp], s);
+            s = fma(d.y, rv[2 * cp + 1], s);
+        }
+        x[(int64_t)rr * n + i] = (double)(omega * s);
+    }
+}
+
+// Fused iteration k >= 2: xout = xin + omega D^-1 (r - A xin).
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_bj_sweep(int n, int width, const int* __restrict__ col,
+                                                       const typename Pair<MT>::type* __restrict__ val,
+                                                       const typename Pair<MT>::type* __restrict__ dinv,
+                                                       MT omega, const double* __restrict__ r,
+                                                       const double* __restrict__ xin, double* __restrict__ xout) {
+    constexpr int BSH = (BS + 1) / 2;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    MT acc[BS];
+#pragma unroll
+    for (int q = 0; q < BS; ++q) acc[q] = MT(0);
+    for (int j = 0; j < width; ++j) {
+        const int c = col[(int64_t)j * n + i];
+        MT xv[2 * BSH];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xv[k] = (MT)xin[(int64_t)k * n + c];
+        if (BS & 1) xv[BS] = MT(0);
+        const typename Pair<MT>::type* vj = val + (int64_t)j * BS * BSH * n + i;
+#pragma unroll
+        for (int q = 0; q < BS; ++q) {
+#pragma unroll
+            for (int cp = 0; cp < BSH; ++cp) {
+                const typename Pair<MT>::type a = vj[(int64_t)(q * BSH + cp) * n];
+                acc[q] = fma(a.x, xv[2 * cp], acc[q]);
+                acc[q] = fma(a.y, xv[2 * cp + 1], acc[q]);
+            }
+        }
+    }
+    MT t[2 * BSH];
+#pragma unroll
+    for (int q = 0; q < BS; ++q) t[q] = (MT)r[(int64_t)q * n + i] - acc[q];
+    if (BS & 1) t[BS] = MT(0);
+#pragma unroll
+    for (int rr = 0; rr < BS; ++rr) {
+        MT s = MT(0);
+#pragma unroll
+        for (int cp = 0; cp < BSH; ++cp) {
+            const typename Pair<MT>::type d = dinv[(int64_t)(rr * BSH + cp) * n + i];
+            s = fma(d.x, t[2 * cp], s);
+            s = fma(d.y, t[2 * cp + 1], s);
+        }
+        const int64_t o = (int64_t)rr * n + i;
+        xout[o] = (double)((MT)xin[o] + omega * s);
+    }
+}
+
+// ----------------------------------------------------------------- transfers
+// Restriction r_c = P^T r: each coarse cell sums E_s^T r_child over its 8
+// children in slot order s = sx + 2 sy + 4 sz. E is [8][BS][BS] (fine row,
+// coarse column).
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_restrict(int fnx, int fny, int fn, int cnx, int cny, int cn,
+                                                       const MT* __restrict__ E, const double* __restrict__ r,
+                                                       double* __restrict__ rc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= cn) return;
+    const int ci = I % cnx, cj = (I / cnx) % cny, ck = I / (cnx * cny);
+    MT out[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) out[c] = MT(0);
+    for (int s = 0; s < 8; ++s) {
+        const int K = (2 * ci + (s & 1)) + fnx * ((2 * cj + ((s >> 1) & 1)) + fny * (2 * ck + ((s >> 2) & 1)));
+        MT rv[BS];
+#pragma unroll
+        for (int m = 0; m < BS; ++m) rv[m] = (MT)r[(int64_t)m * fn + K];
+        const MT* Es = E + s * BS * BS;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            MT a = MT(0);
+#pragma unroll
+            for (int m = 0; m < BS; ++m) a = fma(Es[m * BS + c], rv[m], a);
+            out[c] += a;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < BS; ++c) rc[(int64_t)c * cn + I] = (double)out[c];
+}
+
+// Prolongation z = P z_c: z_K = E_{slot(K)} z_{parent(K)}.
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_prolong(int fnx, int fny, int fn, int cnx, int cny, int cn,
+                                                      const MT* __restrict__ E, const double* __restrict__ zc,
+                                                      double* __restrict__ z) {
+    const int K = blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= fn) return;
+    const int i = K % fnx, j = (K / fnx) % fny, k = K / (fnx * fny);
+    const int I = (i >> 1) + cnx * ((j >> 1) + cny * (k >> 1));
+    const int s = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    MT zv[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) zv[c] = (MT)zc[(int64_t)c * cn + I];
+    const MT* Es = E + s * BS * BS;
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+        MT a = MT(0);
+#pragma unroll
+        for (int c = 0; c < BS; ++c) a = fma(Es[r * BS + c], zv[c], a);
+        z[(int64_t)r * fn + K] = (double)a;
+    }
+}
+
+// ----------------------------------------------------------------- dense GEMV
+// y = A x for the coarsest level's dense inverse (row-major, order np >= n);
+// one wavefront per row.
+__global__ __launch_bounds__(kThreads) void k_gemv(int n, int np, const double* __restrict__ A,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+    const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double* a = A + (int64_t)row * np;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s = fma(a[j], x[j], s);
+    s = wave_sum(s);
+    if (lane == 0) y[row] = s;
+}
+
+// ----------------------------------------------------------------- RM / MGS
+// part_ab[block] = sum a.b over the block's elements; part_cc likewise for c.c
+__global__ __launch_bounds__(kThreads) void k_dot2(int64_t N, const double* __restrict__ a,
+                                                   const double* __restrict__ b, double* __restrict__ part_ab,
+                                                   const double* __restrict__ c, double* __restrict__ part_cc) {
+    __shared__ double sh[kThreads / 64];
+    double s1 = 0.0, s2 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        if (a) s1 = fma(a[e], b[e], s1);
+        if (c) s2 = fma(c[e], c[e], s2);
+    }
+    if (a) {
+        s1 = block_sum(s1, sh);
+        if (threadIdx.x == 0) part_ab[blockIdx.x] = s1;
+    }
+    if (c) {
+        s2 = block_sum(s2, sh);
+        if (threadIdx.x == 0) part_cc[blockIdx.x] = s2;
+    }
+}
+
+// One modified Gram-Schmidt step: beta = sum(part_in) (= W_i . w),
+// w -= beta W_i, z -= beta Z_i, then partials of W_next . w (or w . w when
+// W_next is null) for the following step. Each block updates and then reads
+// only its own elements, so the step needs no grid synchronisation.
+__global__ __launch_bounds__(kThreads) void k_mgs_step(int64_t N, int G, const double* __restrict__ part_in,
+                                                       const double* __restrict__ Wi, const double* __restrict__ Zi,
+                                                       double* __restrict__ w, double* __restrict__ z,
+                                                       const double* __restrict__ Wnext,
+                                                       double* __restrict__ part_out) {
+    __shared__ double sh[kThreads / 64];
+    const double beta = sum_partials(part_in, G, sh);
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double wn = fma(-beta, Wi[e], w[e]);
+        w[e] = wn;
+        z[e] = fma(-beta, Zi[e], z[e]);
+        s = Wnext ? fma(Wnext[e], wn, s) : fma(wn, wn, s);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+}
+
+// gamma = 1/||w|| (0 if the direction broke down), W_k = gamma w,
+// Z_k = gamma z, partials of alpha = W_k . r.
+__global__ __launch_bounds__(kThreads) void k_rm_normalize(int64_t N, int G, const double* __restrict__ part_nin,
+                                                           const double* __restrict__ part_nout, double breakdown,
+                                                           const double* __restrict__ w,
+                                                           const double* __restrict__ z, double* __restrict__ Wk,
+                                                           double* __restrict__ Zk, const double* __restrict__ r,
+                                                           double* __restrict__ part_alpha,
+                                                           double* __restrict__ scal) {
+    __shared__ double sh[kThreads / 64];
+    const double nin = sqrt(sum_partials(part_nin, G, sh));
+    const double nout = sqrt(sum_partials(part_nout, G, sh));
+    const bool keep = nout > breakdown * nin; // false for NaN and for nout == 0
+    const double gamma = keep ? 1.0 / nout : 0.0;
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double wk = gamma * w[e];
+        Wk[e] = wk;
+        Zk[e] = gamma * z[e];
+        s = fma(wk, r[e], s);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        part_alpha[blockIdx.x] = s;
+        if (blockIdx.x == 0 && !keep) scal[S_BREAKDOWNS] += 1.0;
+    }
+}
+
+// alpha = sum(part_alpha); x += alpha Z_k; r -= alpha W_k; partials of r.r
+__global__ __launch_bounds__(kThreads) void k_rm_update(int64_t N, int G, const double* __restrict__ part_alpha,
+                                                        const double* __restrict__ Wk,
+                                                        const double* __restrict__ Zk, double* __restrict__ x,
+                                                        double* __restrict__ r, double* __restrict__ part_rn) {
+    __shared__ double sh[kThreads / 64];
+    const double alpha = sum_partials(part_alpha, G, sh);
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        x[e] = fma(alpha, Zk[e], x[e]);
+        const double rn = fma(-alpha, Wk[e], r[e]);
+        r[e] = rn;
+        s = fma(rn, rn, s);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part_rn[blockIdx.x] = s;
+}
+
+__global__ void k_finish_norm(int G, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sh[kThreads / 64];
+    const double s = sum_partials(part, G, sh);
+    if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t N) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) dst[e] = src[e];
+}
+__global__ void k_fill(double* __restrict__ dst, double v, int64_t N) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) dst[e] = v;
+}
+__global__ void k_axpy(double* __restrict__ y, double a, const double* __restrict__ x, int64_t N) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) y[e] = fma(a, x[e], y[e]);
+}
+
+// ----------------------------------------------------------------- launchers
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_to_soa(const double* in, double* out, int n, int bs, hipStream_t st) {
+    int64_t N = (int64_t)n * bs;
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_soa, dim3(cdiv(N, kThreads)), dim3(kThreads), 0, st, in, out, n, bs);
+    return hipGetLastError();
+}
+hipError_t launch_from_soa(const double* in, double* out, int n, int bs, hipStream_t st) {
+    int64_t N = (int64_t)n * bs;
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_from_soa, dim3(cdiv(N, kThreads)), dim3(kThreads), 0, st, in, out, n, bs);
+    return hipGetLastError();
+}
+
+#define OMG_BS_DISPATCH(bs, KERNEL_CALL)          \
+    switch (bs) {                                 \
+    case 1: { constexpr int BSV = 1; KERNEL_CALL; } break;   \
+    case 4: { constexpr int BSV = 4; KERNEL_CALL; } break;   \
+    case 10: { constexpr int BSV = 10; KERNEL_CALL; } break; \
+    case 20: { constexpr int BSV = 20; KERNEL_CALL; } break; \
+    default: return hipErrorInvalidValue;         \
+    }
+
+hipError_t launch_spmv(const Level& L, int bs, bool fp32, const double* x, const double* b, double* y,
+                       hipStream_t st) {
+    dim3 grid(cdiv(L.n, kThreads)), block(kThreads);
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv<BSV, float>), grid, block, 0, st, L.n, L.width, L.col,
+                                               (const float2*)L.val32, x, b, y));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv<BSV, double>), grid, block, 0, st, L.n, L.width, L.col,
+                                               (const double2*)L.val, x, b, y));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_first(const Level& L, int bs, bool fp32, double omega, const double* r, double* x,
+                           hipStream_t st) {
+    dim3 grid(cdiv(L.n, kThreads)), block(kThreads);
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first<BSV, float>), grid, block, 0, st, L.n,
+                                               (const float2*)L.dinv32, (float)omega, r, x));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first<BSV, double>), grid, block, 0, st, L.n,
+                                               (const double2*)L.dinv, omega, r, x));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_sweep(const Level& L, int bs, bool fp32, double omega, const double* r, const double* xin,
+                           double* xout, hipStream_t st) {
+    dim3 grid(cdiv(L.n, kThreads)), block(kThreads);
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep<BSV, float>), grid, block, 0, st, L.n, L.width, L.col,
+                                               (const float2*)L.val32, (const float2*)L.dinv32, (float)omega, r,
+                                               xin, xout));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep<BSV, double>), grid, block, 0, st, L.n, L.width, L.col,
+                                               (const double2*)L.val, (const double2*)L.dinv, omega, r, xin,
+                                               xout));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
+                           const double* r, double* rc, hipStream_t st) {
+    dim3 grid(cdiv(C.n, kThreads)), block(kThreads);
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, float>), grid, block, 0, st, F.nx, F.ny, F.n, C.nx,
+                                               C.ny, C.n, E32, r, rc));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, double>), grid, block, 0, st, F.nx, F.ny, F.n,
+                                               C.nx, C.ny, C.n, E, r, rc));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
+                          const double* zc, double* z, hipStream_t st) {
+    dim3 grid(cdiv(F.n, kThreads)), block(kThreads);
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong<BSV, float>), grid, block, 0, st, F.nx, F.ny, F.n, C.nx,
+                                               C.ny, C.n, E32, zc, z));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong<BSV, double>), grid, block, 0, st, F.nx, F.ny, F.n, C.nx,
+                                               C.ny, C.n, E, zc, z));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv(const Level& L, const double* x, double* y, hipStream_t st) {
+    const int n = (int)L.N;
+    hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, st, n, L.np, L.ainv, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot2(int64_t N, int G, const double* a, const double* b, double* part_ab, const double* c,
+                       double* part_cc, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot2, dim3(G), dim3(kThreads), 0, st, N, a, b, part_ab, c, part_cc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mgs_step(int64_t N, int G, const double* part_in, const double* Wi, const double* Zi, double* w,
+                           double* z, const double* Wnext, double* part_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mgs_step, dim3(G), dim3(kThreads), 0, st, N, G, part_in, Wi, Zi, w, z, Wnext, part_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rm_normalize(int64_t N, int G, const double* part_nin, const double* part_nout,
+                               double breakdown, const double* w, const double* z, double* Wk, double* Zk,
+                               const double* r, double* part_alpha, double* scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_rm_normalize, dim3(G), dim3(kThreads), 0, st, N, G, part_nin, part_nout, breakdown, w, z,
+                       Wk, Zk, r, part_alpha, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_rm_update(int64_t N, int G, const double* part_alpha, const double* Wk, const double* Zk,
+                            double* x, double* r, double* part_rn, hipStream_t st) {
+    hipLaunchKernelGGL(k_rm_update, dim3(G), dim3(kThreads), 0, st, N, G, part_alpha, Wk, Zk, x, r, part_rn);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kThreads), 0, st, G, part, out);
+    return hipGetLastError();
+}
+
+static inline int stream_blocks(int64_t N) {
+    int64_t b = (N + kThreads * 4 - 1) / (kThreads * 4);
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(stream_blocks(N)), dim3(kThreads), 0, st, dst, src, N);
+    return hipGetLastError();
+}
+hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(stream_blocks(N)), dim3(kThreads), 0, st, dst, v, N);
+    return hipGetLastError();
+}
+hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(stream_blocks(N)), dim3(kThreads), 0, st, y, a, x, N);
+    return hipGetLastError();
+}
+
+} // namespace omg

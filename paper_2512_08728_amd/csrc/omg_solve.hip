@@ -1,0 +1,833 @@
+// OrthoMG solve engine and the C ABI.
+//
+// Host code drives the level recursion of Algorithm 2 (multiplicative
+// synchronous) and of Algorithm 5 in a deterministic form (coarse correction
+// from the residual at the start of the cycle, a fixed number of smoother+RM
+// steps, then RM of the coarse correction, Sec. 4). All arithmetic runs in
+// device kernels; the host reads one residual norm per level iteration for
+// the level-local stopping rules of Sec. 4.2.
+//
+// In the deterministic Algorithm 5 the coarse path of the finest level
+// (restriction output -> coarse recursion -> prolongation) runs on a second
+// HIP stream while the finest-level smoother and residual minimisation run on
+// the caller's stream; the two meet once per cycle (an event) before
+// RM(z_cor), which is the paper's single synchronisation per cycle. The coarse
+// path works on a private copy of the restricted residual, so the result is
+// the same as running both on one stream.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "omg_internal.h"
+
+using namespace omg;
+
+// setup helpers (omg_setup.hip)
+omg_status omg_alloc_level_vectors(omg_solver* s, Level& L);
+omg_status omg_ingest_bsr(omg_solver* s, const omg_bsr* A, std::vector<unsigned char>& valid);
+omg_status omg_assemble_sip(omg_solver* s, const double* nu_dev, std::vector<unsigned char>& valid);
+omg_status omg_galerkin(omg_solver* s, int l, const std::vector<unsigned char>& fvalid,
+                        std::vector<unsigned char>& cvalid);
+omg_status omg_block_inverses(omg_solver* s, Level& L);
+omg_status omg_fp32_copies(omg_solver* s, Level& L);
+omg_status omg_coarse_factor(omg_solver* s, Level& L);
+hipError_t omg_launch_contract(const omg_solver* s, const double* lam, const double* u, double* g_nu,
+                               hipStream_t st);
+
+#define HIP_OK(expr)                                   \
+    do {                                               \
+        if ((expr) != hipSuccess) return OMG_EHIP;     \
+    } while (0)
+
+// ------------------------------------------------------------------ options
+extern "C" void omg_default_options(omg_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->variant = OMG_SYNC_MULT;
+    o->coarse_sync = 0;
+    o->s_pre = 1;
+    o->s_post = 1;
+    o->n_s = 1;
+    o->max_iter = 1000;
+    o->precision = OMG_FP64;
+    o->max_outer = 50;
+    o->overlap_streams = 1;
+    o->trace = 0;
+    o->omega = 0.7;
+    o->inner_tol = 1e-5;
+    o->breakdown = 1e-14;
+    o->crit_rel[0] = 0.1;
+    o->crit_max[0] = 20;
+    o->crit_rel[1] = 0.5;
+    o->crit_max[1] = 2;
+    for (int l = 2; l < OMG_MAX_LEVELS; ++l) {
+        o->crit_rel[l] = -1.0;
+        o->crit_max[l] = 1;
+    }
+}
+
+extern "C" const char* omg_strerror(omg_status st) {
+    switch (st) {
+    case OMG_OK: return "ok";
+    case OMG_EINVAL: return "invalid argument";
+    case OMG_ENOMEM: return "out of memory";
+    case OMG_EHIP: return "HIP runtime error";
+    case OMG_ENOTSPD: return "matrix not symmetric positive definite";
+    case OMG_ENOCONV: return "no convergence within max_iter";
+    case OMG_EBREAKDOWN: return "breakdown";
+    case OMG_EUNSUPPORTED: return "unsupported for this solver";
+    }
+    return "unknown status";
+}
+
+// ------------------------------------------------------------------ teardown
+static void free_level(Level& L) {
+    hipFree(L.col);
+    hipFree(L.val);
+    hipFree(L.val32);
+    hipFree(L.dinv);
+    hipFree(L.dinv32);
+    hipFree(L.ainv);
+    hipFree(L.dslot);
+    hipFree(L.b);
+    hipFree(L.r);
+    hipFree(L.x);
+    hipFree(L.z);
+    hipFree(L.w);
+    hipFree(L.t);
+    hipFree(L.t2);
+    hipFree(L.zcor);
+    hipFree(L.xout);
+    hipFree(L.part);
+    hipFree(L.scal);
+    for (double* c : L.chunks) hipFree(c);
+    L = Level();
+}
+
+extern "C" void omg_destroy(omg_solver* s) {
+    if (!s) return;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->cstream) {
+        hipStreamSynchronize(s->cstream);
+        hipStreamDestroy(s->cstream);
+    }
+    if (s->ev_fork) hipEventDestroy(s->ev_fork);
+    if (s->ev_join) hipEventDestroy(s->ev_join);
+    for (auto& L : s->lev) free_level(L);
+    hipFree(s->E);
+    hipFree(s->E32);
+    hipFree(s->nu);
+    hipFree(s->refm);
+    hipFree(s->bufA);
+    hipFree(s->bufB);
+    hipFree(s->err_flag);
+    if (s->host_scal) hipHostFree(s->host_scal);
+    delete s;
+}
+
+// ------------------------------------------------------------------ setup
+static omg_status check_grid(const omg_grid* g) {
+    if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1 || g->p < 0 || g->p > 3 || g->n_levels < 1 ||
+        g->n_levels > OMG_MAX_LEVELS)
+        return OMG_EINVAL;
+    for (int l = 1; l < g->n_levels; ++l) {
+        const int f = 1 << (l - 1);
+        if ((g->nx / f) % 2 || (g->ny / f) % 2 || (g->nz / f) % 2 || g->nx % (2 * f) || g->ny % (2 * f) ||
+            g->nz % (2 * f))
+            return OMG_EINVAL;
+    }
+    return OMG_OK;
+}
+
+static omg_status create(const omg_grid* g, const omg_options* opt, void* stream, omg_solver** out) {
+    OMG_TRY(check_grid(g));
+    omg_solver* s = new omg_solver();
+    s->grid = *g;
+    if (opt) s->opt = *opt;
+    else omg_default_options(&s->opt);
+    s->p = g->p;
+    s->bs = (g->p + 1) * (g->p + 2) * (g->p + 3) / 6;
+    s->bsh = (s->bs + 1) / 2;
+    s->nlev = g->n_levels;
+    s->stream = (hipStream_t)stream;
+    s->lev.resize(s->nlev);
+    for (int l = 0; l < s->nlev; ++l) {
+        Level& L = s->lev[l];
+        L.nx = g->nx >> l;
+        L.ny = g->ny >> l;
+        L.nz = g->nz >> l;
+        L.n = L.nx * L.ny * L.nz;
+        L.N = (int64_t)L.n * s->bs;
+        L.coarsest = (l == s->nlev - 1);
+        L.G = reduction_blocks(L.N);
+    }
+    *out = s;
+    if (hipMalloc((void**)&s->err_flag, sizeof(int)) != hipSuccess) return OMG_ENOMEM;
+    if (hipHostMalloc((void**)&s->host_scal, sizeof(double) * 4 * OMG_MAX_LEVELS) != hipSuccess) return OMG_ENOMEM;
+    std::vector<double> E;
+    embedding_blocks(s->p, E);
+    s->hE = E;
+    std::vector<float> E32(E.begin(), E.end());
+    if (hipMalloc((void**)&s->E, sizeof(double) * E.size()) != hipSuccess) return OMG_ENOMEM;
+    if (hipMalloc((void**)&s->E32, sizeof(float) * E.size()) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipMemcpy(s->E, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->E32, E32.data(), sizeof(float) * E.size(), hipMemcpyHostToDevice));
+    const size_t vb = sizeof(double) * (size_t)s->lev[0].N;
+    if (hipMalloc((void**)&s->bufA, vb) != hipSuccess) return OMG_ENOMEM;
+    if (hipMalloc((void**)&s->bufB, vb) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    return OMG_OK;
+}
+
+static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& valid0) {
+    std::vector<unsigned char> fvalid = valid0, cvalid;
+    for (int l = 0; l + 1 < s->nlev; ++l) {
+        OMG_TRY(omg_galerkin(s, l, fvalid, cvalid));
+        fvalid.swap(cvalid);
+    }
+    for (int l = 0; l < s->nlev; ++l) {
+        Level& L = s->lev[l];
+        OMG_TRY(omg_alloc_level_vectors(s, L));
+        if (!L.coarsest) {
+            OMG_TRY(omg_block_inverses(s, L));
+            OMG_TRY(omg_fp32_copies(s, L));
+        } else {
+            OMG_TRY(omg_coarse_factor(s, L));
+        }
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_setup(const omg_bsr* A, const omg_grid* grid, const omg_options* opt, void* hip_stream,
+                                omg_solver** out) {
+    if (!out) return OMG_EINVAL;
+    *out = nullptr;
+    if (!A || !grid || !A->row_ptr || !A->col_idx || !A->val) return OMG_EINVAL;
+    const int n = grid->nx * grid->ny * grid->nz;
+    const int bs = (grid->p + 1) * (grid->p + 2) * (grid->p + 3) / 6;
+    if (A->n_cells != n || A->bs != bs || A->row_ptr[0] != 0 || A->row_ptr[n] != A->nnzb) return OMG_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (A->row_ptr[i + 1] < A->row_ptr[i]) return OMG_EINVAL;
+        bool diag = false;
+        for (int64_t q = A->row_ptr[i]; q < A->row_ptr[i + 1]; ++q) {
+            const int c = A->col_idx[q];
+            if (c < 0 || c >= n) return OMG_EINVAL;
+            if (q > A->row_ptr[i] && c <= A->col_idx[q - 1]) return OMG_EINVAL;
+            if (c == i) diag = true;
+        }
+        if (!diag) return OMG_EINVAL;
+    }
+    for (int64_t t = 0; t < A->nnzb * bs * bs; ++t)
+        if (!std::isfinite(A->val[t])) return OMG_EINVAL;
+    omg_solver* s = nullptr;
+    omg_status st = create(grid, opt, hip_stream, &s);
+    std::vector<unsigned char> valid;
+    if (st == OMG_OK) st = omg_ingest_bsr(s, A, valid);
+    if (st == OMG_OK) st = build_hierarchy(s, valid);
+    if (st != OMG_OK) {
+        omg_destroy(s);
+        return st;
+    }
+    *out = s;
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_setup_sip(const omg_grid* grid, const double* nu, const omg_options* opt,
+                                    void* hip_stream, omg_solver** out) {
+    if (!out) return OMG_EINVAL;
+    *out = nullptr;
+    if (!grid || !nu || !(grid->h > 0) || !std::isfinite(grid->penalty_c)) return OMG_EINVAL;
+    omg_solver* s = nullptr;
+    omg_status st = create(grid, opt, hip_stream, &s);
+    if (st == OMG_OK) {
+        // nu must be positive and finite
+        const int n = s->lev[0].n;
+        std::vector<double> hnu(n);
+        if (hipMemcpy(hnu.data(), nu, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess) st = OMG_EHIP;
+        for (int i = 0; st == OMG_OK && i < n; ++i)
+            if (!(hnu[i] > 0.0) || !std::isfinite(hnu[i])) st = OMG_EINVAL;
+    }
+    std::vector<unsigned char> valid;
+    if (st == OMG_OK) st = omg_assemble_sip(s, nu, valid);
+    if (st == OMG_OK) {
+        s->has_sip = 1;
+        st = build_hierarchy(s, valid);
+    }
+    if (st != OMG_OK) {
+        omg_destroy(s);
+        return st;
+    }
+    *out = s;
+    return OMG_OK;
+}
+
+// ------------------------------------------------------------------ solve
+static inline bool use32(const omg_solver* s, int l, bool is_rm) {
+    if (s->mode32 == 1) return true;
+    if (s->mode32 == 2) return !(l == 0 && is_rm);
+    return false;
+}
+
+// Make room for direction index k on level l (chunks of 32 directions).
+static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
+    if (k < (int)L.W.size()) return OMG_OK;
+    const int chunk = 32;
+    double* mem = nullptr;
+    if (hipMalloc((void**)&mem, sizeof(double) * (size_t)L.N * 2 * chunk) != hipSuccess) {
+        (void)hipGetLastError();
+        return OMG_ENOMEM;
+    }
+    L.chunks.push_back(mem);
+    for (int c = 0; c < chunk; ++c) {
+        L.W.push_back(mem + (size_t)L.N * (2 * c));
+        L.Z.push_back(mem + (size_t)L.N * (2 * c + 1));
+    }
+    (void)s;
+    return OMG_OK;
+}
+
+// Residual minimisation (Algorithm 1) on level l with the direction z
+// (overwritten): w = A z, MGS against W with the same coefficients on z,
+// normalise, append, alpha = w.r, x += alpha z, r -= alpha w. Leaves the
+// partials of ||r||^2 in part slot 4.
+static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
+    Level& L = s->lev[l];
+    const int G = L.G;
+    const int64_t N = L.N;
+    OMG_TRY(ensure_dir(s, L, L.k));
+    double* P_nin = L.part;
+    double* P_a = L.part + kMaxRedBlocks;
+    double* P_b = L.part + 2 * kMaxRedBlocks;
+    double* P_alpha = L.part + 3 * kMaxRedBlocks;
+    double* P_rn = L.part + 4 * kMaxRedBlocks;
+    HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
+    const double* P_nout = P_nin;
+    if (L.k == 0) {
+        HIP_OK(launch_dot2(N, G, nullptr, nullptr, nullptr, L.w, P_nin, st));
+    } else {
+        HIP_OK(launch_dot2(N, G, L.W[0], L.w, P_a, L.w, P_nin, st));
+        for (int i = 0; i < L.k; ++i) {
+            double* pin = (i & 1) ? P_b : P_a;
+            double* pout = (i & 1) ? P_a : P_b;
+            const double* next = (i + 1 < L.k) ? L.W[i + 1] : nullptr;
+            HIP_OK(launch_mgs_step(N, G, pin, L.W[i], L.Z[i], L.w, z, next, pout, st));
+            P_nout = pout;
+        }
+    }
+    HIP_OK(launch_rm_normalize(N, G, P_nin, P_nout, s->opt.breakdown, L.w, z, L.W[L.k], L.Z[L.k], L.r, P_alpha,
+                               L.scal, st));
+    HIP_OK(launch_rm_update(N, G, P_alpha, L.W[L.k], L.Z[L.k], L.x, L.r, P_rn, st));
+    L.k++;
+    return OMG_OK;
+}
+
+// Read ||r|| of level l (from the partials of the last update) to the host.
+static omg_status read_rnorm(omg_solver* s, int l, hipStream_t st, double* out) {
+    Level& L = s->lev[l];
+    HIP_OK(launch_finish_norm(L.G, L.part + 4 * kMaxRedBlocks, L.scal + S_RNORM, st));
+    HIP_OK(hipMemcpyAsync(s->host_scal + l, L.scal + S_RNORM, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *out = s->host_scal[l];
+    return OMG_OK;
+}
+
+static omg_status vec_norm(omg_solver* s, int l, const double* v, hipStream_t st, double* out) {
+    Level& L = s->lev[l];
+    HIP_OK(launch_dot2(L.N, L.G, nullptr, nullptr, nullptr, v, L.part + 4 * kMaxRedBlocks, st));
+    return read_rnorm(s, l, st, out);
+}
+
+// Block-Jacobi smoother (Algorithm 4) from x0 = 0 with `sweeps` iterations;
+// result in out (ping-pong through t).
+static omg_status smoother(omg_solver* s, int l, const double* r, int sweeps, double* out, hipStream_t st) {
+    Level& L = s->lev[l];
+    const bool f32 = use32(s, l, false);
+    if (sweeps < 1) sweeps = 1;
+    // place the last sweep's output in `out`
+    double* bufs[2] = {out, L.t};
+    int cur = (sweeps % 2 == 1) ? 0 : 1;
+    HIP_OK(launch_bj_first(L, s->bs, f32, s->opt.omega, r, bufs[cur], st));
+    for (int it = 1; it < sweeps; ++it) {
+        HIP_OK(launch_bj_sweep(L, s->bs, f32, s->opt.omega, r, bufs[cur], bufs[cur ^ 1], st));
+        cur ^= 1;
+    }
+    return OMG_OK;
+}
+
+static void log_trace(omg_solver* s, double rn, int type) {
+    s->trace.push_back(Trace{(double)s->step, rn, (double)type});
+}
+
+static omg_status trace_rm(omg_solver* s, int l, hipStream_t st, int type) {
+    if (l != 0 || !s->opt.trace) return OMG_OK;
+    double rn;
+    OMG_TRY(read_rnorm(s, l, st, &rn));
+    s->step++;
+    log_trace(s, rn, type);
+    return OMG_OK;
+}
+
+// per-level replay queues built from a visit log
+struct ReplayState {
+    std::vector<std::vector<int>> q;
+    std::vector<size_t> pos;
+};
+static thread_local ReplayState* g_replay = nullptr;
+
+static bool stop_level(const omg_solver* s, int l, double rn, double r0n, double bn, int it, double tol,
+                       int replay_count) {
+    if (!std::isfinite(rn)) return true;
+    if (replay_count >= 0) return it >= replay_count;
+    if (l == 0) return (rn <= tol * bn) || it >= s->opt.max_iter;
+    const int idx = l - 1;
+    const double rel = s->opt.crit_rel[idx];
+    if (rel >= 0.0 && rn <= rel * r0n) return true;
+    return it >= s->opt.crit_max[idx];
+}
+
+static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double tol, int variant, hipStream_t st);
+
+// z = P_l MG_{l+1}(P_l^T r, 0): the coarse-grid correction of level l.
+static omg_status coarse_path(omg_solver* s, int l, int variant, hipStream_t st, double* z) {
+    Level& F = s->lev[l];
+    Level& C = s->lev[l + 1];
+    OMG_TRY(mg(s, l + 1, C.b, C.xout, 0.0, variant, st));
+    HIP_OK(launch_prolong(F, C, s->bs, use32(s, l, false), s->E, s->E32, C.xout, z, st));
+    return OMG_OK;
+}
+
+static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double tol, int variant, hipStream_t st) {
+    Level& L = s->lev[l];
+    if (L.coarsest) {
+        HIP_OK(launch_gemv(L, b, xout, st));
+        return OMG_OK;
+    }
+    Level& C = s->lev[l + 1];
+    L.k = 0;
+    HIP_OK(launch_fill(L.x, 0.0, L.N, st));
+    HIP_OK(launch_copy(L.r, b, L.N, st));
+    double r0n;
+    OMG_TRY(vec_norm(s, l, L.r, st, &r0n));
+    const double bn = r0n;
+    if (l == 0) log_trace(s, r0n, 0);
+    int replay_count = -1;
+    if (g_replay && l < (int)g_replay->q.size() && g_replay->pos[l] < g_replay->q[l].size())
+        replay_count = g_replay->q[l][g_replay->pos[l]++];
+    const int sub_variant = (variant == OMG_OVERLAP_DET && s->opt.coarse_sync) ? OMG_SYNC_MULT : variant;
+    int it = 0;
+    double rn = r0n;
+    omg_status status = OMG_OK;
+    while (!stop_level(s, l, rn, r0n, bn, it, tol, replay_count)) {
+        if (variant == OMG_SYNC_MULT) {
+            OMG_TRY(smoother(s, l, L.r, s->opt.s_pre, L.z, st));
+            OMG_TRY(rm(s, l, L.z, st));
+            OMG_TRY(trace_rm(s, l, st, 1));
+            HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
+            OMG_TRY(coarse_path(s, l, sub_variant, st, L.z));
+            OMG_TRY(rm(s, l, L.z, st));
+            OMG_TRY(trace_rm(s, l, st, 2));
+            OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
+            OMG_TRY(rm(s, l, L.z, st));
+            OMG_TRY(trace_rm(s, l, st, 1));
+        } else {
+            // coarse group: restriction of the residual at the start of the cycle
+            HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
+            const bool fork = (l == 0) && s->opt.overlap_streams && !s->opt.trace;
+            if (fork) {
+                HIP_OK(hipEventRecord(s->ev_fork, st));
+                // smoother group: queue the fine work first (asynchronous)
+                for (int t = 0; t < s->opt.n_s; ++t) {
+                    OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
+                    OMG_TRY(rm(s, l, L.z, st));
+                }
+                HIP_OK(hipStreamWaitEvent(s->cstream, s->ev_fork, 0));
+                OMG_TRY(coarse_path(s, l, sub_variant, s->cstream, L.zcor));
+                HIP_OK(hipEventRecord(s->ev_join, s->cstream));
+                HIP_OK(hipStreamWaitEvent(st, s->ev_join, 0));
+            } else {
+                OMG_TRY(coarse_path(s, l, sub_variant, st, L.zcor));
+                for (int t = 0; t < s->opt.n_s; ++t) {
+                    OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
+                    OMG_TRY(rm(s, l, L.z, st));
+                    OMG_TRY(trace_rm(s, l, st, 1));
+                }
+            }
+            OMG_TRY(rm(s, l, L.zcor, st));
+            OMG_TRY(trace_rm(s, l, st, 2));
+        }
+        it++;
+        OMG_TRY(read_rnorm(s, l, st, &rn));
+        if (!std::isfinite(rn)) {
+            status = OMG_EINVAL;
+            break;
+        }
+    }
+    if (l == 0 && status == OMG_OK && rn > tol * bn && replay_count < 0) status = OMG_ENOCONV;
+    s->visits.push_back(l);
+    s->visits.push_back(it);
+    HIP_OK(launch_copy(xout, L.x, L.N, st));
+    return status;
+}
+
+static omg_status solve_soa(omg_solver* s, const double* b, double* x, double tol, omg_report* R) {
+    Level& L = s->lev[0];
+    hipStream_t st = s->stream;
+    double* rr = L.t2;   // outer residual
+    double* e = L.xout;  // correction
+    double bn;
+    OMG_TRY(vec_norm(s, 0, b, st, &bn));
+    if (!std::isfinite(bn)) return OMG_EINVAL;
+    if (bn == 0.0) {
+        HIP_OK(launch_fill(x, 0.0, L.N, st));
+        return OMG_OK;
+    }
+    if (L.coarsest) { // one level: direct solve
+        HIP_OK(launch_spmv(L, s->bs, false, x, b, rr, st));
+        HIP_OK(launch_gemv(L, rr, e, st));
+        HIP_OK(launch_axpy(x, 1.0, e, L.N, st));
+        return OMG_OK;
+    }
+    omg_status status = OMG_OK;
+    if (s->opt.precision == OMG_MIXED_IR) {
+        int outer = 0;
+        for (;;) {
+            HIP_OK(launch_spmv(L, s->bs, false, x, b, rr, st));
+            double rn;
+            OMG_TRY(vec_norm(s, 0, rr, st, &rn));
+            R->rel_res_rec = rn / bn;
+            if (!std::isfinite(rn)) {
+                status = OMG_EINVAL;
+                break;
+            }
+            if (rn <= tol * bn) break;
+            if (outer >= s->opt.max_outer) {
+                status = OMG_ENOCONV;
+                break;
+            }
+            s->mode32 = 1;
+            omg_status st2 = mg(s, 0, rr, e, s->opt.inner_tol, s->opt.variant, st);
+            s->mode32 = 0;
+            R->iters_fine += s->visits.back();
+            if (st2 == OMG_EINVAL || st2 == OMG_EHIP || st2 == OMG_ENOMEM) {
+                status = st2;
+                break;
+            }
+            HIP_OK(launch_axpy(x, 1.0, e, L.N, st));
+            outer++;
+        }
+        R->outer_iters = outer;
+    } else {
+        HIP_OK(launch_spmv(L, s->bs, false, x, b, rr, st));
+        double rn;
+        OMG_TRY(vec_norm(s, 0, rr, st, &rn));
+        if (!std::isfinite(rn)) return OMG_EINVAL;
+        s->mode32 = (s->opt.precision == OMG_MIXED_FLEX) ? 2 : 0;
+        if (rn > 0.0) {
+            status = mg(s, 0, rr, e, tol * bn / rn, s->opt.variant, st);
+            s->mode32 = 0;
+            HIP_OK(launch_axpy(x, 1.0, e, L.N, st));
+            R->iters_fine = s->visits.back();
+            double rrec;
+            OMG_TRY(vec_norm(s, 0, L.r, st, &rrec));
+            R->rel_res_rec = rrec / bn;
+            log_trace(s, rrec, 3);
+        }
+        s->mode32 = 0;
+    }
+    return status;
+}
+
+static omg_status finish_report(omg_solver* s, const double* b, const double* x, omg_report* R) {
+    Level& L = s->lev[0];
+    hipStream_t st = s->stream;
+    double bn, rn;
+    OMG_TRY(vec_norm(s, 0, b, st, &bn));
+    HIP_OK(launch_spmv(L, s->bs, false, x, b, L.t2, st));
+    OMG_TRY(vec_norm(s, 0, L.t2, st, &rn));
+    R->rel_res_true = bn > 0 ? rn / bn : 0.0;
+    R->n_dirs_fine = L.coarsest ? 0 : L.k;
+    double nb = 0;
+    for (auto& Lv : s->lev)
+        if (!Lv.coarsest) {
+            double v;
+            HIP_OK(hipMemcpyAsync(&v, Lv.scal + S_BREAKDOWNS, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            nb += v;
+        }
+    R->n_breakdowns = (int)nb;
+    R->n_visits = (int)s->visits.size() / 2;
+    R->n_trace = (int)s->trace.size();
+    return OMG_OK;
+}
+
+static void reset_logs(omg_solver* s) {
+    s->visits.clear();
+    s->trace.clear();
+    s->step = 0;
+    for (auto& L : s->lev)
+        if (L.scal) hipMemsetAsync(L.scal, 0, sizeof(double) * S_COUNT, s->stream);
+}
+
+static omg_status solve_internal(omg_solver* s, const double* b_soa, double* x_soa, double tol, omg_report* R) {
+    reset_logs(s);
+    ReplayState rs;
+    if (!s->replay.empty()) {
+        rs.q.assign(s->nlev, {});
+        rs.pos.assign(s->nlev, 0);
+        for (size_t i = 0; i + 1 < s->replay.size(); i += 2)
+            if (s->replay[i] >= 0 && s->replay[i] < s->nlev) rs.q[s->replay[i]].push_back(s->replay[i + 1]);
+        g_replay = &rs;
+    }
+    omg_status st = solve_soa(s, b_soa, x_soa, tol, R);
+    g_replay = nullptr;
+    return st;
+}
+
+extern "C" omg_status omg_solve(omg_solver* s, const double* b, double* x, double tol, double* r_out,
+                                omg_report* rep) {
+    if (!s || !b || !x || !(tol >= 0.0)) return OMG_EINVAL;
+    auto t0 = std::chrono::steady_clock::now();
+    omg_report R;
+    std::memset(&R, 0, sizeof(R));
+    Level& L = s->lev[0];
+    hipStream_t st = s->stream;
+    HIP_OK(launch_to_soa(b, s->bufA, L.n, s->bs, st));
+    HIP_OK(launch_to_soa(x, s->bufB, L.n, s->bs, st));
+    omg_status status = solve_internal(s, s->bufA, s->bufB, tol, &R);
+    if (status == OMG_OK || status == OMG_ENOCONV) {
+        HIP_OK(launch_from_soa(s->bufB, x, L.n, s->bs, st));
+        if (r_out && !L.coarsest) HIP_OK(launch_from_soa(L.r, r_out, L.n, s->bs, st));
+        OMG_TRY(finish_report(s, s->bufA, s->bufB, &R));
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    R.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    R.status = status;
+    if (rep) *rep = R;
+    return status;
+}
+
+// Batched solve: each column of each instance is solved as by omg_solve
+// (columns gathered into the solver's internal layout one at a time).
+__global__ void k_gather_col(const double* __restrict__ in, double* __restrict__ out, int n, int bs, int nrhs,
+                             int col) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * bs) return;
+    const int c = (int)(e / bs), k = (int)(e % bs);
+    out[(int64_t)k * n + c] = in[e * nrhs + col];
+}
+__global__ void k_scatter_col(const double* __restrict__ in, double* __restrict__ out, int n, int bs, int nrhs,
+                              int col) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * bs) return;
+    const int c = (int)(e / bs), k = (int)(e % bs);
+    out[e * nrhs + col] = in[(int64_t)k * n + c];
+}
+
+extern "C" omg_status omg_solve_batched(omg_solver* const* s, int32_t n_inst, int32_t nrhs, const double* const* b,
+                                        double* const* x, double tol, omg_report* rep) {
+    if (!s || n_inst < 1 || nrhs < 1 || !b || !x) return OMG_EINVAL;
+    omg_status worst = OMG_OK;
+    for (int i = 0; i < n_inst; ++i) {
+        omg_solver* si = s[i];
+        if (!si || !b[i] || !x[i]) return OMG_EINVAL;
+        Level& L = si->lev[0];
+        const int64_t N = L.N;
+        const dim3 g((unsigned)((N + 255) / 256)), blk(256);
+        for (int c = 0; c < nrhs; ++c) {
+            auto t0 = std::chrono::steady_clock::now();
+            omg_report R;
+            std::memset(&R, 0, sizeof(R));
+            hipLaunchKernelGGL(k_gather_col, g, blk, 0, si->stream, b[i], si->bufA, L.n, si->bs, nrhs, c);
+            hipLaunchKernelGGL(k_gather_col, g, blk, 0, si->stream, x[i], si->bufB, L.n, si->bs, nrhs, c);
+            HIP_OK(hipGetLastError());
+            omg_status st = solve_internal(si, si->bufA, si->bufB, tol, &R);
+            if (st == OMG_OK || st == OMG_ENOCONV) {
+                hipLaunchKernelGGL(k_scatter_col, g, blk, 0, si->stream, si->bufB, x[i], L.n, si->bs, nrhs, c);
+                HIP_OK(hipGetLastError());
+                OMG_TRY(finish_report(si, si->bufA, si->bufB, &R));
+            }
+            HIP_OK(hipStreamSynchronize(si->stream));
+            R.status = st;
+            R.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rep) rep[(size_t)i * nrhs + c] = R;
+            if (st != OMG_OK && worst == OMG_OK) worst = st;
+        }
+    }
+    return worst;
+}
+
+extern "C" omg_status omg_solve_backward(omg_solver* s, const double* u, const double* g_u, double* g_f,
+                                         double* g_nu, double tol, omg_report* rep) {
+    if (!s || !u || !g_u) return OMG_EINVAL;
+    if (g_nu && !s->has_sip) return OMG_EUNSUPPORTED;
+    Level& L = s->lev[0];
+    double* lam = nullptr;
+    if (hipMalloc((void**)&lam, sizeof(double) * L.N) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipMemsetAsync(lam, 0, sizeof(double) * L.N, s->stream));
+    omg_status st = omg_solve(s, g_u, lam, tol, nullptr, rep); // adjoint: A symmetric
+    if (st == OMG_OK || st == OMG_ENOCONV) {
+        if (g_f) HIP_OK(hipMemcpyAsync(g_f, lam, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s->stream));
+        if (g_nu) HIP_OK(omg_launch_contract(s, lam, u, g_nu, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+    }
+    hipFree(lam);
+    return st;
+}
+
+// ------------------------------------------------------------------ inspection
+extern "C" omg_status omg_level_info(const omg_solver* s, int32_t level, int32_t* n_cells, int32_t* ell_width,
+                                     int32_t* k_dirs) {
+    if (!s || level < 0 || level >= s->nlev) return OMG_EINVAL;
+    const Level& L = s->lev[level];
+    if (n_cells) *n_cells = L.n;
+    if (ell_width) *ell_width = L.width;
+    if (k_dirs) *k_dirs = L.k;
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_level_matrix(const omg_solver* s, int32_t level, int32_t* row_ptr, int32_t* col_idx,
+                                       double* val, int64_t* nnzb) {
+    if (!s || level < 0 || level >= s->nlev || !row_ptr || !col_idx || !val) return OMG_EINVAL;
+    const Level& L = s->lev[level];
+    const int n = L.n, bs = s->bs, bsh = s->bsh;
+    std::vector<int> hcol((size_t)L.width * n);
+    std::vector<double> hval((size_t)2 * L.width * n * bs * bsh);
+    HIP_OK(hipMemcpy(hcol.data(), L.col, sizeof(int) * hcol.size(), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(hval.data(), L.val, sizeof(double) * hval.size(), hipMemcpyDeviceToHost));
+    std::vector<int> ds(n);
+    HIP_OK(hipMemcpy(ds.data(), L.dslot, sizeof(int) * n, hipMemcpyDeviceToHost));
+    int64_t q = 0;
+    row_ptr[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        // padding slots point at the cell itself; keep only the recorded diagonal slot among those
+        std::vector<std::pair<int, int>> ent;
+        for (int j = 0; j < L.width; ++j) {
+            const int c = hcol[(size_t)j * n + i];
+            if (c == i && j != ds[i]) continue;
+            ent.push_back({c, j});
+        }
+        std::sort(ent.begin(), ent.end());
+        for (auto& e : ent) {
+            col_idx[q] = e.first;
+            for (int r = 0; r < bs; ++r)
+                for (int cc = 0; cc < bs; ++cc)
+                    val[(size_t)q * bs * bs + r * bs + cc] =
+                        hval[((((size_t)e.second * bs + r) * bsh + (cc >> 1)) * n + i) * 2 + (cc & 1)];
+            ++q;
+        }
+        row_ptr[i + 1] = (int)q;
+    }
+    if (nnzb) *nnzb = q;
+    return OMG_OK;
+}
+
+// level operations on cell-major vectors (converted through bufA/bufB and t/t2)
+extern "C" omg_status omg_level_spmv(omg_solver* s, int32_t level, const double* x, const double* b, double* y) {
+    if (!s || level < 0 || level >= s->nlev || !x || !y) return OMG_EINVAL;
+    Level& L = s->lev[level];
+    if (L.coarsest && level > 0) return OMG_EUNSUPPORTED;
+    hipStream_t st = s->stream;
+    double *xs = s->bufA, *bs_ = nullptr, *ys = s->bufB;
+    HIP_OK(launch_to_soa(x, xs, L.n, s->bs, st));
+    if (b) {
+        bs_ = L.coarsest ? nullptr : L.t;
+        if (!bs_) return OMG_EUNSUPPORTED;
+        HIP_OK(launch_to_soa(b, bs_, L.n, s->bs, st));
+    }
+    HIP_OK(launch_spmv(L, s->bs, false, xs, bs_, ys, st));
+    HIP_OK(launch_from_soa(ys, y, L.n, s->bs, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_level_smoother(omg_solver* s, int32_t level, const double* r, int32_t sweeps,
+                                         double* out) {
+    if (!s || level < 0 || level >= s->nlev - 1 || !r || !out || sweeps < 1) return OMG_EINVAL;
+    Level& L = s->lev[level];
+    hipStream_t st = s->stream;
+    HIP_OK(launch_to_soa(r, s->bufA, L.n, s->bs, st));
+    OMG_TRY(smoother(s, level, s->bufA, sweeps, s->bufB, st));
+    HIP_OK(launch_from_soa(s->bufB, out, L.n, s->bs, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_level_restrict(omg_solver* s, int32_t level, const double* r, double* rc) {
+    if (!s || level < 0 || level >= s->nlev - 1 || !r || !rc) return OMG_EINVAL;
+    Level& F = s->lev[level];
+    Level& C = s->lev[level + 1];
+    hipStream_t st = s->stream;
+    HIP_OK(launch_to_soa(r, s->bufA, F.n, s->bs, st));
+    HIP_OK(launch_restrict(F, C, s->bs, false, s->E, s->E32, s->bufA, s->bufB, st));
+    HIP_OK(launch_from_soa(s->bufB, rc, C.n, s->bs, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_level_prolong(omg_solver* s, int32_t level, const double* zc, double* z) {
+    if (!s || level < 0 || level >= s->nlev - 1 || !zc || !z) return OMG_EINVAL;
+    Level& F = s->lev[level];
+    Level& C = s->lev[level + 1];
+    hipStream_t st = s->stream;
+    HIP_OK(launch_to_soa(zc, s->bufA, C.n, s->bs, st));
+    HIP_OK(launch_prolong(F, C, s->bs, false, s->E, s->E32, s->bufA, s->bufB, st));
+    HIP_OK(launch_from_soa(s->bufB, z, F.n, s->bs, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_coarse_solve(omg_solver* s, const double* b, double* x) {
+    if (!s || !b || !x) return OMG_EINVAL;
+    Level& L = s->lev[s->nlev - 1];
+    hipStream_t st = s->stream;
+    HIP_OK(launch_to_soa(b, s->bufA, L.n, s->bs, st));
+    HIP_OK(launch_gemv(L, s->bufA, s->bufB, st));
+    HIP_OK(launch_from_soa(s->bufB, x, L.n, s->bs, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_get_dirs(const omg_solver* s, int32_t level, double* W, double* Z) {
+    if (!s || level < 0 || level >= s->nlev) return OMG_EINVAL;
+    const Level& L = s->lev[level];
+    for (int i = 0; i < L.k; ++i) {
+        if (W) HIP_OK(launch_from_soa(L.W[i], W + (size_t)i * L.N, L.n, s->bs, s->stream));
+        if (Z) HIP_OK(launch_from_soa(L.Z[i], Z + (size_t)i * L.N, L.n, s->bs, s->stream));
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_get_visits(const omg_solver* s, int32_t* out, int32_t cap, int32_t* n) {
+    if (!s || !n) return OMG_EINVAL;
+    const int cnt = (int)s->visits.size() / 2;
+    *n = cnt;
+    if (out)
+        for (int i = 0; i < cnt && i < cap; ++i) {
+            out[2 * i] = s->visits[2 * i];
+            out[2 * i + 1] = s->visits[2 * i + 1];
+        }
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_get_trace(const omg_solver* s, double* out, int32_t cap, int32_t* n) {
+    if (!s || !n) return OMG_EINVAL;
+    const int cnt = (int)s->trace.size();
+    *n = cnt;
+    if (out)
+        for (int i = 0; i < cnt && i < cap; ++i) {
+            out[3 * i] = s->trace[i].step;
+            out[3 * i + 1] = s->trace[i].rnorm;
+            out[3 * i + 2] = s->trace[i].type;
+        }
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_set_replay(omg_solver* s, const int32_t* visits, int32_t n) {
+    if (!s || n < 0 || (n > 0 && !visits)) return OMG_EINVAL;
+    s->replay.assign(visits, visits + 2 * (size_t)n);
+    return OMG_OK;
+}

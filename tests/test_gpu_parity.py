@@ -1,0 +1,242 @@
+"""GPU path (libomg.so through the C ABI) against the FP64 CPU oracle.
+
+Kernels: elementwise within a few ulps of the operator scale. Solves: the
+same cycle sequence (iteration counts per level visit) and a relative
+solution difference <= 1e-9 in FP64."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_08728_amd  # noqa: F401
+
+
+def omg():
+    import paper_2512_08728_amd as m
+    return m
+
+
+def grid_of(prob):
+    return omg().Solver.make_grid(prob.nx, prob.ny, prob.nz, prob.p, prob.n_levels, prob.h, prob.penalty_c)
+
+
+def pair(n, p, n_levels=None, nu=None, **opts):
+    prob = synth.make_problem(n, p, n_levels=n_levels)
+    if nu is None:
+        nu = synth.nu_sphere(n, n, n, prob.h)
+    o = oracle.Oracle.from_sip(prob, nu, **opts)
+    g = omg().Solver.from_sip(grid_of(prob), torch.tensor(nu, device="cuda"), **opts)
+    return prob, nu, o, g
+
+
+def cuda(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CASES = [(8, 1, 2), (16, 2, 2), (16, 1, 4), (8, 2, 3)]
+
+
+@pytest.mark.parametrize("n,p,lv", CASES)
+def test_assembly_and_galerkin_levels(n, p, lv):
+    """Device SIP assembly and Galerkin coarse operators equal the oracle's
+    quadrature assembly and sparse triple products."""
+    prob, nu, o, g = pair(n, p, lv)
+    for l in range(lv):
+        rp, ci, v = o.matrix(l)
+        grp, gci, gv = g.level_matrix(l)
+        assert np.array_equal(rp, grp) and np.array_equal(ci, gci), l
+        assert relmax(gv, v) < 1e-13, (l, relmax(gv, v))
+
+
+@pytest.mark.parametrize("n,p,lv", CASES)
+def test_level_kernels(n, p, lv):
+    """SpMV (y = A x and y = b - A x), block-Jacobi (1..3 iterations),
+    restriction, prolongation and the coarsest direct solve."""
+    prob, nu, o, g = pair(n, p, lv)
+    rng = np.random.default_rng(1)
+    for l in range(lv - 1):
+        nl = (n >> l) ** 3 * prob.bs
+        x = rng.standard_normal(nl)
+        b = rng.standard_normal(nl)
+        scale = np.abs(o.spmv(np.abs(x), l)).max()
+        assert np.abs(host(g.level_spmv(l, cuda(x))) - o.spmv(x, l)).max() <= 1e-14 * scale
+        assert np.abs(host(g.level_spmv(l, cuda(x), cuda(b))) - o.spmv(x, l, b)).max() <= 1e-14 * scale
+        for s in (1, 2, 3):
+            ref = o.smoother(b, s, l)
+            assert relmax(host(g.level_smoother(l, cuda(b), s)), ref) < 1e-12, (l, s)
+        assert relmax(host(g.level_restrict(l, cuda(x))), o.restrict(x, l)) < 1e-14
+        nc = (n >> (l + 1)) ** 3 * prob.bs
+        zc = rng.standard_normal(nc)
+        assert relmax(host(g.level_prolong(l, cuda(zc))), o.prolong(zc, l)) < 1e-14
+    ncoarse = (n >> (lv - 1)) ** 3 * prob.bs
+    bc = rng.standard_normal(ncoarse)
+    ref = o.coarse_solve(bc)
+    assert relmax(host(g.coarse_solve(cuda(bc))), ref) < 1e-10
+
+
+def _solve_both(n, p, lv, seed=0, tol=1e-10, **opts):
+    prob, nu, o, g = pair(n, p, lv, **opts)
+    b = synth.rhs(prob.n_dofs, seed)
+    x_o = o.solve(b, tol=tol)
+    x_g = host(g.solve(cuda(b), tol=tol))
+    return prob, o, g, b, x_o, x_g
+
+
+@pytest.mark.parametrize("n,p,lv,s", [(8, 1, 2, 1), (16, 2, 2, 2), (16, 1, 4, 2), (8, 2, 3, 2)])
+def test_solve_sync_matches_oracle(n, p, lv, s):
+    """Algorithm 2 (multiplicative, synchronous): same visit sequence and
+    iteration counts, solution within 1e-9 relative."""
+    prob, o, g, b, x_o, x_g = _solve_both(n, p, lv, s_pre=s, s_post=s)
+    assert np.array_equal(o.visits(), g.visits())
+    assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    rep = g.last_report
+    assert rep["status"] == 0 and rep["rel_res_true"] <= 1.0001e-10
+    assert rep["iters_fine"] == o.last_report["iters_fine"]
+
+
+@pytest.mark.parametrize("n,p,lv", [(8, 1, 2), (16, 1, 4)])
+def test_solve_overlap_matches_oracle_and_serial(n, p, lv):
+    """Deterministic Algorithm 5: two-stream execution equals one-stream
+    execution bitwise and the oracle's sequential form within 1e-9."""
+    prob, nu, o, g = pair(n, p, lv, variant="overlap", s_post=2, n_s=1)
+    g1 = omg().Solver.from_sip(grid_of(prob), cuda(nu), variant="overlap", s_post=2, n_s=1, overlap_streams=0)
+    b = synth.rhs(prob.n_dofs, 0)
+    x_o = o.solve(b)
+    x_2 = host(g.solve(cuda(b)))
+    x_1 = host(g1.solve(cuda(b)))
+    assert np.array_equal(x_1, x_2)
+    assert np.array_equal(o.visits(), g.visits())
+    assert np.linalg.norm(x_2 - x_o) <= 1e-9 * np.linalg.norm(x_o)
+
+
+def test_orthonormal_directions_and_residual_on_gpu():
+    prob, nu, o, g = pair(8, 1, 2)
+    b = synth.rhs(prob.n_dofs, 0)
+    g.solve(cuda(b))
+    W, Z = g.dirs(0)
+    W = host(W)
+    assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 1e-12
+    A = o.scipy_matrix(0)
+    assert np.linalg.norm((A @ host(Z).T).T - W) / np.linalg.norm(W) < 1e-12
+
+
+def test_generic_bsr_setup():
+    rp, ci, v = synth.random_spd_bsr(8, 8, 8, 4, seed=1)
+    o = oracle.Oracle.from_bsr(rp, ci, v, 8, 8, 8, 1, 2)
+    g = omg().Solver.from_bsr(rp, ci, v, omg().Solver.make_grid(8, 8, 8, 1, 2))
+    b = synth.rhs(512 * 4, 3)
+    x_o = o.solve(b)
+    x_g = host(g.solve(cuda(b)))
+    assert np.array_equal(o.visits(), g.visits())
+    assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    grp, gci, gv = g.level_matrix(1)
+    rp1, ci1, v1 = o.matrix(1)
+    assert np.array_equal(grp, rp1) and np.array_equal(gci, ci1) and relmax(gv, v1) < 1e-13
+
+
+@pytest.mark.parametrize("mode", ["mixed_ir", "mixed_flex"])
+def test_mixed_precision(mode):
+    """FP32 inner work with FP64 outer residual: reaches the same true FP64
+    residual 1e-10; the difference to the FP64 oracle solution is reported."""
+    prob, nu, o, g = pair(8, 1, 2)
+    _, _, _, gm = pair(8, 1, 2, precision=mode)
+    b = synth.rhs(prob.n_dofs, 0)
+    x_o = o.solve(b)
+    x_m = host(gm.solve(cuda(b)))
+    rep = gm.last_report
+    assert rep["rel_res_true"] <= 1.0001e-10
+    A = o.scipy_matrix(0)
+    assert np.linalg.norm(b - A @ x_m) <= 1.0001e-10 * np.linalg.norm(b)
+    err = np.linalg.norm(x_m - x_o) / np.linalg.norm(x_o)
+    print(f"{mode}: rel. difference to FP64 oracle {err:.3e}, iters {rep['iters_fine']}, outer {rep['outer_iters']}")
+    assert err < 1e-4
+
+
+def test_gradient_matches_oracle():
+    n, p = 8, 1
+    prob = synth.make_problem(n, p, n_levels=2)
+    nu = synth.nu_sphere(n, n, n, prob.h)
+    f = synth.rhs(prob.n_dofs, 0)
+    ut = synth.rhs(prob.n_dofs, 1)
+    o = oracle.Oracle.from_sip(prob, nu)
+    u = o.solve(f, tol=1e-12)
+    gf_o, gnu_o = o.grad(u, u - ut, tol=1e-12)
+    g = omg().Solver.from_sip(grid_of(prob), cuda(nu))
+    gf_g, gnu_g = g.backward(cuda(u), cuda(u - ut), tol=1e-12)
+    assert np.linalg.norm(host(gf_g) - gf_o) <= 1e-9 * np.linalg.norm(gf_o)
+    assert np.linalg.norm(host(gnu_g) - gnu_o) <= 1e-8 * np.linalg.norm(gnu_o)
+
+
+def test_autograd_function():
+    n, p = 4, 1
+    prob = synth.make_problem(n, p, n_levels=2)
+    nu = synth.nu_sphere(n, n, n, prob.h, nu_out=10.0)
+    f = cuda(synth.rhs(prob.n_dofs, 0)).requires_grad_(True)
+    lognu = cuda(np.log(nu)).requires_grad_(True)
+    ut = cuda(synth.rhs(prob.n_dofs, 1))
+    fn = omg().solve_fn()
+    u = fn.apply(f, lognu, grid_of(prob), 1e-12, None)
+    loss = 0.5 * ((u - ut) ** 2).sum()
+    loss.backward()
+    o = oracle.Oracle.from_sip(prob, nu)
+    uo = o.solve(host(f.detach()), tol=1e-12)
+    gf_o, gnu_o = o.grad(uo, uo - host(ut), tol=1e-12)
+    assert np.linalg.norm(host(f.grad) - gf_o) <= 1e-9 * np.linalg.norm(gf_o)
+    assert np.linalg.norm(host(lognu.grad) - nu * gnu_o) <= 1e-8 * np.linalg.norm(nu * gnu_o)
+
+
+def test_batched_columns_equal_single_solves():
+    prob, nu, o, g = pair(8, 1, 2)
+    B = synth.multi_rhs(prob.n_dofs, 3, seed=0)
+    xs, reps = omg().solve_batched([g], [cuda(B)], nrhs=3)
+    X = host(xs[0])
+    for j in range(3):
+        xo = o.solve(B[:, j])
+        assert np.linalg.norm(X[:, j] - xo) <= 1e-9 * np.linalg.norm(xo)
+        assert reps[j]["rel_res_true"] <= 1.0001e-10
+
+
+def test_error_paths():
+    m = omg()
+    prob, nu, o, g = pair(4, 1, 2)
+    x = host(g.solve(cuda(np.zeros(prob.n_dofs))))
+    assert np.all(x == 0)
+    bad = synth.rhs(prob.n_dofs, 0)
+    bad[3] = np.nan
+    with pytest.raises(m.OmgError) as e:
+        g.solve(cuda(bad))
+    assert e.value.status == m.EINVAL
+    _, _, _, g1 = pair(4, 1, 2, max_iter=1)
+    with pytest.raises(m.OmgError) as e:
+        g1.solve(cuda(synth.rhs(prob.n_dofs, 0)))
+    assert e.value.status == m.ENOCONV
+    with pytest.raises(m.OmgError) as e:
+        m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2, penalty_c=-4.0), cuda(nu))
+    assert e.value.status == m.ENOTSPD
+    rp, ci, v = o.matrix(0)
+    ci2 = ci.copy()
+    ci2[[0, 1]] = ci2[[1, 0]]
+    with pytest.raises(m.OmgError) as e:
+        m.Solver.from_bsr(rp, ci2, v, m.Solver.make_grid(4, 4, 4, 1, 2))
+    assert e.value.status == m.EINVAL
+    with pytest.raises(m.OmgError) as e:
+        m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(-nu))
+    assert e.value.status == m.EINVAL

@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the orthonormalization-multigrid solve on one MI355X.
+
+Workload (one "step" = one complete solve): the SIP-DG Poisson problem on
+64^3 cells with the P2 basis (2,621,440 DOFs), coefficient 1 inside a sphere
+of radius 0.3 centred in the unit cube and 1000 outside, iid N(0,1)
+right-hand side (seed 0), 4-level agglomeration hierarchy (64/32/16/8),
+multiplicative synchronous cycle (Algorithm 2) with 2 pre- and 2
+post-block-Jacobi iterations (omega = 0.7), level criteria of Sec. 4.2,
+coarsest level by dense Cholesky, solved to relative residual 1e-10 in FP64
+from x0 = 0. Inputs are resident in HBM before the timed region starts;
+setup (assembly, hierarchy, factorisations) is outside it.
+
+Prints one JSON line: DOF/s (FP64) with the mixed-precision (FP32 inner,
+FP64 iterative refinement) result beside it, the roofline of the dominant
+kernel (durations measured with HIP events on its stream during a solve),
+and the FP64 CPU oracle timed on a bounded sample of the same solve.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, nu, b, gpu_cycles, cycles=2):
+    """The FP64 oracle on the host cores: the first `cycles` cycles of the
+    same solve, scaled to DOF/s of the full solve by the GPU's cycle count."""
+    import oracle
+    o = oracle.Oracle.from_sip(prob, nu, s_pre=2, s_post=2, omega=0.7, max_iter=cycles)
+    t0 = time.perf_counter()
+    o.solve(b, tol=1e-10, check=False)
+    dt = time.perf_counter() - t0
+    frac = cycles / max(gpu_cycles, 1)
+    return {
+        "value": prob.n_dofs * frac / dt,
+        "unit": "DOF/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"first {cycles} of the {gpu_cycles} cycles of the same 64^3 P2 FP64 solve "
+                   f"({dt:.1f} s); DOF/s = DOFs x {cycles}/{gpu_cycles} / time. Later cycles hold more "
+                   f"stored directions, so this overstates the oracle's full-solve rate"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="cells per side")
+    ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solve is not sharded across GPUs in this build "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2512_08728_amd as omg
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob = synth.make_problem(args.n, args.p)
+    nu = synth.nu_sphere(args.n, args.n, args.n, prob.h)
+    b_host = synth.rhs(prob.n_dofs, 0)
+    b = torch.tensor(b_host, device="cuda")
+    grid = omg.Solver.make_grid(prob.nx, prob.ny, prob.nz, prob.p, prob.n_levels, prob.h)
+    opts = dict(s_pre=2, s_post=2, omega=0.7)
+    t0 = time.perf_counter()
+    s = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), **opts)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"setup {t_setup:.2f} s, {prob.n_dofs} DOFs, {prob.n_levels} levels")
+
+    for w in range(args.warmup):
+        s.solve(b, tol=1e-10)
+        log(f"warmup {w}: {s.last_report}")
+    s.kernel_counts()  # reset counters
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    t0 = time.perf_counter()
+    reps = []
+    for k in range(args.steps):
+        x = s.solve(b, tol=1e-10)
+        reps.append(s.last_report)
+        log(f"step {k}: {s.last_report['t_solve_ms']:.1f} ms, {s.last_report['iters_fine']} cycles")
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = prob.n_dofs / (ms_per_step / 1e3)
+    counts = s.kernel_counts() / args.steps
+    rep = reps[-1]
+
+    # dominant kernel: launches per solve x isolated duration, over kinds and levels
+    cand = []
+    for kind in (omg.K_SPMV, omg.K_BJ, omg.K_MGS, omg.K_BJFIRST, omg.K_RMFIN, omg.K_RESTRICT, omg.K_PROLONG,
+                 omg.K_COARSE):
+        for l in range(prob.n_levels):
+            if counts[kind, l] <= 0:
+                continue
+            try:
+                ms, _ = s.bench_kernel(kind, l, reps=10)
+            except omg.OmgError:
+                continue
+            cand.append((counts[kind, l] * ms, kind, l, ms))
+    cand.sort(reverse=True)
+    breakdown = {f"{omg.K_NAMES[k]}@L{l}": round(t, 2) for t, k, l, _ in cand[:8]}
+    log(f"estimated ms per solve by kernel: {breakdown}")
+    roof = None
+    for _, kind, l, _ in cand:
+        if kind in (omg.K_SPMV, omg.K_BJ, omg.K_MGS):
+            # live: events around every launch of this kernel during one more solve
+            s.probe(kind, l, max_launches=200000)
+            s.solve(b, tol=1e-10)
+            n_l, avg_ms, alg = s.probe_result()
+            achieved = alg / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": f"{omg.K_NAMES[kind]} level {l}", "launches_timed": n_l,
+                    "avg_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg}
+            break
+
+    mixed = None
+    if not args.no_mixed:
+        sm = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), precision="mixed_ir", **opts)
+        sm.solve(b, tol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xm = sm.solve(b, tol=1e-10)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        r = sm.last_report
+        err = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
+        mixed = {"value": prob.n_dofs / tm, "unit": "DOF/s", "ms_per_step": round(tm * 1e3, 2),
+                 "iters_fine": r["iters_fine"], "outer_iters": r["outer_iters"],
+                 "rel_res_true": r["rel_res_true"], "rel_diff_to_fp64": err}
+        log(f"mixed: {mixed}")
+        sm.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(prob, nu, b_host, rep["iters_fine"])
+        log(f"cpu: {cpu}")
+
+    out = {
+        "metric": "DOF/s solved to rel. residual 1e-10 (FP64 vs mixed); SpMV/smoother HBM GB/s",
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"SIP-DG Poisson {args.n}^3 cells P{args.p} ({prob.n_dofs} DOFs), sphere r=0.3 "
+                               f"nu 1:1000, N(0,1) rhs seed 0, {prob.n_levels}-level OrthoMG Alg. 2, 2+2 "
+                               f"block-Jacobi omega 0.7, dense Cholesky coarsest, tol 1e-10",
+                   "iters_fine": rep["iters_fine"], "n_dirs_fine": rep["n_dirs_fine"],
+                   "rel_res_true": rep["rel_res_true"], "setup_s": round(t_setup, 3),
+                   "wall_s": round(wall, 3)},
+        "mixed": mixed,
+        "roofline": roof,
+        "kernel_ms_per_solve": breakdown,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

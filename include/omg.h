@@ -188,6 +188,37 @@ omg_status omg_get_trace(const omg_solver *s, double *out, int32_t cap, int32_t 
  * n = 0 switches replay off. */
 omg_status omg_set_replay(omg_solver *s, const int32_t *visits, int32_t n);
 
+/* ---- kernel timing (benchmarks) -------------------------------------- */
+enum {
+    OMG_K_SPMV = 0,      /* w = A z, block SpMV of one level (FP64) */
+    OMG_K_SPMV32 = 1,    /* the same with the FP32 operator */
+    OMG_K_BJ = 2,        /* fused block-Jacobi iteration x' = x + omega D^-1 (r - A x) (FP64) */
+    OMG_K_BJ32 = 3,      /* the same in FP32 */
+    OMG_K_MGS = 4,       /* one modified Gram-Schmidt step of residual minimisation */
+    OMG_K_RESTRICT = 5,  /* r_c = P^T r */
+    OMG_K_PROLONG = 6,   /* z = P z_c */
+    OMG_K_COARSE = 7,    /* coarsest-level solve (dense inverse GEMV) */
+    OMG_K_RMFIN = 8,     /* RM normalisation + update (two kernels) */
+    OMG_K_BJFIRST = 9,   /* first block-Jacobi iteration from zero, x = omega D^-1 r */
+    OMG_K_COUNT = 10
+};
+/* Launch kernel `kind` of level `level` `reps` times on the solver's stream
+ * between two HIP events (inputs are the level's work buffers, filled with
+ * finite data); *avg_ms = mean duration per launch, *alg_bytes = the bytes
+ * the operation must move per launch (operator values and column indices of
+ * the stored blocks, each vector read or written once). */
+omg_status omg_bench_kernel(omg_solver *s, int32_t kind, int32_t level, int32_t reps, double *avg_ms,
+                            double *alg_bytes);
+/* Arm a probe: during the following solves, every launch of kernel `kind` on
+ * `level` (up to max_launches) is bracketed by HIP events on the stream it is
+ * launched on. omg_probe_result returns the number of timed launches, their
+ * mean duration and the algorithmic bytes per launch, and disarms the probe. */
+omg_status omg_probe_kernel(omg_solver *s, int32_t kind, int32_t level, int32_t max_launches);
+omg_status omg_probe_result(omg_solver *s, int64_t *launches, double *avg_ms, double *alg_bytes);
+/* Launch counts of the last solve(s) since the previous call, per kernel kind
+ * and level: host out[OMG_K_COUNT][OMG_MAX_LEVELS]; counters are reset. */
+omg_status omg_get_kernel_counts(omg_solver *s, int64_t *out);
+
 #ifdef __cplusplus
 }
 #endif

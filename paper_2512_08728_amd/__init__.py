@@ -62,7 +62,11 @@ _lib = None
 EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "omg_solve_batched",
            "omg_solve_backward", "omg_destroy", "omg_strerror", "omg_level_info", "omg_level_matrix",
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
-           "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay"]
+           "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay", "omg_bench_kernel",
+           "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result"]
+K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST = range(10)
+K_NAMES = ["spmv", "spmv32", "bj_sweep", "bj_sweep32", "mgs_step", "restrict", "prolong", "coarse_gemv",
+           "rm_finish", "bj_first"]
 
 
 def lib():
@@ -96,6 +100,10 @@ def lib():
         L.omg_get_visits.argtypes = [P, P, i32, P]
         L.omg_get_trace.argtypes = [P, P, i32, P]
         L.omg_set_replay.argtypes = [P, P, i32]
+        L.omg_bench_kernel.argtypes = [P, i32, i32, i32, P, P]
+        L.omg_get_kernel_counts.argtypes = [P, P]
+        L.omg_probe_kernel.argtypes = [P, i32, i32, i32]
+        L.omg_probe_result.argtypes = [P, P, P, P]
         for name in EXPORTS:
             if name not in ("omg_default_options", "omg_destroy", "omg_strerror"):
                 getattr(L, name).restype = ctypes.c_int
@@ -285,6 +293,27 @@ class Solver:
         out = np.zeros(3 * max(n.value, 1))
         lib().omg_get_trace(self._h, out.ctypes.data, n.value, ctypes.byref(n))
         return out[: 3 * n.value].reshape(-1, 3)
+
+    def bench_kernel(self, kind, level, reps=20):
+        """(average ms per launch, algorithmic bytes per launch) of one kernel,
+        timed with HIP events on the solver's stream."""
+        ms, by = ctypes.c_double(), ctypes.c_double()
+        _check(lib().omg_bench_kernel(self._h, kind, level, reps, ctypes.byref(ms), ctypes.byref(by)),
+               "bench_kernel")
+        return ms.value, by.value
+
+    def probe(self, kind, level, max_launches=100000):
+        _check(lib().omg_probe_kernel(self._h, kind, level, max_launches), "probe_kernel")
+
+    def probe_result(self):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().omg_probe_result(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)), "probe_result")
+        return n.value, ms.value, by.value
+
+    def kernel_counts(self):
+        out = np.zeros((10, MAX_LEVELS), dtype=np.int64)
+        _check(lib().omg_get_kernel_counts(self._h, out.ctypes.data), "kernel_counts")
+        return out
 
     def set_replay(self, visits):
         v = np.ascontiguousarray(np.asarray(visits, dtype=np.int32).reshape(-1))

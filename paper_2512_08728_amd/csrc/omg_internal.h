@@ -95,6 +95,12 @@ struct omg_solver {
     std::vector<int> replay;
     size_t replay_pos = 0;
     int mode32 = 0;                    // 0 FP64, 1 FP32 everywhere, 2 FP32 except finest-level RM
+    int64_t kcount[OMG_K_COUNT][OMG_MAX_LEVELS] = {};  // launches per kernel kind and level
+    int64_t nnzb_level[OMG_MAX_LEVELS] = {};           // stored (non-padding) blocks per level
+    // kernel probe: events around launches of one kernel kind on one level
+    int probe_kind = -1, probe_level = -1, probe_max = 0;
+    std::vector<hipEvent_t> probe_ev;                  // begin/end pairs
+    int64_t probe_n = 0;
     int step = 0;
     int status = 0;
 };

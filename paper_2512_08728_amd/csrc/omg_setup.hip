@@ -573,6 +573,9 @@ omg_status omg_alloc_level_vectors(omg_solver* s, Level& L) {
 // Diagonal slot of every cell from the host pattern (padding slots also point
 // at the cell itself, so the first valid slot with column == cell is taken).
 static omg_status upload_dslot(omg_solver* s, Level& L, const std::vector<unsigned char>& valid) {
+    int64_t cnt = 0;
+    for (unsigned char v : valid) cnt += v;
+    s->nnzb_level[&L - s->lev.data()] = cnt;
     std::vector<int> ds(L.n, -1);
     for (int i = 0; i < L.n; ++i)
         for (int j = 0; j < L.width; ++j)

@@ -271,6 +271,25 @@ static inline bool use32(const omg_solver* s, int l, bool is_rm) {
     return false;
 }
 
+// Kernel probe: bracket one launch with a pair of events when armed.
+static void probe_begin(omg_solver* s, int kind, int l, hipStream_t st) {
+    if (s->probe_kind != kind || s->probe_level != l || s->probe_n >= s->probe_max) return;
+    const size_t i = 2 * (size_t)s->probe_n;
+    while (s->probe_ev.size() < i + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        s->probe_ev.push_back(e);
+    }
+    hipEventRecord(s->probe_ev[i], st);
+}
+static void probe_end(omg_solver* s, int kind, int l, hipStream_t st) {
+    if (s->probe_kind != kind || s->probe_level != l || s->probe_n >= s->probe_max) return;
+    const size_t i = 2 * (size_t)s->probe_n;
+    if (s->probe_ev.size() < i + 2) return;
+    hipEventRecord(s->probe_ev[i + 1], st);
+    s->probe_n++;
+}
+
 // Make room for direction index k on level l (chunks of 32 directions).
 static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
     if (k < (int)L.W.size()) return OMG_OK;
@@ -303,7 +322,13 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
     double* P_b = L.part + 2 * kMaxRedBlocks;
     double* P_alpha = L.part + 3 * kMaxRedBlocks;
     double* P_rn = L.part + 4 * kMaxRedBlocks;
+    const int kspmv = use32(s, l, true) ? OMG_K_SPMV32 : OMG_K_SPMV;
+    probe_begin(s, kspmv, l, st);
     HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
+    probe_end(s, kspmv, l, st);
+    s->kcount[kspmv][l]++;
+    s->kcount[OMG_K_MGS][l] += L.k;
+    s->kcount[OMG_K_RMFIN][l]++;
     const double* P_nout = P_nin;
     if (L.k == 0) {
         HIP_OK(launch_dot2(N, G, nullptr, nullptr, nullptr, L.w, P_nin, st));
@@ -313,7 +338,9 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
             double* pin = (i & 1) ? P_b : P_a;
             double* pout = (i & 1) ? P_a : P_b;
             const double* next = (i + 1 < L.k) ? L.W[i + 1] : nullptr;
+            probe_begin(s, OMG_K_MGS, l, st);
             HIP_OK(launch_mgs_step(N, G, pin, L.W[i], L.Z[i], L.w, z, next, pout, st));
+            probe_end(s, OMG_K_MGS, l, st);
             P_nout = pout;
         }
     }
@@ -350,8 +377,13 @@ static omg_status smoother(omg_solver* s, int l, const double* r, int sweeps, do
     double* bufs[2] = {out, L.t};
     int cur = (sweeps % 2 == 1) ? 0 : 1;
     HIP_OK(launch_bj_first(L, s->bs, f32, s->opt.omega, r, bufs[cur], st));
+    s->kcount[OMG_K_BJFIRST][l]++;
+    s->kcount[f32 ? OMG_K_BJ32 : OMG_K_BJ][l] += sweeps - 1;
+    const int kbj = f32 ? OMG_K_BJ32 : OMG_K_BJ;
     for (int it = 1; it < sweeps; ++it) {
+        probe_begin(s, kbj, l, st);
         HIP_OK(launch_bj_sweep(L, s->bs, f32, s->opt.omega, r, bufs[cur], bufs[cur ^ 1], st));
+        probe_end(s, kbj, l, st);
         cur ^= 1;
     }
     return OMG_OK;
@@ -396,6 +428,8 @@ static omg_status coarse_path(omg_solver* s, int l, int variant, hipStream_t st,
     Level& C = s->lev[l + 1];
     OMG_TRY(mg(s, l + 1, C.b, C.xout, 0.0, variant, st));
     HIP_OK(launch_prolong(F, C, s->bs, use32(s, l, false), s->E, s->E32, C.xout, z, st));
+    s->kcount[OMG_K_PROLONG][l]++;
+    s->kcount[OMG_K_RESTRICT][l]++;
     return OMG_OK;
 }
 
@@ -403,6 +437,7 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     Level& L = s->lev[l];
     if (L.coarsest) {
         HIP_OK(launch_gemv(L, b, xout, st));
+        s->kcount[OMG_K_COARSE][l]++;
         return OMG_OK;
     }
     Level& C = s->lev[l + 1];
@@ -829,5 +864,145 @@ extern "C" omg_status omg_get_trace(const omg_solver* s, double* out, int32_t ca
 extern "C" omg_status omg_set_replay(omg_solver* s, const int32_t* visits, int32_t n) {
     if (!s || n < 0 || (n > 0 && !visits)) return OMG_EINVAL;
     s->replay.assign(visits, visits + 2 * (size_t)n);
+    return OMG_OK;
+}
+
+// ------------------------------------------------------------------ kernel timing
+extern "C" omg_status omg_get_kernel_counts(omg_solver* s, int64_t* out) {
+    if (!s || !out) return OMG_EINVAL;
+    for (int k = 0; k < OMG_K_COUNT; ++k)
+        for (int l = 0; l < OMG_MAX_LEVELS; ++l) {
+            out[k * OMG_MAX_LEVELS + l] = s->kcount[k][l];
+            s->kcount[k][l] = 0;
+        }
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t level, int32_t reps, double* avg_ms,
+                                       double* alg_bytes) {
+    if (!s || level < 0 || level >= s->nlev || reps < 1 || !avg_ms || kind < 0 || kind >= OMG_K_COUNT)
+        return OMG_EINVAL;
+    Level& L = s->lev[level];
+    hipStream_t st = s->stream;
+    const int bs = s->bs;
+    const double N = (double)L.N, nnzb = (double)s->nnzb_level[level], bb = (double)bs * bs;
+    const bool needs_fine = kind != OMG_K_COARSE;
+    if (needs_fine && L.coarsest && kind != OMG_K_SPMV) return OMG_EINVAL;
+    if ((kind == OMG_K_RESTRICT || kind == OMG_K_PROLONG) && level + 1 >= s->nlev) return OMG_EINVAL;
+    if (kind == OMG_K_COARSE && !L.coarsest) return OMG_EINVAL;
+    HIP_OK(launch_fill(L.z, 1.0, L.N, st));
+    HIP_OK(launch_fill(L.w, 0.5, L.N, st));
+    HIP_OK(launch_fill(L.b, 0.5, L.N, st));
+    if (L.r) HIP_OK(launch_fill(L.r, 0.25, L.N, st));
+    if (L.x) HIP_OK(launch_fill(L.x, 0.0, L.N, st));
+    double bytes = 0.0;
+    if (kind == OMG_K_RMFIN) OMG_TRY(ensure_dir(s, L, 0));
+    if (kind == OMG_K_MGS) {
+        OMG_TRY(ensure_dir(s, L, 1));
+        HIP_OK(launch_fill(L.W[0], 1.0 / std::sqrt(N), L.N, st));
+        HIP_OK(launch_fill(L.Z[0], 0.0, L.N, st));
+        HIP_OK(launch_fill(L.W[1], 1.0 / std::sqrt(N), L.N, st));
+        HIP_OK(launch_dot2(L.N, L.G, L.W[0], L.w, L.part + kMaxRedBlocks, nullptr, nullptr, st));
+    }
+    auto launch = [&](int rep) -> hipError_t {
+        switch (kind) {
+        case OMG_K_SPMV: bytes = nnzb * bb * 8 + nnzb * 4 + 2 * N * 8;
+            return launch_spmv(L, bs, false, L.z, nullptr, L.w, st);
+        case OMG_K_SPMV32: bytes = nnzb * bb * 4 + nnzb * 4 + 2 * N * 8;
+            return launch_spmv(L, bs, true, L.z, nullptr, L.w, st);
+        case OMG_K_BJ: bytes = nnzb * bb * 8 + nnzb * 4 + L.n * bb * 8 + 3 * N * 8;
+            return launch_bj_sweep(L, bs, false, s->opt.omega, L.r, L.z, L.w, st);
+        case OMG_K_BJ32: bytes = nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8;
+            return launch_bj_sweep(L, bs, true, s->opt.omega, L.r, L.z, L.w, st);
+        case OMG_K_BJFIRST: bytes = L.n * bb * 8 + 2 * N * 8;
+            return launch_bj_first(L, bs, false, s->opt.omega, L.r, L.w, st);
+        case OMG_K_MGS: { // w, z stay resident in the method: one read of W_i and Z_i
+            bytes = 2 * N * 8;
+            double* pin = L.part + ((rep & 1) ? 2 : 1) * kMaxRedBlocks;
+            double* pout = L.part + ((rep & 1) ? 1 : 2) * kMaxRedBlocks;
+            return launch_mgs_step(L.N, L.G, pin, L.W[0], L.Z[0], L.w, L.z, L.W[1], pout, st);
+        }
+        case OMG_K_RESTRICT: {
+            const Level& C = s->lev[level + 1];
+            bytes = (N + (double)C.N) * 8;
+            return launch_restrict(L, C, bs, false, s->E, s->E32, L.r, C.b, st);
+        }
+        case OMG_K_PROLONG: {
+            const Level& C = s->lev[level + 1];
+            bytes = (N + (double)C.N) * 8;
+            return launch_prolong(L, C, bs, false, s->E, s->E32, C.b, L.w, st);
+        }
+        case OMG_K_COARSE: bytes = N * N * 8 + 2 * N * 8;
+            return launch_gemv(L, L.b, L.xout, st);
+        case OMG_K_RMFIN: {
+            bytes = 8 * N * 8;
+            hipError_t e = launch_dot2(L.N, L.G, nullptr, nullptr, nullptr, L.w, L.part, st);
+            if (e != hipSuccess) return e;
+            e = launch_rm_normalize(L.N, L.G, L.part, L.part, s->opt.breakdown, L.w, L.z, L.W[0],
+                                               L.Z[0], L.r, L.part + 3 * kMaxRedBlocks, L.scal, st);
+            if (e != hipSuccess) return e;
+            return launch_rm_update(L.N, L.G, L.part + 3 * kMaxRedBlocks, L.W[0], L.Z[0], L.x, L.r,
+                                    L.part + 4 * kMaxRedBlocks, st);
+        }
+        }
+        return hipErrorInvalidValue;
+    };
+    HIP_OK(launch(0)); // warm-up
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) HIP_OK(launch(r + 1));
+    HIP_OK(hipEventRecord(e1, st));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *avg_ms = ms / reps;
+    if (alg_bytes) *alg_bytes = bytes;
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_probe_kernel(omg_solver* s, int32_t kind, int32_t level, int32_t max_launches) {
+    if (!s || kind < 0 || kind >= OMG_K_COUNT || level < 0 || level >= s->nlev || max_launches < 0)
+        return OMG_EINVAL;
+    s->probe_kind = kind;
+    s->probe_level = level;
+    s->probe_max = max_launches;
+    s->probe_n = 0;
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_probe_result(omg_solver* s, int64_t* launches, double* avg_ms, double* alg_bytes) {
+    if (!s || !launches || !avg_ms) return OMG_EINVAL;
+    double tot = 0.0;
+    for (int64_t i = 0; i < s->probe_n; ++i) {
+        HIP_OK(hipEventSynchronize(s->probe_ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, s->probe_ev[2 * i], s->probe_ev[2 * i + 1]));
+        tot += ms;
+    }
+    *launches = s->probe_n;
+    *avg_ms = s->probe_n ? tot / s->probe_n : 0.0;
+    if (alg_bytes) {
+        const int l = s->probe_level, bs = s->bs;
+        const Level& L = s->lev[l];
+        const double N = (double)L.N, nnzb = (double)s->nnzb_level[l], bb = (double)bs * bs;
+        double b = 0.0;
+        switch (s->probe_kind) {
+        case OMG_K_SPMV: b = nnzb * bb * 8 + nnzb * 4 + 2 * N * 8; break;
+        case OMG_K_SPMV32: b = nnzb * bb * 4 + nnzb * 4 + 2 * N * 8; break;
+        case OMG_K_BJ: b = nnzb * bb * 8 + nnzb * 4 + L.n * bb * 8 + 3 * N * 8; break;
+        case OMG_K_BJ32: b = nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8; break;
+        case OMG_K_MGS: b = 2 * N * 8; break;
+        default: b = 0.0;
+        }
+        *alg_bytes = b;
+    }
+    for (hipEvent_t e : s->probe_ev) hipEventDestroy(e);
+    s->probe_ev.clear();
+    s->probe_kind = -1;
+    s->probe_n = 0;
     return OMG_OK;
 }

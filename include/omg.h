@@ -200,7 +200,8 @@ enum {
     OMG_K_COARSE = 7,    /* coarsest-level solve (dense inverse GEMV) */
     OMG_K_RMFIN = 8,     /* RM normalisation + update (two kernels) */
     OMG_K_BJFIRST = 9,   /* first block-Jacobi iteration from zero, x = omega D^-1 r */
-    OMG_K_COUNT = 10
+    OMG_K_RMP = 10,      /* persistent residual minimisation (whole MGS loop + update, one launch) */
+    OMG_K_COUNT = 11
 };
 /* Launch kernel `kind` of level `level` `reps` times on the solver's stream
  * between two HIP events (inputs are the level's work buffers, filled with

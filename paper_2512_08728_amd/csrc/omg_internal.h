@@ -62,6 +62,15 @@ struct Level {
     int k = 0;
     std::vector<double*> W, Z;         // size = allocated capacity
     std::vector<double*> chunks;       // backing allocations
+    double** dWp = nullptr;            // device copies of the W / Z pointer arrays
+    double** dZp = nullptr;
+    size_t dcap = 0;
+    // persistent residual minimisation (cooperative grid Gp, cells per thread cpt)
+    int persist = 0, Gp = 0, cpt = 0;
+    unsigned* bar = nullptr;           // [2]: [1] = abort flag of the persistent kernel's waits
+    unsigned long long* xslots = nullptr; // exchange words [2][kMaxRedBlocks][2]
+    unsigned long long phase = 0;      // next exchange phase of this level (host counter)
+    int Grn = 1;                       // number of ||r||^2 partials written by the last update
 };
 
 struct Trace {
@@ -101,6 +110,7 @@ struct omg_solver {
     int probe_kind = -1, probe_level = -1, probe_max = 0;
     std::vector<hipEvent_t> probe_ev;                  // begin/end pairs
     int64_t probe_n = 0;
+    double probe_bytes = 0.0;                          // algorithmic bytes summed over probed launches
     int step = 0;
     int status = 0;
 };
@@ -138,6 +148,14 @@ hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_
 hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st);
 hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStream_t st);
+
+// persistent RM (omg_rm.hip)
+bool rm_persistent_config(int n, int bs, int* G, int* cpt);
+hipError_t launch_rm_persistent(int n, int bs, int G, int cpt, int k, const double* const* Wp,
+                                const double* const* Zp, const double* w, const double* z, double* Wk, double* Zk,
+                                double* x, double* r, unsigned long long* slots, unsigned long long g0,
+                                double* part_rn, double breakdown, double* scal, unsigned* abort_flag,
+                                hipStream_t st);
 
 // ---------------------------------------------------------------- setup
 // (omg_setup.hip)

@@ -566,7 +566,7 @@ omg_status omg_alloc_level_vectors(omg_solver* s, Level& L) {
     OMG_TRY(dmalloc((void**)&L.t, vb));
     OMG_TRY(dmalloc((void**)&L.t2, vb));
     OMG_TRY(dmalloc((void**)&L.zcor, vb));
-    OMG_TRY(dmalloc((void**)&L.part, sizeof(double) * 8 * kMaxRedBlocks));
+    OMG_TRY(dmalloc((void**)&L.part, sizeof(double) * 16 * kMaxRedBlocks));
     return OMG_OK;
 }
 

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "omg_internal.h"
@@ -101,6 +102,10 @@ static void free_level(Level& L) {
     hipFree(L.part);
     hipFree(L.scal);
     for (double* c : L.chunks) hipFree(c);
+    hipFree(L.dWp);
+    hipFree(L.dZp);
+    hipFree(L.bar);
+    hipFree(L.xslots);
     L = Level();
 }
 
@@ -193,6 +198,14 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
         if (!L.coarsest) {
             OMG_TRY(omg_block_inverses(s, L));
             OMG_TRY(omg_fp32_copies(s, L));
+            if (!std::getenv("OMG_NO_PERSISTENT_RM")) L.persist = rm_persistent_config(L.n, s->bs, &L.Gp, &L.cpt);
+            if (L.persist) {
+                if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
+                HIP_OK(hipMemset(L.bar, 0, 2 * sizeof(unsigned)));
+                const size_t xs = sizeof(unsigned long long) * 2 * kMaxRedBlocks * 2;
+                if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
+                HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
+            }
         } else {
             OMG_TRY(omg_coarse_factor(s, L));
         }
@@ -282,12 +295,32 @@ static void probe_begin(omg_solver* s, int kind, int l, hipStream_t st) {
     }
     hipEventRecord(s->probe_ev[i], st);
 }
-static void probe_end(omg_solver* s, int kind, int l, hipStream_t st) {
+static void probe_end(omg_solver* s, int kind, int l, hipStream_t st, double bytes) {
     if (s->probe_kind != kind || s->probe_level != l || s->probe_n >= s->probe_max) return;
     const size_t i = 2 * (size_t)s->probe_n;
     if (s->probe_ev.size() < i + 2) return;
     hipEventRecord(s->probe_ev[i + 1], st);
     s->probe_n++;
+    s->probe_bytes += bytes;
+}
+
+// Algorithmic bytes of one launch: operator values and column indices of the
+// stored blocks, block-diagonal inverses, and every vector read or written once.
+static double alg_bytes(const omg_solver* s, int kind, int l, int k) {
+    const Level& L = s->lev[l];
+    const double N = (double)L.N, nnzb = (double)s->nnzb_level[l], bb = (double)s->bs * s->bs;
+    switch (kind) {
+    case OMG_K_SPMV: return nnzb * bb * 8 + nnzb * 4 + 2 * N * 8;
+    case OMG_K_SPMV32: return nnzb * bb * 4 + nnzb * 4 + 2 * N * 8;
+    case OMG_K_BJ: return nnzb * bb * 8 + nnzb * 4 + L.n * bb * 8 + 3 * N * 8;
+    case OMG_K_BJ32: return nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8;
+    case OMG_K_BJFIRST: return L.n * bb * 8 + 2 * N * 8;
+    case OMG_K_MGS: return 2 * N * 8;                 // W_i and Z_i; w and z stay resident
+    case OMG_K_RMP: return (2.0 * k + 8) * N * 8;     // W_i, Z_i for i < k; w, z in; W_k, Z_k out; x, r in/out
+    case OMG_K_RMFIN: return 8 * N * 8;
+    case OMG_K_COARSE: return N * N * 8 + 2 * N * 8;
+    }
+    return 0.0;
 }
 
 // Make room for direction index k on level l (chunks of 32 directions).
@@ -304,6 +337,20 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
         L.W.push_back(mem + (size_t)L.N * (2 * c));
         L.Z.push_back(mem + (size_t)L.N * (2 * c + 1));
     }
+    // device copies of the pointer arrays (read by the persistent RM kernel)
+    double **dW = nullptr, **dZ = nullptr;
+    if (hipMalloc((void**)&dW, sizeof(double*) * L.W.size()) != hipSuccess ||
+        hipMalloc((void**)&dZ, sizeof(double*) * L.Z.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        return OMG_ENOMEM;
+    }
+    HIP_OK(hipMemcpy(dW, L.W.data(), sizeof(double*) * L.W.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(dZ, L.Z.data(), sizeof(double*) * L.Z.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipFree(L.dWp)); // hipFree waits for work that may still read the old arrays
+    HIP_OK(hipFree(L.dZp));
+    L.dWp = dW;
+    L.dZp = dZ;
+    L.dcap = L.W.size();
     (void)s;
     return OMG_OK;
 }
@@ -325,8 +372,28 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
     const int kspmv = use32(s, l, true) ? OMG_K_SPMV32 : OMG_K_SPMV;
     probe_begin(s, kspmv, l, st);
     HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
-    probe_end(s, kspmv, l, st);
+    probe_end(s, kspmv, l, st, alg_bytes(s, kspmv, l, 0));
     s->kcount[kspmv][l]++;
+    // Cooperative grids only ever run on the caller's stream: in the overlap
+    // variant the coarse levels (second stream) use the per-step kernels, in
+    // both its two-stream and one-stream forms, so the two give identical bits.
+    const bool coop = L.persist && st == s->stream && !(s->opt.variant == OMG_OVERLAP_DET && l > 0);
+    if (coop) {
+        probe_begin(s, OMG_K_RMP, l, st);
+        hipError_t e = launch_rm_persistent(L.n, s->bs, L.Gp, L.cpt, L.k, L.dWp, L.dZp, L.w, z, L.W[L.k],
+                                            L.Z[L.k], L.x, L.r, L.xslots, L.phase, P_rn, s->opt.breakdown,
+                                            L.scal, L.bar + 1, st);
+        L.phase += (unsigned long long)L.k + 2;
+        probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
+        if (e == hipSuccess) {
+            s->kcount[OMG_K_RMP][l]++;
+            L.Grn = L.Gp;
+            L.k++;
+            return OMG_OK;
+        }
+        (void)hipGetLastError(); // cooperative launch refused: per-step kernels from now on
+        L.persist = 0;
+    }
     s->kcount[OMG_K_MGS][l] += L.k;
     s->kcount[OMG_K_RMFIN][l]++;
     const double* P_nout = P_nin;
@@ -340,13 +407,14 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
             const double* next = (i + 1 < L.k) ? L.W[i + 1] : nullptr;
             probe_begin(s, OMG_K_MGS, l, st);
             HIP_OK(launch_mgs_step(N, G, pin, L.W[i], L.Z[i], L.w, z, next, pout, st));
-            probe_end(s, OMG_K_MGS, l, st);
+            probe_end(s, OMG_K_MGS, l, st, alg_bytes(s, OMG_K_MGS, l, 0));
             P_nout = pout;
         }
     }
     HIP_OK(launch_rm_normalize(N, G, P_nin, P_nout, s->opt.breakdown, L.w, z, L.W[L.k], L.Z[L.k], L.r, P_alpha,
                                L.scal, st));
     HIP_OK(launch_rm_update(N, G, P_alpha, L.W[L.k], L.Z[L.k], L.x, L.r, P_rn, st));
+    L.Grn = G;
     L.k++;
     return OMG_OK;
 }
@@ -354,7 +422,7 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
 // Read ||r|| of level l (from the partials of the last update) to the host.
 static omg_status read_rnorm(omg_solver* s, int l, hipStream_t st, double* out) {
     Level& L = s->lev[l];
-    HIP_OK(launch_finish_norm(L.G, L.part + 4 * kMaxRedBlocks, L.scal + S_RNORM, st));
+    HIP_OK(launch_finish_norm(L.Grn, L.part + 4 * kMaxRedBlocks, L.scal + S_RNORM, st));
     HIP_OK(hipMemcpyAsync(s->host_scal + l, L.scal + S_RNORM, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     *out = s->host_scal[l];
@@ -364,6 +432,7 @@ static omg_status read_rnorm(omg_solver* s, int l, hipStream_t st, double* out) 
 static omg_status vec_norm(omg_solver* s, int l, const double* v, hipStream_t st, double* out) {
     Level& L = s->lev[l];
     HIP_OK(launch_dot2(L.N, L.G, nullptr, nullptr, nullptr, v, L.part + 4 * kMaxRedBlocks, st));
+    L.Grn = L.G;
     return read_rnorm(s, l, st, out);
 }
 
@@ -383,7 +452,7 @@ static omg_status smoother(omg_solver* s, int l, const double* r, int sweeps, do
     for (int it = 1; it < sweeps; ++it) {
         probe_begin(s, kbj, l, st);
         HIP_OK(launch_bj_sweep(L, s->bs, f32, s->opt.omega, r, bufs[cur], bufs[cur ^ 1], st));
-        probe_end(s, kbj, l, st);
+        probe_end(s, kbj, l, st, alg_bytes(s, kbj, l, 0));
         cur ^= 1;
     }
     return OMG_OK;
@@ -593,6 +662,16 @@ static omg_status finish_report(omg_solver* s, const double* b, const double* x,
             nb += v;
         }
     R->n_breakdowns = (int)nb;
+    for (auto& Lv : s->lev)
+        if (Lv.bar) {
+            unsigned flags[2];
+            HIP_OK(hipMemcpyAsync(flags, Lv.bar, sizeof(flags), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (flags[1]) { // a grid barrier timed out: results are not trustworthy
+                Lv.persist = 0;
+                return OMG_EHIP;
+            }
+        }
     R->n_visits = (int)s->visits.size() / 2;
     R->n_trace = (int)s->trace.size();
     return OMG_OK;
@@ -879,7 +958,7 @@ extern "C" omg_status omg_get_kernel_counts(omg_solver* s, int64_t* out) {
 }
 
 extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t level, int32_t reps, double* avg_ms,
-                                       double* alg_bytes) {
+                                       double* bytes_out) {
     if (!s || level < 0 || level >= s->nlev || reps < 1 || !avg_ms || kind < 0 || kind >= OMG_K_COUNT)
         return OMG_EINVAL;
     Level& L = s->lev[level];
@@ -897,6 +976,15 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
     if (L.x) HIP_OK(launch_fill(L.x, 0.0, L.N, st));
     double bytes = 0.0;
     if (kind == OMG_K_RMFIN) OMG_TRY(ensure_dir(s, L, 0));
+    const int kb = 16; // directions used by the persistent RM benchmark
+    if (kind == OMG_K_RMP) {
+        if (!L.persist) return OMG_EUNSUPPORTED;
+        OMG_TRY(ensure_dir(s, L, kb));
+        for (int i = 0; i <= kb; ++i) {
+            HIP_OK(launch_fill(L.W[i], 1.0 / std::sqrt(N), L.N, st));
+            HIP_OK(launch_fill(L.Z[i], 0.0, L.N, st));
+        }
+    }
     if (kind == OMG_K_MGS) {
         OMG_TRY(ensure_dir(s, L, 1));
         HIP_OK(launch_fill(L.W[0], 1.0 / std::sqrt(N), L.N, st));
@@ -934,6 +1022,14 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
         }
         case OMG_K_COARSE: bytes = N * N * 8 + 2 * N * 8;
             return launch_gemv(L, L.b, L.xout, st);
+        case OMG_K_RMP: bytes = alg_bytes(s, OMG_K_RMP, level, kb);
+        {
+            hipError_t e = launch_rm_persistent(L.n, bs, L.Gp, L.cpt, kb, L.dWp, L.dZp, L.w, L.z, L.W[kb], L.Z[kb],
+                                                L.x, L.r, L.xslots, L.phase, L.part + 4 * kMaxRedBlocks,
+                                                s->opt.breakdown, L.scal, L.bar + 1, st);
+            L.phase += (unsigned long long)kb + 2;
+            return e;
+        }
         case OMG_K_RMFIN: {
             bytes = 8 * N * 8;
             hipError_t e = launch_dot2(L.N, L.G, nullptr, nullptr, nullptr, L.w, L.part, st);
@@ -960,7 +1056,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     *avg_ms = ms / reps;
-    if (alg_bytes) *alg_bytes = bytes;
+    if (bytes_out) *bytes_out = bytes;
     return OMG_OK;
 }
 
@@ -971,10 +1067,11 @@ extern "C" omg_status omg_probe_kernel(omg_solver* s, int32_t kind, int32_t leve
     s->probe_level = level;
     s->probe_max = max_launches;
     s->probe_n = 0;
+    s->probe_bytes = 0.0;
     return OMG_OK;
 }
 
-extern "C" omg_status omg_probe_result(omg_solver* s, int64_t* launches, double* avg_ms, double* alg_bytes) {
+extern "C" omg_status omg_probe_result(omg_solver* s, int64_t* launches, double* avg_ms, double* alg_bytes_out) {
     if (!s || !launches || !avg_ms) return OMG_EINVAL;
     double tot = 0.0;
     for (int64_t i = 0; i < s->probe_n; ++i) {
@@ -985,21 +1082,7 @@ extern "C" omg_status omg_probe_result(omg_solver* s, int64_t* launches, double*
     }
     *launches = s->probe_n;
     *avg_ms = s->probe_n ? tot / s->probe_n : 0.0;
-    if (alg_bytes) {
-        const int l = s->probe_level, bs = s->bs;
-        const Level& L = s->lev[l];
-        const double N = (double)L.N, nnzb = (double)s->nnzb_level[l], bb = (double)bs * bs;
-        double b = 0.0;
-        switch (s->probe_kind) {
-        case OMG_K_SPMV: b = nnzb * bb * 8 + nnzb * 4 + 2 * N * 8; break;
-        case OMG_K_SPMV32: b = nnzb * bb * 4 + nnzb * 4 + 2 * N * 8; break;
-        case OMG_K_BJ: b = nnzb * bb * 8 + nnzb * 4 + L.n * bb * 8 + 3 * N * 8; break;
-        case OMG_K_BJ32: b = nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8; break;
-        case OMG_K_MGS: b = 2 * N * 8; break;
-        default: b = 0.0;
-        }
-        *alg_bytes = b;
-    }
+    if (alg_bytes_out) *alg_bytes_out = s->probe_n ? s->probe_bytes / s->probe_n : 0.0;
     for (hipEvent_t e : s->probe_ev) hipEventDestroy(e);
     s->probe_ev.clear();
     s->probe_kind = -1;

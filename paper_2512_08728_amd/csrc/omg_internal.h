@@ -16,6 +16,10 @@ namespace omg {
 // order, so a result does not depend on timing).
 constexpr int kThreads = 256;
 constexpr int kMaxRedBlocks = 1024;
+// largest number of stored directions per grid-wide exchange in the
+// persistent RM kernel, and the stride of the stored intra-block Gram entries
+constexpr int kRmBlock = 4;
+constexpr int kGramStride = kRmBlock - 1;
 
 // Device-resident scalars of one level (indices into Level::scal).
 enum Scal : int {
@@ -66,10 +70,14 @@ struct Level {
     double** dZp = nullptr;
     size_t dcap = 0;
     // persistent residual minimisation (cooperative grid Gp, cells per thread cpt)
-    int persist = 0, Gp = 0, cpt = 0;
+    int persist = 0, Gp = 0, cpt = 0, rmB = 1;
     unsigned* bar = nullptr;           // [2]: [1] = abort flag of the persistent kernel's waits
-    unsigned long long* xslots = nullptr; // exchange words [2][kMaxRedBlocks][2]
+    unsigned long long* xslots = nullptr; // exchange words [2][kMaxRedBlocks][kRmBlock + 1]
     unsigned long long phase = 0;      // next exchange phase of this level (host counter)
+    // implicit search directions (persistent levels): Z = Z~ U
+    double* U = nullptr;               // [ucap][ucap] column-major, upper triangular
+    int ucap = 0;                      // maximum directions of one level solve
+    double *alphas = nullptr, *betas = nullptr, *gram = nullptr, *dvec = nullptr;
     int Grn = 1;                       // number of ||r||^2 partials written by the last update
 };
 
@@ -150,12 +158,31 @@ hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st);
 hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStream_t st);
 
 // persistent RM (omg_rm.hip)
-bool rm_persistent_config(int n, int bs, int* G, int* cpt);
-hipError_t launch_rm_persistent(int n, int bs, int G, int cpt, int k, const double* const* Wp,
-                                const double* const* Zp, const double* w, const double* z, double* Wk, double* Zk,
-                                double* x, double* r, unsigned long long* slots, unsigned long long g0,
-                                double* part_rn, double breakdown, double* scal, unsigned* abort_flag,
-                                hipStream_t st);
+struct RmArgs {
+    int n, k;                          // cells, directions stored before this RM
+    const double* const* Wp;           // stored orthonormal directions
+    double* Wk;                        // receives the new direction w_k
+    double* Zk;                        // receives the raw direction z~_k
+    const double* w;                   // A z~
+    const double* z;                   // z~
+    double* r;                         // residual (updated)
+    unsigned long long* slots;         // exchange words
+    unsigned long long g0;             // first exchange phase of this launch
+    double* part_rn;                   // partials of ||r||^2 (one per block)
+    double breakdown;
+    double* scal;
+    unsigned* abort_flag;
+    double* betas;                     // [k] MGS coefficients of this RM
+    double* gram;                      // [.][kRmBlock-1] intra-block Gram entries
+    double* U;                         // Z = Z~ U
+    int ucap;
+    double* alphas;                    // alpha of every direction
+};
+bool rm_persistent_config(int n, int bs, int* G, int* cpt, int* B);
+hipError_t launch_rm_persistent(int bs, int G, int cpt, int B, const RmArgs& args, hipStream_t st);
+// out = Z~ (U alpha) for the first k directions
+hipError_t launch_combine(int64_t N, int k, const double* U, int ucap, const double* alpha, double* d,
+                          const double* const* V, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------- setup
 // (omg_setup.hip)

@@ -1,33 +1,42 @@
 // Persistent residual-minimisation kernel (Algorithm 1 after w = A z).
 //
-// One launch performs the whole modified Gram-Schmidt loop, the
-// normalisation, alpha = w.r and the x/r update. Every thread keeps the
-// entries of w and z it owns in registers for the whole loop, so each step
-// reads W_i and Z_i exactly once from memory; the k sequential MGS
-// coefficients need one grid-wide barrier each (the reductions are two-stage
-// and deterministic: every block sums the same partials in the same order).
-// A thread owns CPT cells (all bs components of each, component-major
-// layout), cells t, t + T, ..., T = total threads.
+// One launch performs the modified Gram-Schmidt loop of w against the stored
+// orthonormal directions W, the normalisation, alpha = w.r and the residual
+// update. Each thread keeps the entries of w it owns in registers for the
+// whole loop, so every stored direction is read once per launch.
+//
+// Search directions are kept implicitly: the raw direction z~ handed to RM is
+// stored as it is, and the library keeps the upper-triangular U with
+// Z = Z~ U, i.e. z_k = gamma (z~_k - sum_i beta_i z_i) becomes column k of U.
+// Within one level solve x is only needed at the end, so x = Z~ (U alpha) is
+// formed once by a separate kernel instead of updating x (and z) every step.
+// Per launch this moves k + 6 vectors instead of 2k + 8.
+//
+// MGS is evaluated B directions per grid-wide exchange: with c_t = W_{j0+t}.w
+// (w before the block) and the stored Gram entries G_tm = W_{j0+t}.W_{j0+m},
+// the MGS coefficients satisfy beta_t = c_t - sum_{m<t} G_tm beta_m, which is
+// the sequential MGS recursion in exact arithmetic. G is recorded when a
+// direction is created.
+//
+// Grid-wide exchange without fences: a device-scope fence on this 8-XCD part
+// writes back / invalidates an XCD's L2 and costs tens of microseconds per
+// barrier. Each block instead publishes its partial sums as 64-bit
+// agent-scope atomic words whose two low mantissa bits carry a phase tag
+// (phase mod 3; 3 = empty), and every block reads all G published words with
+// agent-scope atomic loads, waiting until each carries the expected tag.
+// Phases alternate between two slot sets; a block writes phase g+2 into the
+// set of phase g only after it has read every block's phase g+1 words, so
+// every block has finished reading phase g. The host keeps each level's phase
+// counter across launches, so a stale word always carries the tag of phase
+// g-2, never that of g. Clearing the two tag bits perturbs each partial by at
+// most 2^-51 relative; all readers see the same words, so the sums are the
+// same in every block and deterministic. Waits are bounded: a block that
+// waits too long raises an abort flag that ends every other wait, so every
+// wave reaches the end of the kernel; the host checks the flag.
 //
 // The grid is sized from the occupancy query so that every block is resident
-// at once, and the launch is an ordinary one (cooperative launches carry a
-// large per-launch cost on this runtime).
-//
-// Grid-wide exchange without fences: a device-scope memory fence on this
-// 8-XCD part writes back / invalidates an XCD's L2 and costs tens of
-// microseconds per barrier. Instead each block publishes its partial sum as
-// ONE 64-bit agent-scope atomic store whose two low mantissa bits carry a
-// phase tag (phase mod 3; 3 = empty), and every block reads all G published
-// words with agent-scope atomic loads, waiting until each carries the
-// expected tag. Phases alternate between two slot sets; a block writes phase
-// g+2 into the set of phase g only after it has read every block's phase g+1
-// word, so every block has finished reading phase g. The host keeps the phase
-// counter of each level across launches, so a stale word always carries the
-// tag of phase g-2, never that of g. Clearing the two tag bits perturbs each
-// partial by at most 2^-51 relative; every reader sees the same words, so the
-// sums stay identical across blocks and deterministic. Waits are bounded: a
-// block that waits too long raises an abort flag that ends every other wait,
-// so every wave reaches the end of the kernel; the host checks the flag.
+// at once; the launch is an ordinary one (cooperative launches carry a large
+// per-launch cost on this runtime).
 #include "omg_internal.h"
 
 namespace omg {
@@ -38,42 +47,6 @@ __device__ __forceinline__ unsigned long long tag_pack(double v, unsigned tag) {
     return ((unsigned long long)__double_as_longlong(v) & ~3ull) | tag;
 }
 __device__ __forceinline__ double tag_value(unsigned long long b) { return __longlong_as_double(b & ~3ull); }
-
-// Publish (v0, v1) of this block for phase g: slots[set][block][2].
-__device__ __forceinline__ void publish(unsigned long long* slots, int G, unsigned long long g, double v0, double v1) {
-    if (threadIdx.x == 0) {
-        unsigned long long* p = slots + ((g & 1) * G + blockIdx.x) * 2;
-        const unsigned tag = (unsigned)(g % 3);
-        __hip_atomic_store(p + 1, tag_pack(v1, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(p, tag_pack(v0, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Wait for word `w` of every block's phase-g slot and return this thread's
-// share of their sum (combine with a block reduction).
-__device__ __forceinline__ double collect(unsigned long long* slots, int G, unsigned long long g, int w,
-                                          unsigned* abort_flag) {
-    const unsigned tag = (unsigned)(g % 3);
-    const unsigned long long* base = slots + (g & 1) * G * 2 + w;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < G; i += blockDim.x) {
-        unsigned long long b = 0;
-        unsigned spins = 0;
-        for (;;) {
-            b = __hip_atomic_load(base + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((unsigned)(b & 3ull) == tag) break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinMax || ((spins & 127) == 0 &&
-                                       __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                b = 0;
-                break;
-            }
-        }
-        v += tag_value(b);
-    }
-    return v;
-}
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -91,185 +64,340 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
     return s;
 }
 
-// slots: exchange words (2 sets x G blocks x 2 words); g0: first phase of this
-// launch (the launch uses phases g0 .. g0+k+1); part_rn: plain partials of
-// ||r||^2 after the update (read by a later launch).
-template <int BS, int CPT>
-__global__ __launch_bounds__(kThreads) void k_rm_mgs(int n, int k, const double* const* __restrict__ Wp,
-                                                     const double* const* __restrict__ Zp,
-                                                     const double* __restrict__ wv, const double* __restrict__ zv,
-                                                     double* __restrict__ Wk, double* __restrict__ Zk,
-                                                     double* __restrict__ x, double* __restrict__ r,
-                                                     unsigned long long* __restrict__ slots, unsigned long long g0,
-                                                     double* __restrict__ part_rn, double breakdown,
-                                                     double* __restrict__ scal, unsigned* __restrict__ abort_flag) {
+// Publish this block's words for phase g: slots[set][block][SW]. All SW words
+// are written every phase (unused ones as zero), so the previous value of any
+// word is always from phase g-2 and carries a different tag.
+template <int SW>
+__device__ __forceinline__ void publish(unsigned long long* slots, int G, unsigned long long g, const double* v,
+                                        int nw) {
+    if (threadIdx.x == 0) {
+        unsigned long long* p = slots + ((g & 1) * (unsigned long long)G + blockIdx.x) * SW;
+        const unsigned tag = (unsigned)(g % 3);
+        for (int i = 0; i < SW; ++i)
+            __hip_atomic_store(p + i, tag_pack(i < nw ? v[i] : 0.0, tag), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Sum over blocks of words [0, nw) of phase g; every thread gets the totals.
+template <int SW>
+__device__ __forceinline__ void collect(unsigned long long* slots, int G, unsigned long long g, int nw, double* out,
+                                        double* sh, unsigned* abort_flag) {
+    const unsigned tag = (unsigned)(g % 3);
+    const unsigned long long* base = slots + (g & 1) * (unsigned long long)G * SW;
+    double v[SW];
+#pragma unroll
+    for (int w = 0; w < SW; ++w) v[w] = 0.0;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) {
+#pragma unroll
+        for (int w = 0; w < SW; ++w) {
+            if (w < nw) {
+                unsigned long long b = 0;
+                unsigned spins = 0;
+                for (;;) {
+                    b = __hip_atomic_load(base + (unsigned long long)i * SW + w, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    if ((unsigned)(b & 3ull) == tag) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kSpinMax ||
+                        ((spins & 127) == 0 &&
+                         __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        b = 0;
+                        break;
+                    }
+                }
+                v[w] += tag_value(b);
+            }
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < SW; ++w)
+        if (w < nw) out[w] = bsum(v[w], sh);
+}
+
+template <int BS, int CPT, int B>
+__global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
+    constexpr int SW = B + 1;
     __shared__ double sh[kThreads / 64];
     const int G = gridDim.x;
     const int T = G * blockDim.x;
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
-    double w[CPT][BS], z[CPT][BS], a[CPT][BS], an[CPT][BS], zi[CPT][BS];
+    const int n = A.n, k = A.k;
+    double w[CPT][BS], a[B][CPT][BS], an[B][CPT][BS];
     bool valid[CPT];
+    // w in registers; the raw direction z~ is stored as direction k
+    double* Zk = A.Zk;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int c = t0 + j * T;
         valid[j] = c < n;
 #pragma unroll
         for (int q = 0; q < BS; ++q) {
-            w[j][q] = valid[j] ? wv[(int64_t)q * n + c] : 0.0;
-            z[j][q] = valid[j] ? zv[(int64_t)q * n + c] : 0.0;
+            const int64_t e = (int64_t)q * n + c;
+            w[j][q] = valid[j] ? A.w[e] : 0.0;
+            if (valid[j]) Zk[e] = A.z[e];
         }
     }
-    unsigned long long g = g0;
-    // phase g0: ||w_in||^2 and W_0 . w
-    double s_in = 0.0, s_d = 0.0;
-    if (k > 0) {
-        const double* W0 = Wp[0];
+    auto load_block = [&](double (&dst)[B][CPT][BS], int j0) {
 #pragma unroll
-        for (int j = 0; j < CPT; ++j)
+        for (int t = 0; t < B; ++t) {
+            const bool have = j0 + t < k;
+            const double* Wt = have ? A.Wp[j0 + t] : nullptr;
 #pragma unroll
-            for (int q = 0; q < BS; ++q) a[j][q] = valid[j] ? W0[(int64_t)q * n + t0 + j * T] : 0.0;
-    }
+            for (int j = 0; j < CPT; ++j)
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
-#pragma unroll
-        for (int q = 0; q < BS; ++q) {
-            s_in = fma(w[j][q], w[j][q], s_in);
-            if (k > 0) s_d = fma(a[j][q], w[j][q], s_d);
+                for (int q = 0; q < BS; ++q)
+                    dst[t][j][q] = (have && valid[j]) ? Wt[(int64_t)q * n + t0 + j * T] : 0.0;
         }
-    s_in = bsum(s_in, sh);
-    s_d = bsum(s_d, sh);
-    publish(slots, G, g, k > 0 ? s_d : s_in, s_in);
-    const double nin = sqrt(bsum(collect(slots, G, g, 1, abort_flag), sh));
-    double nout2 = nin * nin;
-    for (int i = 0; i < k; ++i) {
-        // loads that do not depend on beta_i go out before the wait
-        const double* Zi = Zp[i];
-        const bool more = i + 1 < k;
-        const double* Wn = more ? Wp[i + 1] : Wp[i];
+    };
+    const int nblk = (k + B - 1) / B;
+    unsigned long long g = A.g0;
+    double vals[SW];
+    // phase g0: dots of the first block and ||w||^2
+    load_block(a, 0);
+    {
+        double s_in = 0.0;
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
 #pragma unroll
-            for (int q = 0; q < BS; ++q) {
-                const int64_t e = (int64_t)q * n + t0 + j * T;
-                zi[j][q] = valid[j] ? Zi[e] : 0.0;
-                an[j][q] = (valid[j] && more) ? Wn[e] : 0.0;
-            }
-        const double beta = bsum(collect(slots, G, g, 0, abort_flag), sh);
-        double s = 0.0;
+            for (int q = 0; q < BS; ++q) s_in = fma(w[j][q], w[j][q], s_in);
+        vals[B] = bsum(s_in, sh);
 #pragma unroll
-        for (int j = 0; j < CPT; ++j)
+        for (int t = 0; t < B; ++t) {
+            double s = 0.0;
 #pragma unroll
-            for (int q = 0; q < BS; ++q) {
-                w[j][q] = fma(-beta, a[j][q], w[j][q]);
-                z[j][q] = fma(-beta, zi[j][q], z[j][q]);
-                a[j][q] = an[j][q];
-                s = more ? fma(a[j][q], w[j][q], s) : fma(w[j][q], w[j][q], s);
+            for (int j = 0; j < CPT; ++j)
+#pragma unroll
+                for (int q = 0; q < BS; ++q) s = fma(a[t][j][q], w[j][q], s);
+            vals[t] = bsum(s, sh);
+        }
+        publish<SW>(A.slots, G, g, vals, SW);
+    }
+    double nin2 = 0.0, nout2 = 0.0;
+    double tot[SW];
+    for (int b = 0; b < nblk; ++b) {
+        const int j0 = b * B;
+        const int bb = min(B, k - j0);
+        if (b + 1 < nblk) load_block(an, j0 + B); // in flight while waiting
+        collect<SW>(A.slots, G, g, (b == 0) ? SW : bb, tot, sh, A.abort_flag);
+        if (b == 0) nin2 = tot[B];
+        double beta[B];
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            double bt = 0.0;
+            if (t < bb) {
+                bt = tot[t];
+                for (int m = 0; m < t; ++m) bt = fma(-A.gram[(int64_t)(j0 + t) * kGramStride + m], beta[m], bt);
             }
-        s = bsum(s, sh);
+            beta[t] = bt;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            for (int t = 0; t < bb; ++t) A.betas[j0 + t] = beta[t];
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+#pragma unroll
+                for (int q = 0; q < BS; ++q) w[j][q] = fma(-beta[t], a[t][j][q], w[j][q]);
         ++g;
-        publish(slots, G, g, s, 0.0);
-        if (!more) nout2 = bsum(collect(slots, G, g, 0, abort_flag), sh);
+        if (b + 1 < nblk) {
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < CPT; ++j)
+#pragma unroll
+                    for (int q = 0; q < BS; ++q) {
+                        a[t][j][q] = an[t][j][q];
+                        s = fma(a[t][j][q], w[j][q], s);
+                    }
+                vals[t] = bsum(s, sh);
+            }
+            publish<SW>(A.slots, G, g, vals, B);
+        } else {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+#pragma unroll
+                for (int q = 0; q < BS; ++q) s = fma(w[j][q], w[j][q], s);
+            vals[0] = bsum(s, sh);
+            publish<SW>(A.slots, G, g, vals, 1);
+            collect<SW>(A.slots, G, g, 1, tot, sh, A.abort_flag);
+            nout2 = tot[0];
+        }
     }
-    const double nout = sqrt(nout2);
-    const bool keep = nout > breakdown * nin; // false for NaN and for nout == 0
+    if (k == 0) {
+        collect<SW>(A.slots, G, g, SW, tot, sh, A.abort_flag);
+        nin2 = tot[B];
+        nout2 = nin2;
+    }
+    const double nin = sqrt(nin2), nout = sqrt(nout2);
+    const bool keep = nout > A.breakdown * nin; // false for NaN and for nout == 0
     const double gamma = keep ? 1.0 / nout : 0.0;
-    double s_a = 0.0;
+    // new direction W_k = gamma w; Gram entries with the earlier directions of its block
+    const int jk0 = k - (k % B), gk = k % B;
+    load_block(a, jk0); // entries t >= gk are zero (directions not stored yet)
+    double s_a = 0.0, s_g[B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) s_g[t] = 0.0;
 #pragma unroll
     for (int j = 0; j < CPT; ++j)
 #pragma unroll
         for (int q = 0; q < BS; ++q) {
             w[j][q] *= gamma;
-            z[j][q] *= gamma;
+            double rv = 0.0;
             if (valid[j]) {
                 const int64_t e = (int64_t)q * n + t0 + j * T;
-                Wk[e] = w[j][q];
-                Zk[e] = z[j][q];
-                a[j][q] = r[e];
-            } else {
-                a[j][q] = 0.0;
+                A.Wk[e] = w[j][q];
+                rv = A.r[e];
             }
-            s_a = fma(w[j][q], a[j][q], s_a);
+            an[0][j][q] = rv; // r kept in registers
+            s_a = fma(w[j][q], rv, s_a);
+#pragma unroll
+            for (int t = 0; t < B; ++t) s_g[t] = fma(a[t][j][q], w[j][q], s_g[t]);
         }
-    s_a = bsum(s_a, sh);
     ++g;
-    publish(slots, G, g, s_a, 0.0);
-    const double alpha = bsum(collect(slots, G, g, 0, abort_flag), sh);
+    vals[0] = bsum(s_a, sh);
+#pragma unroll
+    for (int t = 0; t < B - 1; ++t) vals[1 + t] = bsum(s_g[t], sh);
+    publish<SW>(A.slots, G, g, vals, B);
+    collect<SW>(A.slots, G, g, B, tot, sh, A.abort_flag);
+    const double alpha = tot[0];
     double s_r = 0.0;
 #pragma unroll
     for (int j = 0; j < CPT; ++j)
 #pragma unroll
         for (int q = 0; q < BS; ++q) {
-            const double rn = fma(-alpha, w[j][q], a[j][q]);
-            if (valid[j]) {
-                const int64_t e = (int64_t)q * n + t0 + j * T;
-                x[e] = fma(alpha, z[j][q], x[e]);
-                r[e] = rn;
-            }
+            const double rn = fma(-alpha, w[j][q], an[0][j][q]);
+            if (valid[j]) A.r[(int64_t)q * n + t0 + j * T] = rn;
             s_r = fma(rn, rn, s_r);
         }
     s_r = bsum(s_r, sh);
-    if (threadIdx.x == 0) {
-        part_rn[blockIdx.x] = s_r;
-        if (blockIdx.x == 0 && !keep) scal[S_BREAKDOWNS] += 1.0;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            A.part_rn[0] = s_r;
+            A.alphas[k] = alpha;
+            for (int t = 0; t < B - 1; ++t) A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? tot[1 + t] : 0.0;
+            if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
+        }
+        __syncthreads(); // betas written by thread 0 are read below
+        // column k of U: U[m,k] = gamma (delta_mk - sum_{i=m}^{k-1} beta_i U[m,i])
+        for (int m = threadIdx.x; m <= k; m += blockDim.x) {
+            double s = (m == k) ? 1.0 : 0.0;
+            for (int i = m; i < k; ++i) s = fma(-A.betas[i], A.U[m + (int64_t)i * A.ucap], s);
+            A.U[m + (int64_t)k * A.ucap] = gamma * s;
+        }
+    } else if (threadIdx.x == 0) {
+        A.part_rn[blockIdx.x] = s_r;
     }
 }
 
-template <int BS, int CPT>
+// d = U alpha (upper triangular, k x k, column-major with leading dim ucap)
+__global__ void k_tri_gemv(int k, const double* __restrict__ U, int ucap, const double* __restrict__ alpha,
+                           double* __restrict__ d) {
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < k; m += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = m; j < k; ++j) s = fma(U[m + (int64_t)j * ucap], alpha[j], s);
+        d[m] = s;
+    }
+}
+
+// out = sum_m d[m] V_m (k vectors of length N)
+__global__ __launch_bounds__(kThreads) void k_combine(int64_t N, int k, const double* const* __restrict__ V,
+                                                      const double* __restrict__ d, double* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double s = 0.0;
+        for (int m = 0; m < k; ++m) s = fma(d[m], V[m][e], s);
+        out[e] = s;
+    }
+}
+
+__global__ void k_zero(double* __restrict__ out, int64_t N) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) out[e] = 0.0;
+}
+
+template <int BS, int CPT, int B>
 static const void* rm_kernel() {
-    return reinterpret_cast<const void*>(&k_rm_mgs<BS, CPT>);
+    return reinterpret_cast<const void*>(&k_rm_blk<BS, CPT, B>);
 }
 
-static const void* pick(int bs, int cpt) {
-#define OMG_PICK(B)                                   \
-    if (bs == B) {                                    \
-        if (cpt == 1) return rm_kernel<B, 1>();       \
-        if (cpt == 2) return rm_kernel<B, 2>();       \
-        if (cpt == 4 && B * 4 <= 40) return rm_kernel<B, (B * 4 <= 40 ? 4 : 1)>(); \
-        if (cpt == 8 && B * 8 <= 40) return rm_kernel<B, (B * 8 <= 40 ? 8 : 1)>(); \
-        return nullptr;                               \
+// Instantiations: cells per thread CPT with CPT*BS <= 40, and B in {1, 2, 4}.
+template <int BS, int CPT>
+static const void* pick_b(int b) {
+    if (b == 4) return rm_kernel<BS, CPT, 4>();
+    if (b == 2) return rm_kernel<BS, CPT, 2>();
+    if (b == 1) return rm_kernel<BS, CPT, 1>();
+    return nullptr;
+}
+template <int BS>
+static const void* pick_bs(int cpt, int b) {
+    if (cpt == 1) return pick_b<BS, 1>(b);
+    if constexpr (BS * 2 <= 40) if (cpt == 2) return pick_b<BS, 2>(b);
+    if constexpr (BS * 4 <= 40) if (cpt == 4) return pick_b<BS, 4>(b);
+    if constexpr (BS * 8 <= 40) if (cpt == 8) return pick_b<BS, 8>(b);
+    return nullptr;
+}
+static const void* pick(int bs, int cpt, int b) {
+    switch (bs) {
+    case 1: return pick_bs<1>(cpt, b);
+    case 4: return pick_bs<4>(cpt, b);
+    case 10: return pick_bs<10>(cpt, b);
+    case 20: return pick_bs<20>(cpt, b);
     }
-    OMG_PICK(1)
-    OMG_PICK(4)
-    OMG_PICK(10)
-    OMG_PICK(20)
-#undef OMG_PICK
     return nullptr;
 }
 
-// Choose the cooperative grid for a level: as many co-resident blocks as the
-// device holds (capped by the cells), CPT = cells per thread.
-bool rm_persistent_config(int n, int bs, int* G, int* cpt) {
+// Grid for a level: the smallest cells-per-thread, then the largest MGS block,
+// whose grid is co-resident (occupancy query) with at most 512 blocks (every
+// block reads every block's words per exchange).
+bool rm_persistent_config(int n, int bs, int* G, int* cpt, int* B) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     for (int c : {1, 2, 4, 8}) {
-        const void* f = pick(bs, c);
-        if (!f) continue;
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess || per_cu < 1)
-            continue;
-        const int64_t max_blocks = (int64_t)per_cu * cus;
         const int64_t need = ((int64_t)n + (int64_t)kThreads * c - 1) / ((int64_t)kThreads * c);
-        // every block reads every block's word per exchange: keep G moderate
-        if (need <= max_blocks && need <= 512) {
-            *G = (int)need;
-            *cpt = c;
-            return true;
+        if (need > 512) continue;
+        for (int b : {4, 2, 1}) {
+            const void* f = pick(bs, c, b);
+            if (!f) continue;
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess || per_cu < 1)
+                continue;
+            if (need <= (int64_t)per_cu * cus) {
+                *G = (int)need;
+                *cpt = c;
+                *B = b;
+                return true;
+            }
         }
     }
     return false;
 }
 
-hipError_t launch_rm_persistent(int n, int bs, int G, int cpt, int k, const double* const* Wp,
-                                const double* const* Zp, const double* w, const double* z, double* Wk, double* Zk,
-                                double* x, double* r, unsigned long long* slots, unsigned long long g0,
-                                double* part_rn, double breakdown, double* scal, unsigned* abort_flag,
-                                hipStream_t st) {
-    const void* f = pick(bs, cpt);
+hipError_t launch_rm_persistent(int bs, int G, int cpt, int B, const RmArgs& args, hipStream_t st) {
+    const void* f = pick(bs, cpt, B);
     if (!f) return hipErrorInvalidValue;
-    void* args[] = {&n, &k, (void*)&Wp, (void*)&Zp, (void*)&w, (void*)&z, &Wk, &Zk, &x, &r, &slots, &g0,
-                    &part_rn, &breakdown, &scal, &abort_flag};
-    return hipLaunchKernel(f, dim3(G), dim3(kThreads), args, 0, st);
+    RmArgs a = args;
+    void* params[] = {&a};
+    return hipLaunchKernel(f, dim3(G), dim3(kThreads), params, 0, st);
+}
+
+hipError_t launch_combine(int64_t N, int k, const double* U, int ucap, const double* alpha, double* d,
+                          const double* const* V, double* out, hipStream_t st) {
+    int64_t blocks = (N + kThreads - 1) / kThreads;
+    if (blocks > 2048) blocks = 2048;
+    if (k == 0) {
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kThreads), 0, st, out, N);
+        return hipGetLastError();
+    }
+    if (alpha) // d = U alpha; otherwise d already holds the coefficients
+        hipLaunchKernelGGL(k_tri_gemv, dim3((k + kThreads - 1) / kThreads), dim3(kThreads), 0, st, k, U, ucap,
+                           alpha, d);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)blocks), dim3(kThreads), 0, st, N, k, V, d, out);
+    return hipGetLastError();
 }
 
 } // namespace omg

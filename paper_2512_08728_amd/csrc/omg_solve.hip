@@ -106,6 +106,11 @@ static void free_level(Level& L) {
     hipFree(L.dZp);
     hipFree(L.bar);
     hipFree(L.xslots);
+    hipFree(L.U);
+    hipFree(L.alphas);
+    hipFree(L.betas);
+    hipFree(L.gram);
+    hipFree(L.dvec);
     L = Level();
 }
 
@@ -198,13 +203,29 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
         if (!L.coarsest) {
             OMG_TRY(omg_block_inverses(s, L));
             OMG_TRY(omg_fp32_copies(s, L));
-            if (!std::getenv("OMG_NO_PERSISTENT_RM")) L.persist = rm_persistent_config(L.n, s->bs, &L.Gp, &L.cpt);
+            // the persistent RM runs on the caller's stream only: in the overlap
+            // variant the coarse levels (second stream) keep the per-step kernels
+            const bool eligible = !std::getenv("OMG_NO_PERSISTENT_RM") &&
+                                  !(s->opt.variant == OMG_OVERLAP_DET && l > 0);
+            if (eligible) L.persist = rm_persistent_config(L.n, s->bs, &L.Gp, &L.cpt, &L.rmB);
             if (L.persist) {
+                const int per_it = std::max(3, s->opt.n_s + 1);
+                const int its = (l == 0) ? s->opt.max_iter : s->opt.crit_max[l - 1];
+                L.ucap = per_it * std::max(its, 1) + 4;
                 if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
                 HIP_OK(hipMemset(L.bar, 0, 2 * sizeof(unsigned)));
-                const size_t xs = sizeof(unsigned long long) * 2 * kMaxRedBlocks * 2;
+                const size_t xs = sizeof(unsigned long long) * 2 * kMaxRedBlocks * (kRmBlock + 1);
                 if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
                 HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
+                const size_t uc = (size_t)L.ucap;
+                if (hipMalloc((void**)&L.U, sizeof(double) * uc * uc) != hipSuccess ||
+                    hipMalloc((void**)&L.alphas, sizeof(double) * uc) != hipSuccess ||
+                    hipMalloc((void**)&L.betas, sizeof(double) * uc) != hipSuccess ||
+                    hipMalloc((void**)&L.dvec, sizeof(double) * uc) != hipSuccess ||
+                    hipMalloc((void**)&L.gram, sizeof(double) * uc * kGramStride) != hipSuccess)
+                    return OMG_ENOMEM;
+                HIP_OK(hipMemset(L.U, 0, sizeof(double) * uc * uc));
+                HIP_OK(hipMemset(L.gram, 0, sizeof(double) * uc * kGramStride));
             }
         } else {
             OMG_TRY(omg_coarse_factor(s, L));
@@ -316,7 +337,7 @@ static double alg_bytes(const omg_solver* s, int kind, int l, int k) {
     case OMG_K_BJ32: return nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8;
     case OMG_K_BJFIRST: return L.n * bb * 8 + 2 * N * 8;
     case OMG_K_MGS: return 2 * N * 8;                 // W_i and Z_i; w and z stay resident
-    case OMG_K_RMP: return (2.0 * k + 8) * N * 8;     // W_i, Z_i for i < k; w, z in; W_k, Z_k out; x, r in/out
+    case OMG_K_RMP: return (k + 6.0 + k % L.rmB) * N * 8; // W_i (i < k), w, z~ in, W_k, Z~_k out, r in/out, Gram reads
     case OMG_K_RMFIN: return 8 * N * 8;
     case OMG_K_COARSE: return N * N * 8 + 2 * N * 8;
     }
@@ -374,25 +395,36 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
     HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
     probe_end(s, kspmv, l, st, alg_bytes(s, kspmv, l, 0));
     s->kcount[kspmv][l]++;
-    // Cooperative grids only ever run on the caller's stream: in the overlap
-    // variant the coarse levels (second stream) use the per-step kernels, in
-    // both its two-stream and one-stream forms, so the two give identical bits.
-    const bool coop = L.persist && st == s->stream && !(s->opt.variant == OMG_OVERLAP_DET && l > 0);
-    if (coop) {
+    if (L.persist) {
+        if (L.k + 1 > L.ucap) return OMG_ENOMEM;
+        RmArgs a;
+        a.n = L.n;
+        a.k = L.k;
+        a.Wp = L.dWp;
+        a.Wk = L.W[L.k];
+        a.Zk = L.Z[L.k];
+        a.w = L.w;
+        a.z = z;
+        a.r = L.r;
+        a.slots = L.xslots;
+        a.g0 = L.phase;
+        a.part_rn = P_rn;
+        a.breakdown = s->opt.breakdown;
+        a.scal = L.scal;
+        a.abort_flag = L.bar + 1;
+        a.betas = L.betas;
+        a.gram = L.gram;
+        a.U = L.U;
+        a.ucap = L.ucap;
+        a.alphas = L.alphas;
         probe_begin(s, OMG_K_RMP, l, st);
-        hipError_t e = launch_rm_persistent(L.n, s->bs, L.Gp, L.cpt, L.k, L.dWp, L.dZp, L.w, z, L.W[L.k],
-                                            L.Z[L.k], L.x, L.r, L.xslots, L.phase, P_rn, s->opt.breakdown,
-                                            L.scal, L.bar + 1, st);
-        L.phase += (unsigned long long)L.k + 2;
+        HIP_OK(launch_rm_persistent(s->bs, L.Gp, L.cpt, L.rmB, a, st));
         probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
-        if (e == hipSuccess) {
-            s->kcount[OMG_K_RMP][l]++;
-            L.Grn = L.Gp;
-            L.k++;
-            return OMG_OK;
-        }
-        (void)hipGetLastError(); // cooperative launch refused: per-step kernels from now on
-        L.persist = 0;
+        L.phase += (unsigned long long)((L.k + L.rmB - 1) / L.rmB) + 2;
+        s->kcount[OMG_K_RMP][l]++;
+        L.Grn = L.Gp;
+        L.k++;
+        return OMG_OK;
     }
     s->kcount[OMG_K_MGS][l] += L.k;
     s->kcount[OMG_K_RMFIN][l]++;
@@ -572,7 +604,10 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     if (l == 0 && status == OMG_OK && rn > tol * bn && replay_count < 0) status = OMG_ENOCONV;
     s->visits.push_back(l);
     s->visits.push_back(it);
-    HIP_OK(launch_copy(xout, L.x, L.N, st));
+    if (L.persist) // x = Z~ (U alpha): the search directions are implicit
+        HIP_OK(launch_combine(L.N, L.k, L.U, L.ucap, L.alphas, L.dvec, L.dZp, xout, st));
+    else
+        HIP_OK(launch_copy(xout, L.x, L.N, st));
     return status;
 }
 
@@ -909,7 +944,12 @@ extern "C" omg_status omg_get_dirs(const omg_solver* s, int32_t level, double* W
     const Level& L = s->lev[level];
     for (int i = 0; i < L.k; ++i) {
         if (W) HIP_OK(launch_from_soa(L.W[i], W + (size_t)i * L.N, L.n, s->bs, s->stream));
-        if (Z) HIP_OK(launch_from_soa(L.Z[i], Z + (size_t)i * L.N, L.n, s->bs, s->stream));
+        if (Z && !L.persist) HIP_OK(launch_from_soa(L.Z[i], Z + (size_t)i * L.N, L.n, s->bs, s->stream));
+        if (Z && L.persist) { // z_i = Z~ U[:, i]
+            HIP_OK(launch_combine(L.N, i + 1, L.U, L.ucap, nullptr, L.U + (size_t)i * L.ucap, L.dZp, s->bufB,
+                                  s->stream));
+            HIP_OK(launch_from_soa(s->bufB, Z + (size_t)i * L.N, L.n, s->bs, s->stream));
+        }
     }
     HIP_OK(hipStreamSynchronize(s->stream));
     return OMG_OK;
@@ -978,7 +1018,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
     if (kind == OMG_K_RMFIN) OMG_TRY(ensure_dir(s, L, 0));
     const int kb = 16; // directions used by the persistent RM benchmark
     if (kind == OMG_K_RMP) {
-        if (!L.persist) return OMG_EUNSUPPORTED;
+        if (!L.persist || L.ucap < kb + 1) return OMG_EUNSUPPORTED;
         OMG_TRY(ensure_dir(s, L, kb));
         for (int i = 0; i <= kb; ++i) {
             HIP_OK(launch_fill(L.W[i], 1.0 / std::sqrt(N), L.N, st));
@@ -1022,23 +1062,31 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
         }
         case OMG_K_COARSE: bytes = N * N * 8 + 2 * N * 8;
             return launch_gemv(L, L.b, L.xout, st);
-        case OMG_K_RMP: bytes = alg_bytes(s, OMG_K_RMP, level, kb);
-        {
-            hipError_t e = launch_rm_persistent(L.n, bs, L.Gp, L.cpt, kb, L.dWp, L.dZp, L.w, L.z, L.W[kb], L.Z[kb],
-                                                L.x, L.r, L.xslots, L.phase, L.part + 4 * kMaxRedBlocks,
-                                                s->opt.breakdown, L.scal, L.bar + 1, st);
-            L.phase += (unsigned long long)kb + 2;
+        case OMG_K_RMP: {
+            bytes = alg_bytes(s, OMG_K_RMP, level, kb);
+            RmArgs a;
+            a.n = L.n;
+            a.k = kb;
+            a.Wp = L.dWp;
+            a.Wk = L.W[kb];
+            a.Zk = L.Z[kb];
+            a.w = L.w;
+            a.z = L.z;
+            a.r = L.r;
+            a.slots = L.xslots;
+            a.g0 = L.phase;
+            a.part_rn = L.part + 4 * kMaxRedBlocks;
+            a.breakdown = s->opt.breakdown;
+            a.scal = L.scal;
+            a.abort_flag = L.bar + 1;
+            a.betas = L.betas;
+            a.gram = L.gram;
+            a.U = L.U;
+            a.ucap = L.ucap;
+            a.alphas = L.alphas;
+            hipError_t e = launch_rm_persistent(bs, L.Gp, L.cpt, L.rmB, a, st);
+            L.phase += (unsigned long long)((kb + L.rmB - 1) / L.rmB) + 2;
             return e;
-        }
-        case OMG_K_RMFIN: {
-            bytes = 8 * N * 8;
-            hipError_t e = launch_dot2(L.N, L.G, nullptr, nullptr, nullptr, L.w, L.part, st);
-            if (e != hipSuccess) return e;
-            e = launch_rm_normalize(L.N, L.G, L.part, L.part, s->opt.breakdown, L.w, L.z, L.W[0],
-                                               L.Z[0], L.r, L.part + 3 * kMaxRedBlocks, L.scal, st);
-            if (e != hipSuccess) return e;
-            return launch_rm_update(L.N, L.G, L.part + 3 * kMaxRedBlocks, L.W[0], L.Z[0], L.x, L.r,
-                                    L.part + 4 * kMaxRedBlocks, st);
         }
         }
         return hipErrorInvalidValue;

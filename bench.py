@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run the library's plain copy kernel on one finest-level vector "
+                         "(reference for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solve is not sharded across GPUs in this build "
@@ -85,6 +88,9 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup:.2f} s, {prob.n_dofs} DOFs, {prob.n_levels} levels")
+    if args.calib_copy:
+        ms, by = s.bench_kernel(omg.K_COPY, 0, reps=5)
+        log(f"calibration copy: {by / 2:.0f} bytes read + {by / 2:.0f} written per launch, {ms * 1e3:.1f} us")
 
     for w in range(args.warmup):
         s.solve(b, tol=1e-10)

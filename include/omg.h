@@ -201,7 +201,8 @@ enum {
     OMG_K_RMFIN = 8,     /* RM normalisation + update (two kernels) */
     OMG_K_BJFIRST = 9,   /* first block-Jacobi iteration from zero, x = omega D^-1 r */
     OMG_K_RMP = 10,      /* persistent residual minimisation (whole MGS loop + update, one launch) */
-    OMG_K_COUNT = 11
+    OMG_K_COPY = 11,     /* plain copy of one level vector (reference for traffic counters) */
+    OMG_K_COUNT = 12
 };
 /* Launch kernel `kind` of level `level` `reps` times on the solver's stream
  * between two HIP events (inputs are the level's work buffers, filled with

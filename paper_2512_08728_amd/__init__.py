@@ -64,9 +64,9 @@ EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "om
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
            "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay", "omg_bench_kernel",
            "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result"]
-K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST, K_RMP = range(11)
+K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST, K_RMP, K_COPY = range(12)
 K_NAMES = ["spmv", "spmv32", "bj_sweep", "bj_sweep32", "mgs_step", "restrict", "prolong", "coarse_gemv",
-           "rm_finish", "bj_first", "rm_persistent"]
+           "rm_finish", "bj_first", "rm_persistent", "copy"]
 
 
 def lib():
@@ -311,7 +311,7 @@ class Solver:
         return n.value, ms.value, by.value
 
     def kernel_counts(self):
-        out = np.zeros((11, MAX_LEVELS), dtype=np.int64)
+        out = np.zeros((12, MAX_LEVELS), dtype=np.int64)
         _check(lib().omg_get_kernel_counts(self._h, out.ctypes.data), "kernel_counts")
         return out
 

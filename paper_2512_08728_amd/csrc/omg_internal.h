@@ -42,6 +42,7 @@ struct Level {
     int64_t N = 0;                     // DOFs = n*bs
     int width = 0;                     // ELL block slots per cell
     int coarsest = 0;
+    int rowsplit = 0;                  // small level: one thread per (cell, block row) in SpMV / smoother
     int G = 1;                         // reduction grid for this level
 
     int* col = nullptr;                // [width][n]
@@ -74,10 +75,10 @@ struct Level {
     unsigned* bar = nullptr;           // [2]: [1] = abort flag of the persistent kernel's waits
     unsigned long long* xslots = nullptr; // exchange words [2][kMaxRedBlocks][kRmBlock + 1]
     unsigned long long phase = 0;      // next exchange phase of this level (host counter)
-    // implicit search directions (persistent levels): Z = Z~ U
-    double* U = nullptr;               // [ucap][ucap] column-major, upper triangular
+    // implicit search directions (persistent levels): raw directions + MGS coefficients
+    double* hist = nullptr;            // packed beta rows, ucap*(ucap-1)/2
     int ucap = 0;                      // maximum directions of one level solve
-    double *alphas = nullptr, *betas = nullptr, *gram = nullptr, *dvec = nullptr;
+    double *alphas = nullptr, *gammas = nullptr, *gram = nullptr, *dvec = nullptr;
     int Grn = 1;                       // number of ||r||^2 partials written by the last update
 };
 
@@ -155,6 +156,7 @@ hipError_t launch_rm_update(int64_t N, int G, const double* part_alpha, const do
 hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_t st);
 hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st);
+hipError_t launch_stream_copy(double* dst, const double* src, int64_t N, hipStream_t st);
 hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStream_t st);
 
 // persistent RM (omg_rm.hip)
@@ -172,17 +174,19 @@ struct RmArgs {
     double breakdown;
     double* scal;
     unsigned* abort_flag;
-    double* betas;                     // [k] MGS coefficients of this RM
-    double* gram;                      // [.][kRmBlock-1] intra-block Gram entries
-    double* U;                         // Z = Z~ U
-    int ucap;
+    double* hist;                      // packed rows: beta_{k,i} at k(k-1)/2 + i
+    double* gammas;                    // gamma of every direction (0 = dropped)
     double* alphas;                    // alpha of every direction
+    double* gram;                      // [.][kRmBlock-1] intra-block Gram entries
 };
 bool rm_persistent_config(int n, int bs, int* G, int* cpt, int* B);
 hipError_t launch_rm_persistent(int bs, int G, int cpt, int B, const RmArgs& args, hipStream_t st);
-// out = Z~ (U alpha) for the first k directions
-hipError_t launch_combine(int64_t N, int k, const double* U, int ucap, const double* alpha, double* d,
-                          const double* const* V, double* out, hipStream_t st);
+// d = coefficients of x = sum_k alpha_k z_k in the raw directions
+hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,
+                        hipStream_t st);
+// out = sum_m d[m] V_m
+hipError_t launch_lincomb(int64_t N, int k, const double* d, const double* const* V, double* out,
+                          hipStream_t st);
 
 // ---------------------------------------------------------------- setup
 // (omg_setup.hip)

@@ -168,6 +168,95 @@ __global__ __launch_bounds__(kThreads) void k_bj_sweep(int n, int width, const i
     }
 }
 
+// Row-split variants for small levels: one thread per (cell, block row), so
+// a level with few cells still spreads over the whole GPU. Same FMA order as
+// the cell-per-thread kernels, hence the same results bit for bit.
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_spmv_rows(int n, int width, const int* __restrict__ col,
+                                                        const typename Pair<MT>::type* __restrict__ val,
+                                                        const double* __restrict__ x, const double* __restrict__ b,
+                                                        double* __restrict__ y) {
+    constexpr int BSH = (BS + 1) / 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * BS) return;
+    const int i = (int)(t % n), r = (int)(t / n);
+    MT acc = MT(0);
+    for (int j = 0; j < width; ++j) {
+        const int c = col[(int64_t)j * n + i];
+        const typename Pair<MT>::type* vj = val + ((int64_t)j * BS * BSH + (int64_t)r * BSH) * n + i;
+#pragma unroll
+        for (int cp = 0; cp < BSH; ++cp) {
+            const typename Pair<MT>::type a = vj[(int64_t)cp * n];
+            acc = fma(a.x, (MT)x[(int64_t)(2 * cp) * n + c], acc);
+            acc = fma(a.y, (2 * cp + 1 < BS) ? (MT)x[(int64_t)(2 * cp + 1) * n + c] : MT(0), acc);
+        }
+    }
+    const int64_t o = (int64_t)r * n + i;
+    y[o] = b ? (double)((MT)b[o] - acc) : (double)acc;
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_bj_first_rows(int n, const typename Pair<MT>::type* __restrict__ dinv,
+                                                            MT omega, const double* __restrict__ r,
+                                                            double* __restrict__ x) {
+    constexpr int BSH = (BS + 1) / 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * BS) return;
+    const int i = (int)(t % n), rr = (int)(t / n);
+    MT s = MT(0);
+#pragma unroll
+    for (int cp = 0; cp < BSH; ++cp) {
+        const typename Pair<MT>::type d = dinv[(int64_t)(rr * BSH + cp) * n + i];
+        s = fma(d.x, (MT)r[(int64_t)(2 * cp) * n + i], s);
+        s = fma(d.y, (2 * cp + 1 < BS) ? (MT)r[(int64_t)(2 * cp + 1) * n + i] : MT(0), s);
+    }
+    x[(int64_t)rr * n + i] = (double)(omega * s);
+}
+
+// 64 cells x BS rows per block; the residual block t of each cell goes
+// through LDS to the D^-1 product.
+template <int BS, typename MT>
+__global__ __launch_bounds__(64 * BS) void k_bj_sweep_rows(int n, int width, const int* __restrict__ col,
+                                                           const typename Pair<MT>::type* __restrict__ val,
+                                                           const typename Pair<MT>::type* __restrict__ dinv,
+                                                           MT omega, const double* __restrict__ r,
+                                                           const double* __restrict__ xin,
+                                                           double* __restrict__ xout) {
+    constexpr int BSH = (BS + 1) / 2;
+    __shared__ MT ts[2 * BSH][64];
+    const int lc = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lc;
+    const bool ok = i < n;
+    MT acc = MT(0);
+    if (ok) {
+        for (int j = 0; j < width; ++j) {
+            const int c = col[(int64_t)j * n + i];
+            const typename Pair<MT>::type* vj = val + ((int64_t)j * BS * BSH + (int64_t)q * BSH) * n + i;
+#pragma unroll
+            for (int cp = 0; cp < BSH; ++cp) {
+                const typename Pair<MT>::type a = vj[(int64_t)cp * n];
+                acc = fma(a.x, (MT)xin[(int64_t)(2 * cp) * n + c], acc);
+                acc = fma(a.y, (2 * cp + 1 < BS) ? (MT)xin[(int64_t)(2 * cp + 1) * n + c] : MT(0), acc);
+            }
+        }
+        ts[q][lc] = (MT)r[(int64_t)q * n + i] - acc;
+    }
+    if (BS & 1) {
+        if (q == 0) ts[BS][lc] = MT(0);
+    }
+    __syncthreads();
+    if (!ok) return;
+    MT s = MT(0);
+#pragma unroll
+    for (int cp = 0; cp < BSH; ++cp) {
+        const typename Pair<MT>::type d = dinv[(int64_t)(q * BSH + cp) * n + i];
+        s = fma(d.x, ts[2 * cp][lc], s);
+        s = fma(d.y, ts[2 * cp + 1][lc], s);
+    }
+    const int64_t o = (int64_t)q * n + i;
+    xout[o] = (double)((MT)xin[o] + omega * s);
+}
+
 // ----------------------------------------------------------------- transfers
 // Restriction r_c = P^T r: each coarse cell sums E_s^T r_child over its 8
 // children in slot order s = sx + 2 sy + 4 sz. E is [8][BS][BS] (fine row,
@@ -341,6 +430,11 @@ __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) dst[e] = src[e];
 }
+// plain streaming copy (16-byte accesses), the reference kernel for traffic counters
+__global__ void k_stream_copy(double2* __restrict__ dst, const double2* __restrict__ src, int64_t N2) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N2; e += stride) dst[e] = src[e];
+}
 __global__ void k_fill(double* __restrict__ dst, double v, int64_t N) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) dst[e] = v;
@@ -377,6 +471,17 @@ hipError_t launch_from_soa(const double* in, double* out, int n, int bs, hipStre
 
 hipError_t launch_spmv(const Level& L, int bs, bool fp32, const double* x, const double* b, double* y,
                        hipStream_t st) {
+    if (L.rowsplit) {
+        dim3 g(cdiv((int64_t)L.n * bs, kThreads)), blk(kThreads);
+        if (fp32) {
+            OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv_rows<BSV, float>), g, blk, 0, st, L.n, L.width, L.col,
+                                                   (const float2*)L.val32, x, b, y));
+        } else {
+            OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv_rows<BSV, double>), g, blk, 0, st, L.n, L.width, L.col,
+                                                   (const double2*)L.val, x, b, y));
+        }
+        return hipGetLastError();
+    }
     dim3 grid(cdiv(L.n, kThreads)), block(kThreads);
     if (fp32) {
         OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv<BSV, float>), grid, block, 0, st, L.n, L.width, L.col,
@@ -390,6 +495,17 @@ hipError_t launch_spmv(const Level& L, int bs, bool fp32, const double* x, const
 
 hipError_t launch_bj_first(const Level& L, int bs, bool fp32, double omega, const double* r, double* x,
                            hipStream_t st) {
+    if (L.rowsplit) {
+        dim3 g(cdiv((int64_t)L.n * bs, kThreads)), blk(kThreads);
+        if (fp32) {
+            OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first_rows<BSV, float>), g, blk, 0, st, L.n,
+                                                   (const float2*)L.dinv32, (float)omega, r, x));
+        } else {
+            OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first_rows<BSV, double>), g, blk, 0, st, L.n,
+                                                   (const double2*)L.dinv, omega, r, x));
+        }
+        return hipGetLastError();
+    }
     dim3 grid(cdiv(L.n, kThreads)), block(kThreads);
     if (fp32) {
         OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first<BSV, float>), grid, block, 0, st, L.n,
@@ -403,6 +519,20 @@ hipError_t launch_bj_first(const Level& L, int bs, bool fp32, double omega, cons
 
 hipError_t launch_bj_sweep(const Level& L, int bs, bool fp32, double omega, const double* r, const double* xin,
                            double* xout, hipStream_t st) {
+    if (L.rowsplit) {
+        dim3 g(cdiv(L.n, 64)), blk(64 * bs);
+        if (fp32) {
+            OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep_rows<BSV, float>), g, dim3(64 * BSV), 0, st, L.n,
+                                                   L.width, L.col, (const float2*)L.val32, (const float2*)L.dinv32,
+                                                   (float)omega, r, xin, xout));
+        } else {
+            OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep_rows<BSV, double>), g, dim3(64 * BSV), 0, st, L.n,
+                                                   L.width, L.col, (const double2*)L.val, (const double2*)L.dinv,
+                                                   omega, r, xin, xout));
+        }
+        (void)blk;
+        return hipGetLastError();
+    }
     dim3 grid(cdiv(L.n, kThreads)), block(kThreads);
     if (fp32) {
         OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep<BSV, float>), grid, block, 0, st, L.n, L.width, L.col,
@@ -489,6 +619,11 @@ static inline int stream_blocks(int64_t N) {
 hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st) {
     if (N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy, dim3(stream_blocks(N)), dim3(kThreads), 0, st, dst, src, N);
+    return hipGetLastError();
+}
+hipError_t launch_stream_copy(double* dst, const double* src, int64_t N, hipStream_t st) {
+    if (N % 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stream_copy, dim3(2048), dim3(kThreads), 0, st, (double2*)dst, (const double2*)src, N / 2);
     return hipGetLastError();
 }
 hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st) {

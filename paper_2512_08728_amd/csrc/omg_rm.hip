@@ -6,11 +6,12 @@
 // whole loop, so every stored direction is read once per launch.
 //
 // Search directions are kept implicitly: the raw direction z~ handed to RM is
-// stored as it is, and the library keeps the upper-triangular U with
-// Z = Z~ U, i.e. z_k = gamma (z~_k - sum_i beta_i z_i) becomes column k of U.
-// Within one level solve x is only needed at the end, so x = Z~ (U alpha) is
-// formed once by a separate kernel instead of updating x (and z) every step.
-// Per launch this moves k + 6 vectors instead of 2k + 8.
+// stored as it is, together with the MGS coefficients beta_{k,i}, gamma_k and
+// alpha_k, so that z_k = gamma_k (z~_k - sum_{i<k} beta_{k,i} z_i). Within one
+// level solve x is only needed at the end: x = sum_k alpha_k z_k = sum_k d_k z~_k
+// with d obtained by a backward recurrence over k (k_recon), then one pass
+// over the raw directions (k_combine). Per launch this moves k + 6 vectors
+// instead of 2k + 8.
 //
 // MGS is evaluated B directions per grid-wide exchange: with c_t = W_{j0+t}.w
 // (w before the block) and the stored Gram entries G_tm = W_{j0+t}.W_{j0+m},
@@ -192,8 +193,8 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
             }
             beta[t] = bt;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            for (int t = 0; t < bb; ++t) A.betas[j0 + t] = beta[t];
+        if (blockIdx.x == 0 && threadIdx.x == 0) // row k of the coefficient history
+            for (int t = 0; t < bb; ++t) A.hist[(int64_t)k * (k - 1) / 2 + j0 + t] = beta[t];
 #pragma unroll
         for (int t = 0; t < B; ++t)
 #pragma unroll
@@ -274,32 +275,34 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
             s_r = fma(rn, rn, s_r);
         }
     s_r = bsum(s_r, sh);
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) {
-            A.part_rn[0] = s_r;
+    if (threadIdx.x == 0) {
+        A.part_rn[blockIdx.x] = s_r;
+        if (blockIdx.x == 0) {
             A.alphas[k] = alpha;
+            A.gammas[k] = gamma;
             for (int t = 0; t < B - 1; ++t) A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? tot[1 + t] : 0.0;
             if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
         }
-        __syncthreads(); // betas written by thread 0 are read below
-        // column k of U: U[m,k] = gamma (delta_mk - sum_{i=m}^{k-1} beta_i U[m,i])
-        for (int m = threadIdx.x; m <= k; m += blockDim.x) {
-            double s = (m == k) ? 1.0 : 0.0;
-            for (int i = m; i < k; ++i) s = fma(-A.betas[i], A.U[m + (int64_t)i * A.ucap], s);
-            A.U[m + (int64_t)k * A.ucap] = gamma * s;
-        }
-    } else if (threadIdx.x == 0) {
-        A.part_rn[blockIdx.x] = s_r;
     }
 }
 
-// d = U alpha (upper triangular, k x k, column-major with leading dim ucap)
-__global__ void k_tri_gemv(int k, const double* __restrict__ U, int ucap, const double* __restrict__ alpha,
-                           double* __restrict__ d) {
-    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < k; m += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int j = m; j < k; ++j) s = fma(U[m + (int64_t)j * ucap], alpha[j], s);
-        d[m] = s;
+// Coefficients of x = sum_k alpha_k z_k in the raw directions: with
+// z_k = gamma_k (z~_k - sum_{i<k} beta_{k,i} z_i), walk k downwards keeping the
+// coefficient c_i of every z_i still to be expanded: d_k = c_k gamma_k, then
+// c_i -= d_k beta_{k,i} for i < k. One wavefront; c lives in LDS.
+__global__ __launch_bounds__(64) void k_recon(int K, const double* __restrict__ hist,
+                                              const double* __restrict__ gammas, const double* __restrict__ alphas,
+                                              double* __restrict__ d) {
+    extern __shared__ double c[];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) c[i] = alphas[i];
+    __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {
+        const double dk = c[k] * gammas[k];
+        __syncthreads();
+        if (threadIdx.x == 0) d[k] = dk;
+        const double* hk = hist + (int64_t)k * (k - 1) / 2;
+        for (int i = threadIdx.x; i < k; i += blockDim.x) c[i] = fma(-dk, hk[i], c[i]);
+        __syncthreads();
     }
 }
 
@@ -385,17 +388,21 @@ hipError_t launch_rm_persistent(int bs, int G, int cpt, int B, const RmArgs& arg
     return hipLaunchKernel(f, dim3(G), dim3(kThreads), params, 0, st);
 }
 
-hipError_t launch_combine(int64_t N, int k, const double* U, int ucap, const double* alpha, double* d,
-                          const double* const* V, double* out, hipStream_t st) {
+hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,
+                        hipStream_t st) {
+    if (K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recon, dim3(1), dim3(64), sizeof(double) * (size_t)K, st, K, hist, gammas, alphas, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(int64_t N, int k, const double* d, const double* const* V, double* out,
+                          hipStream_t st) {
     int64_t blocks = (N + kThreads - 1) / kThreads;
     if (blocks > 2048) blocks = 2048;
     if (k == 0) {
         hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kThreads), 0, st, out, N);
         return hipGetLastError();
     }
-    if (alpha) // d = U alpha; otherwise d already holds the coefficients
-        hipLaunchKernelGGL(k_tri_gemv, dim3((k + kThreads - 1) / kThreads), dim3(kThreads), 0, st, k, U, ucap,
-                           alpha, d);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)blocks), dim3(kThreads), 0, st, N, k, V, d, out);
     return hipGetLastError();
 }

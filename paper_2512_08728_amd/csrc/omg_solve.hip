@@ -106,9 +106,9 @@ static void free_level(Level& L) {
     hipFree(L.dZp);
     hipFree(L.bar);
     hipFree(L.xslots);
-    hipFree(L.U);
+    hipFree(L.hist);
     hipFree(L.alphas);
-    hipFree(L.betas);
+    hipFree(L.gammas);
     hipFree(L.gram);
     hipFree(L.dvec);
     L = Level();
@@ -170,6 +170,9 @@ static omg_status create(const omg_grid* g, const omg_options* opt, void* stream
         L.N = (int64_t)L.n * s->bs;
         L.coarsest = (l == s->nlev - 1);
         L.G = reduction_blocks(L.N);
+        // few cells: split block rows over threads so the launch covers the GPU
+        const char* rs = std::getenv("OMG_ROWSPLIT_MAX_CELLS");
+        L.rowsplit = s->bs <= 16 && L.n <= (rs ? std::atoi(rs) : 65536); // 64*bs threads per smoother block
     }
     *out = s;
     if (hipMalloc((void**)&s->err_flag, sizeof(int)) != hipSuccess) return OMG_ENOMEM;
@@ -218,13 +221,12 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
                 if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
                 HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
                 const size_t uc = (size_t)L.ucap;
-                if (hipMalloc((void**)&L.U, sizeof(double) * uc * uc) != hipSuccess ||
+                if (hipMalloc((void**)&L.hist, sizeof(double) * (uc * (uc - 1) / 2 + 1)) != hipSuccess ||
                     hipMalloc((void**)&L.alphas, sizeof(double) * uc) != hipSuccess ||
-                    hipMalloc((void**)&L.betas, sizeof(double) * uc) != hipSuccess ||
+                    hipMalloc((void**)&L.gammas, sizeof(double) * uc) != hipSuccess ||
                     hipMalloc((void**)&L.dvec, sizeof(double) * uc) != hipSuccess ||
                     hipMalloc((void**)&L.gram, sizeof(double) * uc * kGramStride) != hipSuccess)
                     return OMG_ENOMEM;
-                HIP_OK(hipMemset(L.U, 0, sizeof(double) * uc * uc));
                 HIP_OK(hipMemset(L.gram, 0, sizeof(double) * uc * kGramStride));
             }
         } else {
@@ -412,11 +414,10 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
         a.breakdown = s->opt.breakdown;
         a.scal = L.scal;
         a.abort_flag = L.bar + 1;
-        a.betas = L.betas;
-        a.gram = L.gram;
-        a.U = L.U;
-        a.ucap = L.ucap;
+        a.hist = L.hist;
+        a.gammas = L.gammas;
         a.alphas = L.alphas;
+        a.gram = L.gram;
         probe_begin(s, OMG_K_RMP, l, st);
         HIP_OK(launch_rm_persistent(s->bs, L.Gp, L.cpt, L.rmB, a, st));
         probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
@@ -604,8 +605,10 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     if (l == 0 && status == OMG_OK && rn > tol * bn && replay_count < 0) status = OMG_ENOCONV;
     s->visits.push_back(l);
     s->visits.push_back(it);
-    if (L.persist) // x = Z~ (U alpha): the search directions are implicit
-        HIP_OK(launch_combine(L.N, L.k, L.U, L.ucap, L.alphas, L.dvec, L.dZp, xout, st));
+    if (L.persist) { // x = sum_k d_k z~_k: the search directions are implicit
+        HIP_OK(launch_recon(L.k, L.hist, L.gammas, L.alphas, L.dvec, st));
+        HIP_OK(launch_lincomb(L.N, L.k, L.dvec, L.dZp, xout, st));
+    }
     else
         HIP_OK(launch_copy(xout, L.x, L.N, st));
     return status;
@@ -942,16 +945,37 @@ extern "C" omg_status omg_coarse_solve(omg_solver* s, const double* b, double* x
 extern "C" omg_status omg_get_dirs(const omg_solver* s, int32_t level, double* W, double* Z) {
     if (!s || level < 0 || level >= s->nlev) return OMG_EINVAL;
     const Level& L = s->lev[level];
-    for (int i = 0; i < L.k; ++i) {
-        if (W) HIP_OK(launch_from_soa(L.W[i], W + (size_t)i * L.N, L.n, s->bs, s->stream));
-        if (Z && !L.persist) HIP_OK(launch_from_soa(L.Z[i], Z + (size_t)i * L.N, L.n, s->bs, s->stream));
-        if (Z && L.persist) { // z_i = Z~ U[:, i]
-            HIP_OK(launch_combine(L.N, i + 1, L.U, L.ucap, nullptr, L.U + (size_t)i * L.ucap, L.dZp, s->bufB,
+    const size_t K = (size_t)L.k;
+    std::vector<double> U; // persistent levels: z_j = sum_q U[q,j] z~_q, from the coefficient history
+    double* dcol = nullptr;
+    if (Z && L.persist && K > 0) {
+        std::vector<double> hh(K * (K - 1) / 2 + 1), gg(K);
+        HIP_OK(hipMemcpy(hh.data(), L.hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(gg.data(), L.gammas, sizeof(double) * K, hipMemcpyDeviceToHost));
+        U.assign(K * K, 0.0); // column j: gamma_j (e_j - sum_{m<j} beta_{j,m} U[:,m])
+        for (size_t j = 0; j < K; ++j) {
+            for (size_t m = 0; m < j; ++m) {
+                const double b = hh[j * (j - 1) / 2 + m];
+                for (size_t q = 0; q <= m; ++q) U[q + j * K] -= b * U[q + m * K];
+            }
+            U[j + j * K] += 1.0;
+            for (size_t q = 0; q <= j; ++q) U[q + j * K] *= gg[j];
+        }
+        HIP_OK(hipMalloc((void**)&dcol, sizeof(double) * K));
+    }
+    for (size_t i = 0; i < K; ++i) {
+        if (W) HIP_OK(launch_from_soa(L.W[i], W + i * L.N, L.n, s->bs, s->stream));
+        if (Z && !L.persist) HIP_OK(launch_from_soa(L.Z[i], Z + i * L.N, L.n, s->bs, s->stream));
+        if (Z && L.persist) {
+            HIP_OK(hipMemcpyAsync(dcol, U.data() + i * K, sizeof(double) * (i + 1), hipMemcpyHostToDevice,
                                   s->stream));
-            HIP_OK(launch_from_soa(s->bufB, Z + (size_t)i * L.N, L.n, s->bs, s->stream));
+            HIP_OK(launch_lincomb(L.N, (int)i + 1, dcol, L.dZp, s->bufB, s->stream));
+            HIP_OK(launch_from_soa(s->bufB, Z + i * L.N, L.n, s->bs, s->stream));
+            HIP_OK(hipStreamSynchronize(s->stream));
         }
     }
     HIP_OK(hipStreamSynchronize(s->stream));
+    if (dcol) HIP_OK(hipFree(dcol));
     return OMG_OK;
 }
 
@@ -1006,7 +1030,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
     const int bs = s->bs;
     const double N = (double)L.N, nnzb = (double)s->nnzb_level[level], bb = (double)bs * bs;
     const bool needs_fine = kind != OMG_K_COARSE;
-    if (needs_fine && L.coarsest && kind != OMG_K_SPMV) return OMG_EINVAL;
+    if (needs_fine && L.coarsest && kind != OMG_K_SPMV && kind != OMG_K_COPY) return OMG_EINVAL;
     if ((kind == OMG_K_RESTRICT || kind == OMG_K_PROLONG) && level + 1 >= s->nlev) return OMG_EINVAL;
     if (kind == OMG_K_COARSE && !L.coarsest) return OMG_EINVAL;
     HIP_OK(launch_fill(L.z, 1.0, L.N, st));
@@ -1062,6 +1086,8 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
         }
         case OMG_K_COARSE: bytes = N * N * 8 + 2 * N * 8;
             return launch_gemv(L, L.b, L.xout, st);
+        case OMG_K_COPY: bytes = 2 * N * 8;
+            return launch_stream_copy(L.w, L.z, L.N, st);
         case OMG_K_RMP: {
             bytes = alg_bytes(s, OMG_K_RMP, level, kb);
             RmArgs a;
@@ -1079,11 +1105,10 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
             a.breakdown = s->opt.breakdown;
             a.scal = L.scal;
             a.abort_flag = L.bar + 1;
-            a.betas = L.betas;
-            a.gram = L.gram;
-            a.U = L.U;
-            a.ucap = L.ucap;
+            a.hist = L.hist;
+            a.gammas = L.gammas;
             a.alphas = L.alphas;
+            a.gram = L.gram;
             hipError_t e = launch_rm_persistent(bs, L.Gp, L.cpt, L.rmB, a, st);
             L.phase += (unsigned long long)((kb + L.rmB - 1) / L.rmB) + 2;
             return e;

@@ -17,6 +17,7 @@ kernel (durations measured with HIP events on its stream during a solve),
 and the FP64 CPU oracle timed on a bounded sample of the same solve.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,10 +27,105 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_RM = os.path.join(ROOT, "profiles", "rm_persistent_L0_64cubed_p2.md")
+RM_SOURCE = os.path.join(ROOT, "paper_2512_08728_amd", "csrc", "omg_rm.hip")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rm_kernel_sha():
+    """Hash of the RM kernel's source: the part of its file before the
+    direction-recombination kernels (exchange helpers and the kernel itself)."""
+    text = open(RM_SOURCE, "rb").read()
+    end = text.find(b"// Coefficients of x = sum_k alpha_k z_k")
+    return hashlib.sha256(text[:end] if end > 0 else text).hexdigest()
+
+
+def profile_traffic(alg_bytes):
+    """HBM bytes per launch of the finest-level persistent RM kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by what the same counter reads for the plain copy
+    kernel of known size). None when the summary is absent or was taken on a
+    different kernel source."""
+    if not os.path.exists(PROFILE_RM):
+        return None
+    kv = {}
+    for line in open(PROFILE_RM):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    sha = rm_kernel_sha()
+    if kv.get("source_sha256") != sha:
+        return None
+    copy = float(kv["copy_bytes_each_way"])
+    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * copy / (float(kv["copy_fetch_kib"]) * 1024)
+    write = float(kv["write_kib_per_dispatch"]) * 1024 * copy / (float(kv["copy_write_kib"]) * 1024)
+    return {"bytes": round(fetch + write), "ratio_to_algorithmic": round((fetch + write) / alg_bytes, 4),
+            "note": f"counters of {kv.get('kernel', '?')} over {kv.get('dispatches', '?')} dispatches"}
+
+
+def batched_bench(omg, synth, torch):
+    """Batched workloads: 32 right-hand sides on one 32^3 P2 operator in
+    lockstep (matrix-core multi-RHS block products) against one single solve,
+    and 16 uneven instances (16^3..48^3 P2, FP64 outer / FP32 inner) in one
+    batched call against the same solves one after another."""
+    out = {}
+    prob = synth.make_problem(32, 2)
+    nu = synth.nu_sphere(32, 32, 32, prob.h)
+    grid = omg.Solver.make_grid(32, 32, 32, 2, prob.n_levels, prob.h)
+    s = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), s_pre=2, s_post=2)
+    B = torch.tensor(synth.multi_rhs(prob.n_dofs, 32, seed=0), device="cuda")
+    omg.solve_batched([s], [B], nrhs=32)  # creates the column solvers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, reps = omg.solve_batched([s], [B], nrhs=32)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b0 = B[:, 0].contiguous()
+    s.solve(b0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve(b0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    out["multi_rhs_32x32cubed_p2"] = {
+        "value": prob.n_dofs * 32 / tb, "unit": "DOF/s", "ms": round(tb * 1e3, 1),
+        "single_solve_ms": round(t1 * 1e3, 1), "speedup_vs_32_single": round(32 * t1 / tb, 2),
+        "iters_fine": [r["iters_fine"] for r in reps], "max_rel_res_true": max(r["rel_res_true"] for r in reps)}
+    log(f"multi-RHS: {out['multi_rhs_32x32cubed_p2']}")
+    s.close()
+    insts = synth.instances(16, seed=2)
+    solvers, rhs, dofs = [], [], 0
+    for inst in insts:
+        pr = synth.make_problem(inst.n, 2)
+        nu_i = synth.nu_sphere(inst.n, inst.n, inst.n, pr.h, center=inst.center, radius=inst.radius,
+                               nu_out=inst.ratio)
+        g = omg.Solver.make_grid(inst.n, inst.n, inst.n, 2, pr.n_levels, pr.h)
+        solvers.append(omg.Solver.from_sip(g, torch.tensor(nu_i, device="cuda"), s_pre=2, s_post=2,
+                                           precision="mixed_ir"))
+        rhs.append(torch.tensor(synth.rhs(pr.n_dofs, inst.seed), device="cuda").reshape(-1, 1))
+        dofs += pr.n_dofs
+    omg.solve_batched(solvers, rhs, nrhs=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, reps = omg.solve_batched(solvers, rhs, nrhs=1)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for sv, r in zip(solvers, rhs):
+        sv.solve(r.reshape(-1))
+    torch.cuda.synchronize()
+    tseq = time.perf_counter() - t0
+    out["instances_16_p2_mixed"] = {
+        "value": dofs / tb, "unit": "DOF/s", "ms": round(tb * 1e3, 1), "sequential_ms": round(tseq * 1e3, 1),
+        "speedup_vs_sequential": round(tseq / tb, 2), "cells_per_side": [i.n for i in insts], "total_dofs": dofs,
+        "max_rel_res_true": max(r["rel_res_true"] for r in reps)}
+    log(f"instances: {out['instances_16_p2_mixed']}")
+    for sv in solvers:
+        sv.close()
+    return out
 
 
 def cpu_baseline(prob, nu, b, gpu_cycles, cycles=2):
@@ -61,6 +157,7 @@ def main():
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the library's plain copy kernel on one finest-level vector "
                          "(reference for traffic counters)")
@@ -147,28 +244,34 @@ def main():
         if kind in (omg.K_SPMV, omg.K_BJ, omg.K_MGS, omg.K_RMP):
             n_l, avg_ms, alg = probed.get((kind, l)) or probe(kind, l)
             achieved = alg / (avg_ms * 1e-3) / 1e9
+            tr = profile_traffic(alg) if (kind == omg.K_RMP and l == 0) else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
+                    "traffic_detail": tr,
                     "kernel": f"{omg.K_NAMES[kind]} level {l}", "launches_timed": n_l,
                     "avg_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg}
             break
 
     mixed = None
     if not args.no_mixed:
-        sm = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), precision="mixed_ir", **opts)
-        sm.solve(b, tol=1e-10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xm = sm.solve(b, tol=1e-10)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        r = sm.last_report
-        err = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
-        mixed = {"value": prob.n_dofs / tm, "unit": "DOF/s", "ms_per_step": round(tm * 1e3, 2),
-                 "iters_fine": r["iters_fine"], "outer_iters": r["outer_iters"],
-                 "rel_res_true": r["rel_res_true"], "rel_diff_to_fp64": err}
-        log(f"mixed: {mixed}")
-        sm.close()
+        mixed = {}
+        for mode in ("mixed_ir", "mixed_flex"):
+            sm = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), precision=mode, **opts)
+            sm.solve(b, tol=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xm = sm.solve(b, tol=1e-10)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t0
+            r = sm.last_report
+            err = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
+            mixed[mode] = {"value": prob.n_dofs / tm, "unit": "DOF/s", "ms_per_step": round(tm * 1e3, 2),
+                           "iters_fine": r["iters_fine"], "outer_iters": r["outer_iters"],
+                           "rel_res_true": r["rel_res_true"], "rel_diff_to_fp64": err}
+            log(f"{mode}: {mixed[mode]}")
+            sm.close()
+
+    batched = None if args.no_batched else batched_bench(omg, synth, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -195,6 +298,7 @@ def main():
                    "rel_res_true": rep["rel_res_true"], "setup_s": round(t_setup, 3),
                    "wall_s": round(wall, 3)},
         "mixed": mixed,
+        "batched": batched,
         "roofline": roof,
         "kernel_ms_per_solve": breakdown,
         "cpu_baseline": cpu,

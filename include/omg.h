@@ -174,6 +174,26 @@ omg_status omg_level_restrict(omg_solver *s, int32_t level, const double *r, dou
 omg_status omg_level_prolong(omg_solver *s, int32_t level, const double *zc, double *z);
 /* x = A_c^-1 b on the coarsest level. */
 omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
+/* Multi-right-hand-side forms of the level operations, as run inside
+ * omg_solve_batched (matrix-core block products): X, B, Y are device arrays
+ * of shape (N_l, nrhs), RHS index fastest, cell-major DOFs, 1 <= nrhs <= 32.
+ * op OMG_MR_SPMV: Y = A_l X (B null) or Y = B - A_l X; OMG_MR_SMOOTHER:
+ * Y = Smoother(A_l, X, 0) with `sweeps` block-Jacobi iterations
+ * (Algorithm 4); OMG_MR_COARSE: Y = A_c^-1 X (coarsest level, FP64 only).
+ * fp32 = 1 uses the FP32 operator copies (inputs rounded to FP32, FP32
+ * arithmetic, results widened to FP64). OMG_EUNSUPPORTED for bs > 16. */
+enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
+/* Launch configurations the autotuners chose on a level, host shapes[15]:
+ * [0..11] the multi-right-hand-side kernels (tuned on the first batched
+ * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
+ * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..5 is
+ * (wavefronts per block, 16-column tiles per wavefront) = (4,2), (2,2),
+ * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..14] the persistent
+ * residual-minimisation kernel (tuned at setup): blocks, vector entries per
+ * thread, directions per grid exchange; -1 if the level does not use it. */
+omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
+omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
+                           const double *X, const double *B, double *Y);
 /* Stored directions of level l after the last solve (device, cell-major,
  * [k][N] each); W or Z nullable. */
 omg_status omg_get_dirs(const omg_solver *s, int32_t level, double *W, double *Z);

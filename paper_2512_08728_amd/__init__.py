@@ -63,7 +63,9 @@ EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "om
            "omg_solve_backward", "omg_destroy", "omg_strerror", "omg_level_info", "omg_level_matrix",
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
            "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay", "omg_bench_kernel",
-           "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result"]
+           "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result", "omg_level_multi",
+           "omg_level_tuning"]
+MR_SPMV, MR_SMOOTHER, MR_COARSE = 0, 1, 2
 K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST, K_RMP, K_COPY = range(12)
 K_NAMES = ["spmv", "spmv32", "bj_sweep", "bj_sweep32", "mgs_step", "restrict", "prolong", "coarse_gemv",
            "rm_finish", "bj_first", "rm_persistent", "copy"]
@@ -104,6 +106,8 @@ def lib():
         L.omg_get_kernel_counts.argtypes = [P, P]
         L.omg_probe_kernel.argtypes = [P, i32, i32, i32]
         L.omg_probe_result.argtypes = [P, P, P, P]
+        L.omg_level_multi.argtypes = [P, i32, i32, i32, i32, i32, P, P, P]
+        L.omg_level_tuning.argtypes = [P, i32, P]
         for name in EXPORTS:
             if name not in ("omg_default_options", "omg_destroy", "omg_strerror"):
                 getattr(L, name).restype = ctypes.c_int
@@ -271,6 +275,24 @@ class Solver:
         x = torch.empty_like(b)
         _check(lib().omg_coarse_solve(self._h, _ptr(b), _ptr(x)), "coarse_solve")
         return x
+
+    def level_multi(self, l, op, X, B=None, sweeps=1, fp32=False):
+        """Multi-right-hand-side level operation (as inside batched solves):
+        X, B are (N_l, nrhs) CUDA tensors, RHS index fastest."""
+        import torch
+        X = X.contiguous()
+        Y = torch.empty_like(X)
+        nrhs = X.shape[1]
+        _check(lib().omg_level_multi(self._h, l, op, nrhs, sweeps, int(fp32), _ptr(X),
+                                     None if B is None else _ptr(B.contiguous()), _ptr(Y)), "level_multi")
+        return Y
+
+    def level_tuning(self, l):
+        """Autotuned launch configurations of level l: (multi-RHS shapes
+        [op][fp32][two tiles], (RM blocks, entries per thread, MGS block))."""
+        out = np.zeros(15, dtype=np.int32)
+        _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
+        return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:])
 
     def dirs(self, l=0):
         import torch

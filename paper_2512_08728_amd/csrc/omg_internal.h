@@ -20,6 +20,30 @@ constexpr int kMaxRedBlocks = 1024;
 // persistent RM kernel, and the stride of the stored intra-block Gram entries
 constexpr int kRmBlock = 4;
 constexpr int kGramStride = kRmBlock - 1;
+// right-hand sides advanced together by the batched solve (two 16-wide
+// matrix-core tiles), and the pointers of their vectors passed by value
+constexpr int kMaxCols = 32;
+struct ColPtrs {
+    double* p[kMaxCols];
+};
+struct NormPack {
+    const double* part[kMaxCols];
+    int G[kMaxCols];
+};
+// Independent operators (instances) advanced together by one grouped launch
+// per operation; segment q covers blocks [blk0[q], blk0[q+1]).
+constexpr int kMaxSeg = 16;
+struct SegTable {
+    int count;
+    int blk0[kMaxSeg + 1];
+    int n[kMaxSeg], width[kMaxSeg];
+    const int* col[kMaxSeg];
+    const void* val[kMaxSeg];          // pair layout of the level (FP64 or FP32 copy)
+    const void* dinv[kMaxSeg];
+    const double* x[kMaxSeg];
+    const double* b[kMaxSeg];
+    double* y[kMaxSeg];
+};
 
 // Device-resident scalars of one level (indices into Level::scal).
 enum Scal : int {
@@ -52,9 +76,22 @@ struct Level {
     float* dinv32 = nullptr;
     double* ainv = nullptr;            // coarsest: dense inverse, [np][np] SoA DOF order
     int np = 0;                        // padded dense order
+    double* atile = nullptr;           // coarsest: lower-triangle 64x64 tiles of ainv (symmetric GEMV)
+    double* spart = nullptr;           // [ntile][ntile][64] partial products of the symmetric GEMV
+    int ntile = 0;
 
     std::vector<int> hcol;             // host copy of col (Galerkin symbolic phase)
     int* dslot = nullptr;              // [n] slot of the diagonal block of each cell
+    // block-contiguous copies for the multi-right-hand-side kernels (built on
+    // first use): blocks [n][width][bs][bs], inverses [n][bs][bs]
+    double* ablk = nullptr;
+    float* ablk32 = nullptr;
+    double* dblk = nullptr;
+    float* dblk32 = nullptr;
+    int shared_op = 0;                 // operator arrays belong to another solver (column solvers)
+    // autotuned launch shape + 1 of the multi-RHS kernels [op: spmv, bj_first,
+    // bj_sweep][FP64, FP32][one tile, two tiles]; 0 = not tuned
+    int mr_shape[3][2][2] = {};
 
     // work vectors (SoA, N each)
     double *b = nullptr, *r = nullptr, *x = nullptr, *z = nullptr, *w = nullptr;
@@ -70,8 +107,8 @@ struct Level {
     double** dWp = nullptr;            // device copies of the W / Z pointer arrays
     double** dZp = nullptr;
     size_t dcap = 0;
-    // persistent residual minimisation (cooperative grid Gp, cells per thread cpt)
-    int persist = 0, Gp = 0, cpt = 0, rmB = 1;
+    // persistent residual minimisation (one co-resident grid of Gp blocks)
+    int persist = 0, Gp = 0, ept = 0, rmB = 1; // grid, vector entries per thread, MGS block
     unsigned* bar = nullptr;           // [2]: [1] = abort flag of the persistent kernel's waits
     unsigned long long* xslots = nullptr; // exchange words [2][kMaxRedBlocks][kRmBlock + 1]
     unsigned long long phase = 0;      // next exchange phase of this level (host counter)
@@ -105,7 +142,8 @@ struct omg_solver {
     double* refm = nullptr;            // reference matrices: S, F[3][2][2], B[3][2] (device)
     // external <-> internal layout buffers (fine level)
     double *bufA = nullptr, *bufB = nullptr;
-    double* host_scal = nullptr;       // pinned
+    double* host_scal = nullptr;       // pinned, mapped: residual norms per level
+    double* host_scal_dev = nullptr;   // its device address
     int* err_flag = nullptr;           // device error flag (setup kernels)
     // logs of the last solve
     std::vector<int> visits;
@@ -122,6 +160,12 @@ struct omg_solver {
     double probe_bytes = 0.0;                          // algorithmic bytes summed over probed launches
     int step = 0;
     int status = 0;
+    // batched solves: column solvers that share this solver's operator arrays
+    // (work vectors and search directions of their own), created on demand
+    omg_solver* owner = nullptr;       // set on a column solver: the solver whose operator it uses
+    std::vector<omg_solver*> columns;
+    double* bnorm_host = nullptr;      // [kMaxCols] pinned, mapped: norms of batched members
+    double* bnorm_dev = nullptr;       // its device address
 };
 
 namespace omg {
@@ -142,6 +186,7 @@ hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, co
 hipError_t launch_prolong(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
                           const double* zc, double* z, hipStream_t st);
 hipError_t launch_gemv(const Level& L, const double* x, double* y, hipStream_t st);
+hipError_t build_symv_tiles(Level& L, hipStream_t st);
 
 // reductions: partial sums into part[0..G) (deterministic fixed-order)
 hipError_t launch_dot2(int64_t N, int G, const double* a, const double* b, double* part_ab, const double* c,
@@ -154,6 +199,9 @@ hipError_t launch_rm_normalize(int64_t N, int G, const double* part_nin, const d
 hipError_t launch_rm_update(int64_t N, int G, const double* part_alpha, const double* Wk, const double* Zk,
                             double* x, double* r, double* part_rn, hipStream_t st);
 hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_t st);
+// x = 0, r = b, partials of ||b||^2 into part[0..G) (as launch_dot2)
+hipError_t launch_level_init(int64_t N, int G, const double* b, double* x, double* r, double* part,
+                             hipStream_t st);
 hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st);
 hipError_t launch_stream_copy(double* dst, const double* src, int64_t N, hipStream_t st);
@@ -161,7 +209,8 @@ hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStrea
 
 // persistent RM (omg_rm.hip)
 struct RmArgs {
-    int n, k;                          // cells, directions stored before this RM
+    int64_t N;                         // vector entries
+    int k;                             // directions stored before this RM
     const double* const* Wp;           // stored orthonormal directions
     double* Wk;                        // receives the new direction w_k
     double* Zk;                        // receives the raw direction z~_k
@@ -179,8 +228,13 @@ struct RmArgs {
     double* alphas;                    // alpha of every direction
     double* gram;                      // [.][kRmBlock-1] intra-block Gram entries
 };
-bool rm_persistent_config(int n, int bs, int* G, int* cpt, int* B);
-hipError_t launch_rm_persistent(int bs, int G, int cpt, int B, const RmArgs& args, hipStream_t st);
+struct RmConfig {
+    int G, ept, B; // blocks, vector entries per thread, MGS directions per exchange
+};
+// co-resident configurations for N entries, most preferred first; returns the count
+int rm_persistent_candidates(int64_t N, RmConfig* out, int cap);
+bool rm_persistent_config(int64_t N, int* G, int* ept, int* B);
+hipError_t launch_rm_persistent(int G, int ept, int B, const RmArgs& args, hipStream_t st);
 // d = coefficients of x = sum_k alpha_k z_k in the raw directions
 hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,
                         hipStream_t st);
@@ -188,12 +242,46 @@ hipError_t launch_recon(int K, const double* hist, const double* gammas, const d
 hipError_t launch_lincomb(int64_t N, int k, const double* d, const double* const* V, double* out,
                           hipStream_t st);
 
+// multi-right-hand-side kernels (omg_multi.hip): nr <= kMaxCols columns that
+// share the operator of L; B may be null (then Y = A X, else Y = B - A X)
+hipError_t build_blocks(Level& L, int bs, int bsh, hipStream_t st);
+hipError_t launch_spmv_mr(const Level& L, int bs, bool fp32, int nr, const ColPtrs& X, const ColPtrs* B,
+                          const ColPtrs& Y, hipStream_t st);
+hipError_t launch_bj_first_mr(const Level& L, int bs, bool fp32, double omega, int nr, const ColPtrs& R,
+                              const ColPtrs& X, hipStream_t st);
+hipError_t launch_bj_sweep_mr(const Level& L, int bs, bool fp32, double omega, int nr, const ColPtrs& R,
+                              const ColPtrs& Xin, const ColPtrs& Xout, hipStream_t st);
+hipError_t launch_dense_mr(const Level& L, int nr, const ColPtrs& X, const ColPtrs& Y, hipStream_t st);
+// time every launch shape of the multi-RHS kernels on L for nr columns and keep
+// the fastest per (operation, precision, tile count); best_us[6] (nullable)
+hipError_t tune_mr(Level& L, int bs, int nr, const ColPtrs& X, const ColPtrs& Y, const ColPtrs& T, int reps,
+                   hipStream_t st, double* best_us);
+// grouped forms over T.count instances of one block size (blk0 is filled in):
+// SpMV y = A x or b - A x; first block-Jacobi iteration y = omega D^-1 b;
+// fused iteration y = x + omega D^-1 (b - A x)
+hipError_t launch_spmv_grouped(int bs, bool fp32, SegTable& T, hipStream_t st);
+hipError_t launch_bj_first_grouped(int bs, bool fp32, double omega, SegTable& T, hipStream_t st);
+hipError_t launch_bj_sweep_grouped(int bs, bool fp32, double omega, SegTable& T, hipStream_t st);
+// out[c] = sqrt(sum of the G[c] partials of column c), same order as launch_finish_norm
+hipError_t launch_finish_norms(int m, const NormPack& P, double* out, hipStream_t st);
+
 // ---------------------------------------------------------------- setup
 // (omg_setup.hip)
 int reduction_blocks(int64_t N);
 void basis_orders(int p, std::vector<int>& a, std::vector<int>& b, std::vector<int>& c);
 void embedding_blocks(int p, std::vector<double>& E);
 void reference_matrices(int p, double h, double penalty_c, std::vector<double>& out);
+
+// ---------------------------------------------------------------- engine
+// (omg_solve.hip), shared with the batched driver (omg_batch.hip)
+bool engine_use32(const omg_solver* s, int l, bool is_rm);
+bool engine_stop_level(const omg_solver* s, int l, double rn, double r0n, int it, double tol);
+// RM of Algorithm 1 with w = A z already in the level's w vector
+omg_status engine_rm_apply(omg_solver* s, int l, double* z, hipStream_t st);
+// a column solver for batched solves: shares the operator of `owner`
+omg_status engine_make_column(omg_solver* owner, omg_solver** out);
+omg_status engine_finish_report(omg_solver* s, const double* b, const double* x, omg_report* R);
+void engine_reset_logs(omg_solver* s);
 
 } // namespace omg
 

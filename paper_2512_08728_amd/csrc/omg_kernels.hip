@@ -57,16 +57,14 @@ __global__ void k_from_soa(const double* __restrict__ in, double* __restrict__ o
 }
 
 // ----------------------------------------------------------------- block SpMV
-// y = A x, or y = b - A x. Thread per cell; MT is the storage type of A and
-// the arithmetic type (FP32 mixed forms accumulate in float).
+// y = A x, or y = b - A x, for cell i. MT is the storage type of A and the
+// arithmetic type (FP32 mixed forms accumulate in float).
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_spmv(int n, int width, const int* __restrict__ col,
-                                                   const typename Pair<MT>::type* __restrict__ val,
-                                                   const double* __restrict__ x, const double* __restrict__ b,
-                                                   double* __restrict__ y) {
+__device__ __forceinline__ void spmv_cell(int i, int n, int width, const int* __restrict__ col,
+                                          const typename Pair<MT>::type* __restrict__ val,
+                                          const double* __restrict__ x, const double* __restrict__ b,
+                                          double* __restrict__ y) {
     constexpr int BSH = (BS + 1) / 2;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     MT acc[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) acc[r] = MT(0);
@@ -94,15 +92,23 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, int width, const int* 
     }
 }
 
+// Thread per cell.
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_spmv(int n, int width, const int* __restrict__ col,
+                                                   const typename Pair<MT>::type* __restrict__ val,
+                                                   const double* __restrict__ x, const double* __restrict__ b,
+                                                   double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    spmv_cell<BS, MT>(i, n, width, col, val, x, b, y);
+}
+
 // ----------------------------------------------------------------- block-Jacobi
 // First iteration from x0 = 0: x = omega D^-1 r.
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_bj_first(int n, const typename Pair<MT>::type* __restrict__ dinv,
-                                                       MT omega, const double* __restrict__ r,
-                                                       double* __restrict__ x) {
+__device__ __forceinline__ void bj_first_cell(int i, int n, const typename Pair<MT>::type* __restrict__ dinv,
+                                              MT omega, const double* __restrict__ r, double* __restrict__ x) {
     constexpr int BSH = (BS + 1) / 2;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     MT rv[2 * BSH];
 #pragma unroll
     for (int k = 0; k < BS; ++k) rv[k] = (MT)r[(int64_t)k * n + i];
@@ -120,16 +126,23 @@ __global__ __launch_bounds__(kThreads) void k_bj_first(int n, const typename Pai
     }
 }
 
-// Fused iteration k >= 2: xout = xin + omega D^-1 (r - A xin).
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_bj_sweep(int n, int width, const int* __restrict__ col,
-                                                       const typename Pair<MT>::type* __restrict__ val,
-                                                       const typename Pair<MT>::type* __restrict__ dinv,
+__global__ __launch_bounds__(kThreads) void k_bj_first(int n, const typename Pair<MT>::type* __restrict__ dinv,
                                                        MT omega, const double* __restrict__ r,
-                                                       const double* __restrict__ xin, double* __restrict__ xout) {
-    constexpr int BSH = (BS + 1) / 2;
+                                                       double* __restrict__ x) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    bj_first_cell<BS, MT>(i, n, dinv, omega, r, x);
+}
+
+// Fused iteration k >= 2: xout = xin + omega D^-1 (r - A xin).
+template <int BS, typename MT>
+__device__ __forceinline__ void bj_sweep_cell(int i, int n, int width, const int* __restrict__ col,
+                                              const typename Pair<MT>::type* __restrict__ val,
+                                              const typename Pair<MT>::type* __restrict__ dinv, MT omega,
+                                              const double* __restrict__ r, const double* __restrict__ xin,
+                                              double* __restrict__ xout) {
+    constexpr int BSH = (BS + 1) / 2;
     MT acc[BS];
 #pragma unroll
     for (int q = 0; q < BS; ++q) acc[q] = MT(0);
@@ -166,6 +179,54 @@ __global__ __launch_bounds__(kThreads) void k_bj_sweep(int n, int width, const i
         const int64_t o = (int64_t)rr * n + i;
         xout[o] = (double)((MT)xin[o] + omega * s);
     }
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_bj_sweep(int n, int width, const int* __restrict__ col,
+                                                       const typename Pair<MT>::type* __restrict__ val,
+                                                       const typename Pair<MT>::type* __restrict__ dinv,
+                                                       MT omega, const double* __restrict__ r,
+                                                       const double* __restrict__ xin, double* __restrict__ xout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bj_sweep_cell<BS, MT>(i, n, width, col, val, dinv, omega, r, xin, xout);
+}
+
+// ----------------------------------------------------------------- grouped
+// One launch over several independent operators (instances): segment q owns
+// blocks [blk0[q], blk0[q+1]), one thread per cell of its level, so each
+// instance gets a share of the grid proportional to its cells. The per-cell
+// arithmetic is the single-instance kernels' (same results bit for bit).
+__device__ __forceinline__ int segment_of(const SegTable& T, int block) {
+    int q = 0;
+    while (q + 1 < T.count && block >= T.blk0[q + 1]) ++q;
+    return q;
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_spmv_grouped(SegTable T) {
+    const int q = segment_of(T, blockIdx.x);
+    const int i = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
+    if (i >= T.n[q]) return;
+    spmv_cell<BS, MT>(i, T.n[q], T.width[q], T.col[q], (const typename Pair<MT>::type*)T.val[q], T.x[q], T.b[q],
+                      T.y[q]);
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_bj_first_grouped(SegTable T, MT omega) {
+    const int q = segment_of(T, blockIdx.x);
+    const int i = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
+    if (i >= T.n[q]) return;
+    bj_first_cell<BS, MT>(i, T.n[q], (const typename Pair<MT>::type*)T.dinv[q], omega, T.b[q], T.y[q]);
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_bj_sweep_grouped(SegTable T, MT omega) {
+    const int q = segment_of(T, blockIdx.x);
+    const int i = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
+    if (i >= T.n[q]) return;
+    bj_sweep_cell<BS, MT>(i, T.n[q], T.width[q], T.col[q], (const typename Pair<MT>::type*)T.val[q],
+                          (const typename Pair<MT>::type*)T.dinv[q], omega, T.b[q], T.x[q], T.y[q]);
 }
 
 // Row-split variants for small levels: one thread per (cell, block row), so
@@ -327,6 +388,83 @@ __global__ __launch_bounds__(kThreads) void k_gemv(int n, int np, const double* 
     if (lane == 0) y[row] = s;
 }
 
+// Symmetric form: only the lower-triangle 64x64 tiles of A are stored
+// (tile (I, J), I >= J, at index I(I+1)/2 + J, row-major, zero beyond n), so
+// each visit reads half the matrix. Tile (I, J) contributes A_IJ x_J to y_I
+// and, off the diagonal, A_IJ^T x_I to y_J; the contributions go to
+// part[I][J][.] and part[J][I][.] and are summed over J in a fixed order.
+constexpr int kSymT = 64;
+__global__ __launch_bounds__(kThreads) void k_symv_tiles(int n, const double* __restrict__ T,
+                                                         const double* __restrict__ x, double* __restrict__ part,
+                                                         int nt) {
+    __shared__ double xs[2][kSymT];
+    __shared__ double cs[kSymT][kSymT + 1];
+    // tile index -> (I, J), I >= J
+    const int t = blockIdx.x;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    if (threadIdx.x < kSymT) {
+        const int gi = J * kSymT + threadIdx.x;
+        xs[0][threadIdx.x] = gi < n ? x[gi] : 0.0;
+    } else if (threadIdx.x < 2 * kSymT) {
+        const int gi = I * kSymT + threadIdx.x - kSymT;
+        xs[1][threadIdx.x - kSymT] = gi < n ? x[gi] : 0.0;
+    }
+    __syncthreads();
+    const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 16;
+    const double2* rowp = (const double2*)(T + (size_t)t * kSymT * kSymT + (size_t)r * kSymT + c0);
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double2 v = rowp[q];
+        a[2 * q] = v.x;
+        a[2 * q + 1] = v.y;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s = fma(a[q], xs[0][c0 + q], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if ((threadIdx.x & 3) == 0) part[((size_t)I * nt + J) * kSymT + r] = s;
+    if (I == J) return; // uniform per block
+    const double xr = xs[1][r];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cs[c0 + q][r] = a[q] * xr;
+    __syncthreads();
+    if (threadIdx.x < kSymT) {
+        double u = 0.0;
+        for (int rr = 0; rr < kSymT; ++rr) u += cs[threadIdx.x][rr];
+        part[((size_t)J * nt + I) * kSymT + threadIdx.x] = u;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_symv_reduce(int n, int nt, const double* __restrict__ part,
+                                                          double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int I = i / kSymT, il = i % kSymT;
+    double s = 0.0;
+    for (int J = 0; J < nt; ++J) s += part[((size_t)I * nt + J) * kSymT + il];
+    y[i] = s;
+}
+
+// Pack the lower-triangle tiles of the dense A (row-major, leading dim np).
+__global__ void k_symv_pack(int n, int np, int nt, const double* __restrict__ A, double* __restrict__ T) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntiles = (int64_t)nt * (nt + 1) / 2;
+    if (e >= ntiles * kSymT * kSymT) return;
+    const int64_t t = e / (kSymT * kSymT);
+    const int rc = (int)(e % (kSymT * kSymT)), r = rc / kSymT, c = rc % kSymT;
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+    while ((int64_t)I * (I + 1) / 2 > t) --I;
+    const int J = (int)(t - (int64_t)I * (I + 1) / 2);
+    const int gr = I * kSymT + r, gc = J * kSymT + c;
+    T[e] = (gr < n && gc < n) ? A[(size_t)gr * np + gc] : 0.0;
+}
+
 // ----------------------------------------------------------------- RM / MGS
 // part_ab[block] = sum a.b over the block's elements; part_cc likewise for c.c
 __global__ __launch_bounds__(kThreads) void k_dot2(int64_t N, const double* __restrict__ a,
@@ -424,6 +562,33 @@ __global__ void k_finish_norm(int G, const double* __restrict__ part, double* __
     __shared__ double sh[kThreads / 64];
     const double s = sum_partials(part, G, sh);
     if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+// Level entry of Algorithm 2 with x0 = 0: x = 0, r = b, and the partials of
+// ||r||^2 (same grid-stride order and block sums as k_dot2, so the norm is
+// the same bit for bit).
+__global__ __launch_bounds__(kThreads) void k_level_init(int64_t N, const double* __restrict__ b,
+                                                         double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ part) {
+    __shared__ double sh[kThreads / 64];
+    double s2 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double v = b[e];
+        x[e] = 0.0;
+        r[e] = v;
+        s2 = fma(v, v, s2);
+    }
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s2;
+}
+
+// one block per column: the same partial order as k_finish_norm
+__global__ void k_finish_norms(NormPack P, double* __restrict__ out) {
+    __shared__ double sh[kThreads / 64];
+    const int c = blockIdx.x;
+    const double s = sum_partials(P.part[c], P.G[c], sh);
+    if (threadIdx.x == 0) out[c] = sqrt(s);
 }
 
 __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t N) {
@@ -546,6 +711,56 @@ hipError_t launch_bj_sweep(const Level& L, int bs, bool fp32, double omega, cons
     return hipGetLastError();
 }
 
+static int fill_segments(SegTable& T) {
+    int b = 0;
+    for (int q = 0; q < T.count; ++q) {
+        T.blk0[q] = b;
+        b += cdiv(T.n[q], kThreads);
+    }
+    T.blk0[T.count] = b;
+    return b;
+}
+
+hipError_t launch_spmv_grouped(int bs, bool fp32, SegTable& T, hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxSeg) return hipErrorInvalidValue;
+    const int nb = fill_segments(T);
+    if (nb == 0) return hipSuccess;
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv_grouped<BSV, float>), dim3(nb), dim3(kThreads), 0, st, T));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_spmv_grouped<BSV, double>), dim3(nb), dim3(kThreads), 0, st, T));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_first_grouped(int bs, bool fp32, double omega, SegTable& T, hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxSeg) return hipErrorInvalidValue;
+    const int nb = fill_segments(T);
+    if (nb == 0) return hipSuccess;
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first_grouped<BSV, float>), dim3(nb), dim3(kThreads), 0, st, T,
+                                               (float)omega));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_first_grouped<BSV, double>), dim3(nb), dim3(kThreads), 0, st,
+                                               T, omega));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_sweep_grouped(int bs, bool fp32, double omega, SegTable& T, hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxSeg) return hipErrorInvalidValue;
+    const int nb = fill_segments(T);
+    if (nb == 0) return hipSuccess;
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep_grouped<BSV, float>), dim3(nb), dim3(kThreads), 0, st, T,
+                                               (float)omega));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_bj_sweep_grouped<BSV, double>), dim3(nb), dim3(kThreads), 0, st,
+                                               T, omega));
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
                            const double* r, double* rc, hipStream_t st) {
     dim3 grid(cdiv(C.n, kThreads)), block(kThreads);
@@ -574,7 +789,29 @@ hipError_t launch_prolong(const Level& F, const Level& C, int bs, bool fp32, con
 
 hipError_t launch_gemv(const Level& L, const double* x, double* y, hipStream_t st) {
     const int n = (int)L.N;
+    if (L.atile) {
+        const int nt = L.ntile;
+        hipLaunchKernelGGL(k_symv_tiles, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kThreads), 0, st, n, L.atile, x,
+                           L.spart, nt);
+        hipLaunchKernelGGL(k_symv_reduce, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, n, nt, L.spart, y);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, st, n, L.np, L.ainv, x, y);
+    return hipGetLastError();
+}
+
+hipError_t build_symv_tiles(Level& L, hipStream_t st) {
+    if (L.atile || !L.ainv) return hipSuccess;
+    const int n = (int)L.N;
+    const int nt = (n + kSymT - 1) / kSymT;
+    const int64_t ntiles = (int64_t)nt * (nt + 1) / 2;
+    hipError_t e;
+    if ((e = hipMalloc((void**)&L.atile, sizeof(double) * ntiles * kSymT * kSymT)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&L.spart, sizeof(double) * (size_t)nt * nt * kSymT)) != hipSuccess) return e;
+    L.ntile = nt;
+    const int64_t tot = ntiles * kSymT * kSymT;
+    hipLaunchKernelGGL(k_symv_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, L.np, nt, L.ainv,
+                       L.atile);
     return hipGetLastError();
 }
 
@@ -606,6 +843,18 @@ hipError_t launch_rm_update(int64_t N, int G, const double* part_alpha, const do
 
 hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kThreads), 0, st, G, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_init(int64_t N, int G, const double* b, double* x, double* r, double* part,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_level_init, dim3(G), dim3(kThreads), 0, st, N, b, x, r, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_norms(int m, const NormPack& P, double* out, hipStream_t st) {
+    if (m < 1 || m > kMaxCols) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_finish_norms, dim3(m), dim3(kThreads), 0, st, P, out);
     return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@
 // The grid is sized from the occupancy query so that every block is resident
 // at once; the launch is an ordinary one (cooperative launches carry a large
 // per-launch cost on this runtime).
+#include <cstdlib>
+
 #include "omg_internal.h"
 
 namespace omg {
@@ -54,6 +56,33 @@ __device__ __forceinline__ double wsum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+// Block sums of nv values at once (one pair of barriers for all of them);
+// per value the order is that of bsum. sh holds kMaxVals * (kThreads/64).
+constexpr int kMaxVals = kRmBlock + 1;
+template <int NV>
+__device__ __forceinline__ void bsum_n(double (&v)[NV], int nv, double* sh) {
+    constexpr int NW = kThreads / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+        if (i < nv) v[i] = wsum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) sh[i * NW + wid] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < nv) {
+            double s = 0.0;
+            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sh[i * NW + q];
+            v[i] = s;
+        }
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ double bsum(double v, double* sh) {
     v = wsum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -112,67 +141,65 @@ __device__ __forceinline__ void collect(unsigned long long* slots, int G, unsign
             }
         }
     }
+    bsum_n<SW>(v, nw, sh);
 #pragma unroll
     for (int w = 0; w < SW; ++w)
-        if (w < nw) out[w] = bsum(v[w], sh);
+        if (w < nw) out[w] = v[w];
 }
 
-template <int BS, int CPT, int B>
+// Every vector is handled as a flat array of N entries (RM has no cell
+// structure): thread t of a grid of T threads owns entries t + j T, j < EPT,
+// so consecutive threads touch consecutive addresses.
+template <int EPT, int B>
 __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
     constexpr int SW = B + 1;
-    __shared__ double sh[kThreads / 64];
+    __shared__ double sh[kMaxVals * (kThreads / 64)];
     const int G = gridDim.x;
-    const int T = G * blockDim.x;
-    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = A.n, k = A.k;
-    double w[CPT][BS], a[B][CPT][BS], an[B][CPT][BS];
-    bool valid[CPT];
+    const int64_t T = (int64_t)G * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = A.N;
+    const int k = A.k;
+    double w[EPT], a[B][EPT], an[B][EPT];
+    bool valid[EPT];
     // w in registers; the raw direction z~ is stored as direction k
     double* Zk = A.Zk;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int c = t0 + j * T;
-        valid[j] = c < n;
-#pragma unroll
-        for (int q = 0; q < BS; ++q) {
-            const int64_t e = (int64_t)q * n + c;
-            w[j][q] = valid[j] ? A.w[e] : 0.0;
-            if (valid[j]) Zk[e] = A.z[e];
-        }
+    for (int j = 0; j < EPT; ++j) {
+        const int64_t e = t0 + j * T;
+        valid[j] = e < N;
+        w[j] = valid[j] ? A.w[e] : 0.0;
+        if (valid[j]) Zk[e] = A.z[e];
     }
-    auto load_block = [&](double (&dst)[B][CPT][BS], int j0) {
+    auto load_block = [&](double (&dst)[B][EPT], int j0) {
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             const bool have = j0 + t < k;
             const double* Wt = have ? A.Wp[j0 + t] : nullptr;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-#pragma unroll
-                for (int q = 0; q < BS; ++q)
-                    dst[t][j][q] = (have && valid[j]) ? Wt[(int64_t)q * n + t0 + j * T] : 0.0;
+            for (int j = 0; j < EPT; ++j) dst[t][j] = (have && valid[j]) ? Wt[t0 + j * T] : 0.0;
         }
     };
     const int nblk = (k + B - 1) / B;
     unsigned long long g = A.g0;
     double vals[SW];
-    // phase g0: dots of the first block and ||w||^2
+    // phase g0: dots of the first block and ||w||^2; the next block is loaded
+    // meanwhile. Block b+2 is requested as soon as block b+1 becomes current,
+    // so loads stay in flight through every reduction, publish and wait.
     load_block(a, 0);
+    if (nblk > 1) load_block(an, B);
     {
         double s_in = 0.0;
 #pragma unroll
-        for (int j = 0; j < CPT; ++j)
-#pragma unroll
-            for (int q = 0; q < BS; ++q) s_in = fma(w[j][q], w[j][q], s_in);
-        vals[B] = bsum(s_in, sh);
+        for (int j = 0; j < EPT; ++j) s_in = fma(w[j], w[j], s_in);
+        vals[B] = s_in;
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-#pragma unroll
-                for (int q = 0; q < BS; ++q) s = fma(a[t][j][q], w[j][q], s);
-            vals[t] = bsum(s, sh);
+            for (int j = 0; j < EPT; ++j) s = fma(a[t][j], w[j], s);
+            vals[t] = s;
         }
+        bsum_n<SW>(vals, SW, sh);
         publish<SW>(A.slots, G, g, vals, SW);
     }
     double nin2 = 0.0, nout2 = 0.0;
@@ -180,7 +207,6 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
     for (int b = 0; b < nblk; ++b) {
         const int j0 = b * B;
         const int bb = min(B, k - j0);
-        if (b + 1 < nblk) load_block(an, j0 + B); // in flight while waiting
         collect<SW>(A.slots, G, g, (b == 0) ? SW : bb, tot, sh, A.abort_flag);
         if (b == 0) nin2 = tot[B];
         double beta[B];
@@ -198,31 +224,29 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
 #pragma unroll
         for (int t = 0; t < B; ++t)
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-#pragma unroll
-                for (int q = 0; q < BS; ++q) w[j][q] = fma(-beta[t], a[t][j][q], w[j][q]);
+            for (int j = 0; j < EPT; ++j) w[j] = fma(-beta[t], a[t][j], w[j]);
         ++g;
         if (b + 1 < nblk) {
+#pragma unroll
+            for (int t = 0; t < B; ++t)
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) a[t][j] = an[t][j];
+            if (b + 2 < nblk) load_block(an, j0 + 2 * B);
 #pragma unroll
             for (int t = 0; t < B; ++t) {
                 double s = 0.0;
 #pragma unroll
-                for (int j = 0; j < CPT; ++j)
-#pragma unroll
-                    for (int q = 0; q < BS; ++q) {
-                        a[t][j][q] = an[t][j][q];
-                        s = fma(a[t][j][q], w[j][q], s);
-                    }
-                vals[t] = bsum(s, sh);
+                for (int j = 0; j < EPT; ++j) s = fma(a[t][j], w[j], s);
+                vals[t] = s;
             }
+            bsum_n<SW>(vals, B, sh);
             publish<SW>(A.slots, G, g, vals, B);
         } else {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-#pragma unroll
-                for (int q = 0; q < BS; ++q) s = fma(w[j][q], w[j][q], s);
-            vals[0] = bsum(s, sh);
+            for (int j = 0; j < EPT; ++j) s = fma(w[j], w[j], s);
+            vals[0] = s;
+            bsum_n<SW>(vals, 1, sh);
             publish<SW>(A.slots, G, g, vals, 1);
             collect<SW>(A.slots, G, g, 1, tot, sh, A.abort_flag);
             nout2 = tot[0];
@@ -243,37 +267,34 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
 #pragma unroll
     for (int t = 0; t < B; ++t) s_g[t] = 0.0;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
-#pragma unroll
-        for (int q = 0; q < BS; ++q) {
-            w[j][q] *= gamma;
-            double rv = 0.0;
-            if (valid[j]) {
-                const int64_t e = (int64_t)q * n + t0 + j * T;
-                A.Wk[e] = w[j][q];
-                rv = A.r[e];
-            }
-            an[0][j][q] = rv; // r kept in registers
-            s_a = fma(w[j][q], rv, s_a);
-#pragma unroll
-            for (int t = 0; t < B; ++t) s_g[t] = fma(a[t][j][q], w[j][q], s_g[t]);
+    for (int j = 0; j < EPT; ++j) {
+        w[j] *= gamma;
+        double rv = 0.0;
+        if (valid[j]) {
+            const int64_t e = t0 + j * T;
+            A.Wk[e] = w[j];
+            rv = A.r[e];
         }
-    ++g;
-    vals[0] = bsum(s_a, sh);
+        an[0][j] = rv; // r kept in registers
+        s_a = fma(w[j], rv, s_a);
 #pragma unroll
-    for (int t = 0; t < B - 1; ++t) vals[1 + t] = bsum(s_g[t], sh);
+        for (int t = 0; t < B; ++t) s_g[t] = fma(a[t][j], w[j], s_g[t]);
+    }
+    ++g;
+    vals[0] = s_a;
+#pragma unroll
+    for (int t = 0; t < B - 1; ++t) vals[1 + t] = s_g[t];
+    bsum_n<SW>(vals, B, sh);
     publish<SW>(A.slots, G, g, vals, B);
     collect<SW>(A.slots, G, g, B, tot, sh, A.abort_flag);
     const double alpha = tot[0];
     double s_r = 0.0;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
-#pragma unroll
-        for (int q = 0; q < BS; ++q) {
-            const double rn = fma(-alpha, w[j][q], an[0][j][q]);
-            if (valid[j]) A.r[(int64_t)q * n + t0 + j * T] = rn;
-            s_r = fma(rn, rn, s_r);
-        }
+    for (int j = 0; j < EPT; ++j) {
+        const double rn = fma(-alpha, w[j], an[0][j]);
+        if (valid[j]) A.r[t0 + j * T] = rn;
+        s_r = fma(rn, rn, s_r);
+    }
     s_r = bsum(s_r, sh);
     if (threadIdx.x == 0) {
         A.part_rn[blockIdx.x] = s_r;
@@ -322,66 +343,69 @@ __global__ void k_zero(double* __restrict__ out, int64_t N) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) out[e] = 0.0;
 }
 
-template <int BS, int CPT, int B>
+template <int EPT, int B>
 static const void* rm_kernel() {
-    return reinterpret_cast<const void*>(&k_rm_blk<BS, CPT, B>);
+    return reinterpret_cast<const void*>(&k_rm_blk<EPT, B>);
 }
 
-// Instantiations: cells per thread CPT with CPT*BS <= 40, and B in {1, 2, 4}.
-template <int BS, int CPT>
+// Instantiations: entries per thread EPT, MGS block B in {1, 2, 4}.
+constexpr int kEpts[] = {1, 2, 4, 8, 10, 16, 20};
+template <int EPT>
 static const void* pick_b(int b) {
-    if (b == 4) return rm_kernel<BS, CPT, 4>();
-    if (b == 2) return rm_kernel<BS, CPT, 2>();
-    if (b == 1) return rm_kernel<BS, CPT, 1>();
+    if (b == 4) return rm_kernel<EPT, 4>();
+    if (b == 2) return rm_kernel<EPT, 2>();
+    if (b == 1) return rm_kernel<EPT, 1>();
     return nullptr;
 }
-template <int BS>
-static const void* pick_bs(int cpt, int b) {
-    if (cpt == 1) return pick_b<BS, 1>(b);
-    if constexpr (BS * 2 <= 40) if (cpt == 2) return pick_b<BS, 2>(b);
-    if constexpr (BS * 4 <= 40) if (cpt == 4) return pick_b<BS, 4>(b);
-    if constexpr (BS * 8 <= 40) if (cpt == 8) return pick_b<BS, 8>(b);
-    return nullptr;
-}
-static const void* pick(int bs, int cpt, int b) {
-    switch (bs) {
-    case 1: return pick_bs<1>(cpt, b);
-    case 4: return pick_bs<4>(cpt, b);
-    case 10: return pick_bs<10>(cpt, b);
-    case 20: return pick_bs<20>(cpt, b);
+static const void* pick(int ept, int b) {
+    switch (ept) {
+    case 1: return pick_b<1>(b);
+    case 2: return pick_b<2>(b);
+    case 4: return pick_b<4>(b);
+    case 8: return pick_b<8>(b);
+    case 10: return pick_b<10>(b);
+    case 16: return pick_b<16>(b);
+    case 20: return pick_b<20>(b);
     }
     return nullptr;
 }
 
-// Grid for a level: the smallest cells-per-thread, then the largest MGS block,
-// whose grid is co-resident (occupancy query) with at most 512 blocks (every
-// block reads every block's words per exchange).
-bool rm_persistent_config(int n, int bs, int* G, int* cpt, int* B) {
+// Co-resident launch configurations for a level of N entries: grids of at
+// most kMaxRedBlocks blocks whose blocks all fit at once (occupancy query),
+// in order of preference (fewest entries per thread, then the largest MGS
+// block, then at most 512 blocks before larger grids).
+int rm_persistent_candidates(int64_t N, RmConfig* out, int cap) {
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-    for (int c : {1, 2, 4, 8}) {
-        const int64_t need = ((int64_t)n + (int64_t)kThreads * c - 1) / ((int64_t)kThreads * c);
-        if (need > 512) continue;
-        for (int b : {4, 2, 1}) {
-            const void* f = pick(bs, c, b);
-            if (!f) continue;
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess || per_cu < 1)
-                continue;
-            if (need <= (int64_t)per_cu * cus) {
-                *G = (int)need;
-                *cpt = c;
-                *B = b;
-                return true;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    int n = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int e : kEpts) {
+            const int64_t need = (N + (int64_t)kThreads * e - 1) / ((int64_t)kThreads * e);
+            if (pass == 0 ? need > 512 : (need <= 512 || need > kMaxRedBlocks)) continue;
+            for (int b : {4, 2, 1}) {
+                const void* f = pick(e, b);
+                int per_cu = 0;
+                if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess ||
+                    per_cu < 1 || need > (int64_t)per_cu * cus)
+                    continue;
+                if (n < cap) out[n++] = RmConfig{(int)need, e, b};
             }
         }
-    }
-    return false;
+    return n;
 }
 
-hipError_t launch_rm_persistent(int bs, int G, int cpt, int B, const RmArgs& args, hipStream_t st) {
-    const void* f = pick(bs, cpt, B);
+bool rm_persistent_config(int64_t N, int* G, int* ept, int* B) {
+    RmConfig c[64];
+    if (rm_persistent_candidates(N, c, 64) < 1) return false;
+    *G = c[0].G;
+    *ept = c[0].ept;
+    *B = c[0].B;
+    return true;
+}
+
+hipError_t launch_rm_persistent(int G, int ept, int B, const RmArgs& args, hipStream_t st) {
+    const void* f = pick(ept, B);
     if (!f) return hipErrorInvalidValue;
     RmArgs a = args;
     void* params[] = {&a};

@@ -11,6 +11,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <cstdlib>
+
 #include "omg_internal.h"
 
 namespace omg {
@@ -826,6 +828,7 @@ omg_status omg_coarse_factor(omg_solver* s, Level& L) {
         for (int i = 1; i < nt; ++i) hipLaunchKernelGGL(k_trinv_row, dim3(i), dim3(256), 0, q, D, X, np, i, linv);
         hipLaunchKernelGGL(k_xtx, dim3((unsigned)nt * nt), dim3(256), 0, q, X, L.ainv, np, nt);
         if (hipGetLastError() != hipSuccess) st = OMG_EHIP;
+        if (st == OMG_OK && !std::getenv("OMG_NO_SYMV") && build_symv_tiles(L, q) != hipSuccess) st = OMG_EHIP;
         int err = 0;
         if (hipMemcpyAsync(&err, s->err_flag, sizeof(int), hipMemcpyDeviceToHost, q) != hipSuccess) st = OMG_EHIP;
         if (hipStreamSynchronize(q) != hipSuccess) st = OMG_EHIP;

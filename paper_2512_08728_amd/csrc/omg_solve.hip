@@ -83,13 +83,20 @@ extern "C" const char* omg_strerror(omg_status st) {
 
 // ------------------------------------------------------------------ teardown
 static void free_level(Level& L) {
-    hipFree(L.col);
-    hipFree(L.val);
-    hipFree(L.val32);
-    hipFree(L.dinv);
-    hipFree(L.dinv32);
-    hipFree(L.ainv);
-    hipFree(L.dslot);
+    if (!L.shared_op) {
+        hipFree(L.col);
+        hipFree(L.val);
+        hipFree(L.val32);
+        hipFree(L.dinv);
+        hipFree(L.dinv32);
+        hipFree(L.ainv);
+        hipFree(L.atile);
+        hipFree(L.dslot);
+        hipFree(L.ablk);
+        hipFree(L.ablk32);
+        hipFree(L.dblk);
+        hipFree(L.dblk32);
+    }
     hipFree(L.b);
     hipFree(L.r);
     hipFree(L.x);
@@ -101,6 +108,7 @@ static void free_level(Level& L) {
     hipFree(L.xout);
     hipFree(L.part);
     hipFree(L.scal);
+    hipFree(L.spart);
     for (double* c : L.chunks) hipFree(c);
     hipFree(L.dWp);
     hipFree(L.dZp);
@@ -117,6 +125,13 @@ static void free_level(Level& L) {
 extern "C" void omg_destroy(omg_solver* s) {
     if (!s) return;
     if (s->stream) hipStreamSynchronize(s->stream);
+    for (omg_solver* c : s->columns) omg_destroy(c);
+    s->columns.clear();
+    if (s->bnorm_host) hipHostFree(s->bnorm_host);
+    if (s->owner) { // column solver: E, E32 belong to the owner
+        s->E = nullptr;
+        s->E32 = nullptr;
+    }
     if (s->cstream) {
         hipStreamSynchronize(s->cstream);
         hipStreamDestroy(s->cstream);
@@ -136,6 +151,18 @@ extern "C" void omg_destroy(omg_solver* s) {
 }
 
 // ------------------------------------------------------------------ setup
+// Small host-visible scalars the kernels write directly (mapped, coherent).
+static omg_status alloc_host_scalars(omg_solver* s) {
+    const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void**)&s->host_scal, sizeof(double) * 4 * OMG_MAX_LEVELS, fl) != hipSuccess ||
+        hipHostMalloc((void**)&s->bnorm_host, sizeof(double) * kMaxCols, fl) != hipSuccess)
+        return OMG_ENOMEM;
+    if (hipHostGetDevicePointer((void**)&s->host_scal_dev, s->host_scal, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&s->bnorm_dev, s->bnorm_host, 0) != hipSuccess)
+        return OMG_EHIP;
+    return OMG_OK;
+}
+
 static omg_status check_grid(const omg_grid* g) {
     if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1 || g->p < 0 || g->p > 3 || g->n_levels < 1 ||
         g->n_levels > OMG_MAX_LEVELS)
@@ -176,7 +203,7 @@ static omg_status create(const omg_grid* g, const omg_options* opt, void* stream
     }
     *out = s;
     if (hipMalloc((void**)&s->err_flag, sizeof(int)) != hipSuccess) return OMG_ENOMEM;
-    if (hipHostMalloc((void**)&s->host_scal, sizeof(double) * 4 * OMG_MAX_LEVELS) != hipSuccess) return OMG_ENOMEM;
+    OMG_TRY(alloc_host_scalars(s));
     std::vector<double> E;
     embedding_blocks(s->p, E);
     s->hE = E;
@@ -191,6 +218,101 @@ static omg_status create(const omg_grid* g, const omg_options* opt, void* stream
     HIP_OK(hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    return OMG_OK;
+}
+
+// Storage of the persistent RM kernel on one level: exchange words, abort
+// flag, MGS coefficient history (sized for the level's iteration cap).
+static omg_status alloc_rm_state(omg_solver* s, Level& L, int l) {
+    const int per_it = std::max(3, s->opt.n_s + 1);
+    const int its = (l == 0) ? s->opt.max_iter : s->opt.crit_max[l - 1];
+    L.ucap = per_it * std::max(its, 1) + 4;
+    if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipMemset(L.bar, 0, 2 * sizeof(unsigned)));
+    const size_t xs = sizeof(unsigned long long) * 2 * kMaxRedBlocks * (kRmBlock + 1);
+    if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
+    L.phase = 0;
+    const size_t uc = (size_t)L.ucap;
+    if (hipMalloc((void**)&L.hist, sizeof(double) * (uc * (uc - 1) / 2 + 1)) != hipSuccess ||
+        hipMalloc((void**)&L.alphas, sizeof(double) * uc) != hipSuccess ||
+        hipMalloc((void**)&L.gammas, sizeof(double) * uc) != hipSuccess ||
+        hipMalloc((void**)&L.dvec, sizeof(double) * uc) != hipSuccess ||
+        hipMalloc((void**)&L.gram, sizeof(double) * uc * kGramStride) != hipSuccess)
+        return OMG_ENOMEM;
+    HIP_OK(hipMemset(L.gram, 0, sizeof(double) * uc * kGramStride));
+    return OMG_OK;
+}
+
+static omg_status ensure_dir(omg_solver* s, Level& L, int k);
+
+// Launch configuration of the persistent RM kernel on level l: time every
+// co-resident configuration (entries per thread, MGS block, grid) with kt
+// stored directions (zero data: the traffic and exchanges do not depend on
+// the values) and keep the fastest. The directions' storage is the level's
+// own; the solve overwrites everything these launches write.
+static omg_status tune_rm(omg_solver* s, int l) {
+    Level& L = s->lev[l];
+    RmConfig c[64];
+    const int nc = rm_persistent_candidates(L.N, c, 64);
+    if (nc <= 1 || std::getenv("OMG_RM_NOTUNE")) return OMG_OK;
+    const int kt = std::min(L.ucap - 1, 40);
+    OMG_TRY(ensure_dir(s, L, kt));
+    hipStream_t st = s->stream;
+    for (int i = 0; i <= kt; ++i) HIP_OK(launch_fill(L.W[i], 0.0, L.N, st));
+    HIP_OK(launch_fill(L.w, 0.0, L.N, st));
+    HIP_OK(launch_fill(L.z, 0.0, L.N, st));
+    HIP_OK(launch_fill(L.r, 0.0, L.N, st));
+    RmArgs a;
+    a.N = L.N;
+    a.k = kt;
+    a.Wp = L.dWp;
+    a.Wk = L.W[kt];
+    a.Zk = L.Z[kt];
+    a.w = L.w;
+    a.z = L.z;
+    a.r = L.r;
+    a.slots = L.xslots;
+    a.part_rn = L.part + 4 * kMaxRedBlocks;
+    a.breakdown = s->opt.breakdown;
+    a.scal = L.scal;
+    a.abort_flag = L.bar + 1;
+    a.hist = L.hist;
+    a.gammas = L.gammas;
+    a.alphas = L.alphas;
+    a.gram = L.gram;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bi = 0;
+    omg_status res = OMG_OK;
+    for (int q = 0; q < nc && res == OMG_OK; ++q) {
+        const int reps = 3;
+        for (int r = 0; r <= reps && res == OMG_OK; ++r) {
+            if (r == 1 && hipEventRecord(e0, st) != hipSuccess) res = OMG_EHIP;
+            a.g0 = L.phase;
+            if (res == OMG_OK && launch_rm_persistent(c[q].G, c[q].ept, c[q].B, a, st) != hipSuccess) res = OMG_EHIP;
+            L.phase += (unsigned long long)((kt + c[q].B - 1) / c[q].B) + 2;
+        }
+        float ms = 0.f;
+        if (res == OMG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            res = OMG_EHIP;
+        if (res == OMG_OK && ms < best) {
+            best = ms;
+            bi = q;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    OMG_TRY(res);
+    unsigned flags[2] = {0, 0};
+    HIP_OK(hipMemcpy(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags[1]) return OMG_EHIP; // a bounded wait expired
+    L.Gp = c[bi].G;
+    L.ept = c[bi].ept;
+    L.rmB = c[bi].B;
     return OMG_OK;
 }
 
@@ -210,24 +332,10 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
             // variant the coarse levels (second stream) keep the per-step kernels
             const bool eligible = !std::getenv("OMG_NO_PERSISTENT_RM") &&
                                   !(s->opt.variant == OMG_OVERLAP_DET && l > 0);
-            if (eligible) L.persist = rm_persistent_config(L.n, s->bs, &L.Gp, &L.cpt, &L.rmB);
+            if (eligible) L.persist = rm_persistent_config(L.N, &L.Gp, &L.ept, &L.rmB);
             if (L.persist) {
-                const int per_it = std::max(3, s->opt.n_s + 1);
-                const int its = (l == 0) ? s->opt.max_iter : s->opt.crit_max[l - 1];
-                L.ucap = per_it * std::max(its, 1) + 4;
-                if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
-                HIP_OK(hipMemset(L.bar, 0, 2 * sizeof(unsigned)));
-                const size_t xs = sizeof(unsigned long long) * 2 * kMaxRedBlocks * (kRmBlock + 1);
-                if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
-                HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
-                const size_t uc = (size_t)L.ucap;
-                if (hipMalloc((void**)&L.hist, sizeof(double) * (uc * (uc - 1) / 2 + 1)) != hipSuccess ||
-                    hipMalloc((void**)&L.alphas, sizeof(double) * uc) != hipSuccess ||
-                    hipMalloc((void**)&L.gammas, sizeof(double) * uc) != hipSuccess ||
-                    hipMalloc((void**)&L.dvec, sizeof(double) * uc) != hipSuccess ||
-                    hipMalloc((void**)&L.gram, sizeof(double) * uc * kGramStride) != hipSuccess)
-                    return OMG_ENOMEM;
-                HIP_OK(hipMemset(L.gram, 0, sizeof(double) * uc * kGramStride));
+                OMG_TRY(alloc_rm_state(s, L, l));
+                OMG_TRY(tune_rm(s, l));
             }
         } else {
             OMG_TRY(omg_coarse_factor(s, L));
@@ -381,8 +489,20 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
 // Residual minimisation (Algorithm 1) on level l with the direction z
 // (overwritten): w = A z, MGS against W with the same coefficients on z,
 // normalise, append, alpha = w.r, x += alpha z, r -= alpha w. Leaves the
-// partials of ||r||^2 in part slot 4.
+// partials of ||r||^2 in part slot 4 (L.Grn of them).
+static omg_status rm_apply(omg_solver* s, int l, double* z, hipStream_t st);
 static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
+    Level& L = s->lev[l];
+    const int kspmv = use32(s, l, true) ? OMG_K_SPMV32 : OMG_K_SPMV;
+    probe_begin(s, kspmv, l, st);
+    HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
+    probe_end(s, kspmv, l, st, alg_bytes(s, kspmv, l, 0));
+    s->kcount[kspmv][l]++;
+    return rm_apply(s, l, z, st);
+}
+
+// The part of RM after w = A z (w in L.w).
+static omg_status rm_apply(omg_solver* s, int l, double* z, hipStream_t st) {
     Level& L = s->lev[l];
     const int G = L.G;
     const int64_t N = L.N;
@@ -392,15 +512,10 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
     double* P_b = L.part + 2 * kMaxRedBlocks;
     double* P_alpha = L.part + 3 * kMaxRedBlocks;
     double* P_rn = L.part + 4 * kMaxRedBlocks;
-    const int kspmv = use32(s, l, true) ? OMG_K_SPMV32 : OMG_K_SPMV;
-    probe_begin(s, kspmv, l, st);
-    HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
-    probe_end(s, kspmv, l, st, alg_bytes(s, kspmv, l, 0));
-    s->kcount[kspmv][l]++;
     if (L.persist) {
         if (L.k + 1 > L.ucap) return OMG_ENOMEM;
         RmArgs a;
-        a.n = L.n;
+        a.N = L.N;
         a.k = L.k;
         a.Wp = L.dWp;
         a.Wk = L.W[L.k];
@@ -419,7 +534,7 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
         a.alphas = L.alphas;
         a.gram = L.gram;
         probe_begin(s, OMG_K_RMP, l, st);
-        HIP_OK(launch_rm_persistent(s->bs, L.Gp, L.cpt, L.rmB, a, st));
+        HIP_OK(launch_rm_persistent(L.Gp, L.ept, L.rmB, a, st));
         probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
         L.phase += (unsigned long long)((L.k + L.rmB - 1) / L.rmB) + 2;
         s->kcount[OMG_K_RMP][l]++;
@@ -453,10 +568,11 @@ static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
 }
 
 // Read ||r|| of level l (from the partials of the last update) to the host.
+// The finishing kernel writes straight into mapped, coherent pinned host
+// memory, so the read costs one kernel and one wait (no copy command).
 static omg_status read_rnorm(omg_solver* s, int l, hipStream_t st, double* out) {
     Level& L = s->lev[l];
-    HIP_OK(launch_finish_norm(L.Grn, L.part + 4 * kMaxRedBlocks, L.scal + S_RNORM, st));
-    HIP_OK(hipMemcpyAsync(s->host_scal + l, L.scal + S_RNORM, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(launch_finish_norm(L.Grn, L.part + 4 * kMaxRedBlocks, s->host_scal_dev + l, st));
     HIP_OK(hipStreamSynchronize(st));
     *out = s->host_scal[l];
     return OMG_OK;
@@ -544,10 +660,10 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     }
     Level& C = s->lev[l + 1];
     L.k = 0;
-    HIP_OK(launch_fill(L.x, 0.0, L.N, st));
-    HIP_OK(launch_copy(L.r, b, L.N, st));
+    HIP_OK(launch_level_init(L.N, L.G, b, L.x, L.r, L.part + 4 * kMaxRedBlocks, st));
+    L.Grn = L.G;
     double r0n;
-    OMG_TRY(vec_norm(s, l, L.r, st, &r0n));
+    OMG_TRY(read_rnorm(s, l, st, &r0n));
     const double bn = r0n;
     if (l == 0) log_trace(s, r0n, 0);
     int replay_count = -1;
@@ -761,55 +877,82 @@ extern "C" omg_status omg_solve(omg_solver* s, const double* b, double* x, doubl
     return status;
 }
 
-// Batched solve: each column of each instance is solved as by omg_solve
-// (columns gathered into the solver's internal layout one at a time).
-__global__ void k_gather_col(const double* __restrict__ in, double* __restrict__ out, int n, int bs, int nrhs,
-                             int col) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * bs) return;
-    const int c = (int)(e / bs), k = (int)(e % bs);
-    out[(int64_t)k * n + c] = in[e * nrhs + col];
+// ------------------------------------------------------------------ engine
+// entry points shared with the batched driver
+namespace omg {
+bool engine_use32(const omg_solver* s, int l, bool is_rm) { return use32(s, l, is_rm); }
+bool engine_stop_level(const omg_solver* s, int l, double rn, double r0n, int it, double tol) {
+    return stop_level(s, l, rn, r0n, r0n, it, tol, -1);
 }
-__global__ void k_scatter_col(const double* __restrict__ in, double* __restrict__ out, int n, int bs, int nrhs,
-                              int col) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * bs) return;
-    const int c = (int)(e / bs), k = (int)(e % bs);
-    out[e * nrhs + col] = in[(int64_t)k * n + c];
+omg_status engine_rm_apply(omg_solver* s, int l, double* z, hipStream_t st) { return rm_apply(s, l, z, st); }
+omg_status engine_finish_report(omg_solver* s, const double* b, const double* x, omg_report* R) {
+    return finish_report(s, b, x, R);
 }
+void engine_reset_logs(omg_solver* s) { reset_logs(s); }
 
-extern "C" omg_status omg_solve_batched(omg_solver* const* s, int32_t n_inst, int32_t nrhs, const double* const* b,
-                                        double* const* x, double tol, omg_report* rep) {
-    if (!s || n_inst < 1 || nrhs < 1 || !b || !x) return OMG_EINVAL;
-    omg_status worst = OMG_OK;
-    for (int i = 0; i < n_inst; ++i) {
-        omg_solver* si = s[i];
-        if (!si || !b[i] || !x[i]) return OMG_EINVAL;
-        Level& L = si->lev[0];
-        const int64_t N = L.N;
-        const dim3 g((unsigned)((N + 255) / 256)), blk(256);
-        for (int c = 0; c < nrhs; ++c) {
-            auto t0 = std::chrono::steady_clock::now();
-            omg_report R;
-            std::memset(&R, 0, sizeof(R));
-            hipLaunchKernelGGL(k_gather_col, g, blk, 0, si->stream, b[i], si->bufA, L.n, si->bs, nrhs, c);
-            hipLaunchKernelGGL(k_gather_col, g, blk, 0, si->stream, x[i], si->bufB, L.n, si->bs, nrhs, c);
-            HIP_OK(hipGetLastError());
-            omg_status st = solve_internal(si, si->bufA, si->bufB, tol, &R);
-            if (st == OMG_OK || st == OMG_ENOCONV) {
-                hipLaunchKernelGGL(k_scatter_col, g, blk, 0, si->stream, si->bufB, x[i], L.n, si->bs, nrhs, c);
-                HIP_OK(hipGetLastError());
-                OMG_TRY(finish_report(si, si->bufA, si->bufB, &R));
-            }
-            HIP_OK(hipStreamSynchronize(si->stream));
-            R.status = st;
-            R.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            if (rep) rep[(size_t)i * nrhs + c] = R;
-            if (st != OMG_OK && worst == OMG_OK) worst = st;
+// A column solver: the owner's operator arrays (shared, not copied), its own
+// work vectors, search directions and persistent-RM state on every level.
+omg_status engine_make_column(omg_solver* o, omg_solver** out) {
+    omg_solver* s = new omg_solver();
+    *out = s;
+    s->owner = o;
+    s->opt = o->opt;
+    s->grid = o->grid;
+    s->bs = o->bs;
+    s->bsh = o->bsh;
+    s->p = o->p;
+    s->nlev = o->nlev;
+    s->stream = o->stream;
+    s->E = o->E;
+    s->E32 = o->E32;
+    for (int l = 0; l < OMG_MAX_LEVELS; ++l) s->nnzb_level[l] = o->nnzb_level[l];
+    s->lev.resize(s->nlev);
+    for (int l = 0; l < s->nlev; ++l) {
+        const Level& P = o->lev[l];
+        Level& L = s->lev[l];
+        L.nx = P.nx;
+        L.ny = P.ny;
+        L.nz = P.nz;
+        L.n = P.n;
+        L.N = P.N;
+        L.width = P.width;
+        L.coarsest = P.coarsest;
+        L.rowsplit = P.rowsplit;
+        L.G = P.G;
+        L.shared_op = 1;
+        L.col = P.col;
+        L.val = P.val;
+        L.val32 = P.val32;
+        L.dinv = P.dinv;
+        L.dinv32 = P.dinv32;
+        L.ainv = P.ainv;
+        L.np = P.np;
+        L.atile = P.atile;
+        L.ntile = P.ntile;
+        if (L.atile && hipMalloc((void**)&L.spart, sizeof(double) * (size_t)L.ntile * L.ntile * 64) != hipSuccess)
+            return OMG_ENOMEM;
+        L.dslot = P.dslot;
+        L.ablk = P.ablk;
+        L.ablk32 = P.ablk32;
+        L.dblk = P.dblk;
+        L.dblk32 = P.dblk32;
+        OMG_TRY(omg_alloc_level_vectors(s, L));
+        if (!L.coarsest && P.persist) {
+            L.persist = 1;
+            L.Gp = P.Gp;
+            L.ept = P.ept;
+            L.rmB = P.rmB;
+            OMG_TRY(alloc_rm_state(s, L, l));
         }
     }
-    return worst;
+    const size_t vb = sizeof(double) * (size_t)s->lev[0].N;
+    if (hipMalloc((void**)&s->bufA, vb) != hipSuccess) return OMG_ENOMEM;
+    if (hipMalloc((void**)&s->bufB, vb) != hipSuccess) return OMG_ENOMEM;
+    OMG_TRY(alloc_host_scalars(s));
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return OMG_OK;
 }
+} // namespace omg
 
 extern "C" omg_status omg_solve_backward(omg_solver* s, const double* u, const double* g_u, double* g_f,
                                          double* g_nu, double tol, omg_report* rep) {
@@ -1091,7 +1234,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
         case OMG_K_RMP: {
             bytes = alg_bytes(s, OMG_K_RMP, level, kb);
             RmArgs a;
-            a.n = L.n;
+            a.N = L.N;
             a.k = kb;
             a.Wp = L.dWp;
             a.Wk = L.W[kb];
@@ -1109,7 +1252,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
             a.gammas = L.gammas;
             a.alphas = L.alphas;
             a.gram = L.gram;
-            hipError_t e = launch_rm_persistent(bs, L.Gp, L.cpt, L.rmB, a, st);
+            hipError_t e = launch_rm_persistent(L.Gp, L.ept, L.rmB, a, st);
             L.phase += (unsigned long long)((kb + L.rmB - 1) / L.rmB) + 2;
             return e;
         }

@@ -1,0 +1,204 @@
+"""GPU checks at the workload sizes (64^3 P2, 48^3 P2, 96^3 P1), where the
+oracle cannot run whole solves in seconds: per-kernel outputs against the
+oracle, properties of the solves (true FP64 residual by the oracle's own
+SpMV), mixed precision at coefficient ratios 1e3 and 1e6, and gradients
+against finite differences."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def omg():
+    import paper_2512_08728_amd as m
+    return m
+
+
+def grid_of(prob):
+    return omg().Solver.make_grid(prob.nx, prob.ny, prob.nz, prob.p, prob.n_levels, prob.h, prob.penalty_c)
+
+
+def cuda(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    """64^3 P2, 4 levels, sphere r = 0.3, ratio 1000 (the benchmark workload)."""
+    prob = synth.make_problem(64, 2)
+    nu = synth.nu_sphere(64, 64, 64, prob.h)
+    t = time.time()
+    o = oracle.Oracle.from_sip(prob, nu, s_pre=2, s_post=2)
+    say(f"oracle setup 64^3 P2: {time.time() - t:.1f} s")
+    g = omg().Solver.from_sip(grid_of(prob), cuda(nu), s_pre=2, s_post=2)
+    return prob, nu, o, g
+
+
+def test_fullsize_operators(big):
+    """Device assembly and Galerkin coarse operators at 64^3 P2 equal the
+    oracle's quadrature assembly and triple products on every level."""
+    prob, nu, o, g = big
+    for l in range(prob.n_levels):
+        rp, ci, v = o.matrix(l)
+        grp, gci, gv = g.level_matrix(l)
+        assert np.array_equal(rp, grp) and np.array_equal(ci, gci)
+        err = np.abs(gv - v).max() / np.abs(v).max()
+        say(f"level {l}: {len(ci)} blocks, max rel. difference {err:.2e}")
+        assert err < 1e-13
+
+
+def test_fullsize_kernels(big):
+    prob, nu, o, g = big
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(prob.n_dofs)
+    b = rng.standard_normal(prob.n_dofs)
+    scale = np.abs(o.spmv(np.abs(x))).max()
+    assert np.abs(host(g.level_spmv(0, cuda(x), cuda(b))) - o.spmv(x, 0, b)).max() <= 1e-14 * scale
+    ref = o.smoother(b, 2, 0)
+    assert np.abs(host(g.level_smoother(0, cuda(b), 2)) - ref).max() <= 1e-12 * np.abs(ref).max()
+    rc = o.restrict(x, 0)
+    assert np.abs(host(g.level_restrict(0, cuda(x))) - rc).max() <= 1e-14 * np.abs(rc).max()
+    n3 = (64 >> 3) ** 3 * prob.bs
+    bc = rng.standard_normal(n3)
+    ref = o.coarse_solve(bc)
+    assert np.abs(host(g.coarse_solve(cuda(bc))) - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_fullsize_solve_true_residual(big):
+    """The benchmark solve reaches ||b - A x|| <= 1e-10 ||b|| with A the
+    oracle's own operator; the recursive residual agrees with the true one."""
+    prob, nu, o, g = big
+    b = synth.rhs(prob.n_dofs, 0)
+    t = time.time()
+    x = host(g.solve(cuda(b), tol=1e-10))
+    rep = g.last_report
+    say(f"64^3 P2 FP64 solve: {time.time() - t:.1f} s, {rep['iters_fine']} cycles, {rep['n_dirs_fine']} directions")
+    r = o.spmv(x, 0, b)
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    assert rel <= 1.0001e-10, rel
+    assert abs(rep["rel_res_true"] - rel) <= 1e-3 * rel
+
+
+@pytest.mark.parametrize("ratio", [1e3, 1e6])
+def test_mixed_precision_ratios(ratio):
+    """FP32 inner OrthoMG with FP64 iterative refinement reaches the FP64
+    residual 1e-10 at coefficient ratios 1e3 and 1e6 (64^3 P2); the
+    difference to the FP64 solution is reported."""
+    prob = synth.make_problem(64, 2)
+    nu = synth.nu_sphere(64, 64, 64, prob.h, nu_out=ratio)
+    b = synth.rhs(prob.n_dofs, 0)
+    g64 = omg().Solver.from_sip(grid_of(prob), cuda(nu), s_pre=2, s_post=2)
+    gm = omg().Solver.from_sip(grid_of(prob), cuda(nu), s_pre=2, s_post=2, precision="mixed_ir")
+    t = time.time()
+    xm = host(gm.solve(cuda(b), tol=1e-10))
+    tm = time.time() - t
+    rm = gm.last_report
+    t = time.time()
+    x64 = host(g64.solve(cuda(b), tol=1e-10))
+    t64 = time.time() - t
+    r64 = g64.last_report
+    diff = np.linalg.norm(xm - x64) / np.linalg.norm(x64)
+    say(f"ratio {ratio:g}: FP64 {t64:.1f} s ({r64['iters_fine']} cycles), mixed {tm:.1f} s "
+        f"({rm['iters_fine']} inner cycles, {rm['outer_iters']} refinements), rel. diff {diff:.2e}, "
+        f"true residuals {r64['rel_res_true']:.2e} / {rm['rel_res_true']:.2e}")
+    assert rm["rel_res_true"] <= 1.0001e-10 and r64["rel_res_true"] <= 1.0001e-10
+    g64.close()
+    gm.close()
+
+
+def _delta(prob, s0, nu1, u0, tol):
+    """u(nu1) - u(nu0) = A(nu1)^-1 (A(nu0) - A(nu1)) u0 with s0 the solver of
+    nu0, solved directly so its accuracy is relative to the (small)
+    difference itself."""
+    s1 = omg().Solver.from_sip(grid_of(prob), cuda(nu1))
+    rhs = s0.level_spmv(0, cuda(u0)) - s1.level_spmv(0, cuda(u0))
+    d = host(s1.solve(rhs, tol=tol))
+    s1.close()
+    return d
+
+
+@pytest.fixture(scope="module")
+def grad48():
+    """48^3 P2 (ratio 1000): forward solve, adjoint gradient of
+    L = 0.5 ||u - u_t||^2 with respect to f and log(nu)."""
+    prob = synth.make_problem(48, 2)
+    nu = synth.nu_sphere(48, 48, 48, prob.h)
+    f = synth.rhs(prob.n_dofs, 0)
+    ut = synth.rhs(prob.n_dofs, 1)
+    s = omg().Solver.from_sip(grid_of(prob), cuda(nu))
+    t = time.time()
+    u = host(s.solve(cuda(f), tol=1e-12))
+    g_f, g_nu = s.backward(cuda(u), cuda(u - ut), tol=1e-12)
+    say(f"48^3 P2 forward + adjoint: {time.time() - t:.1f} s")
+    cells = np.random.default_rng(3).choice(prob.n_cells, size=20, replace=False)
+    yield prob, nu, f, ut, u, host(g_f), host(g_nu) * nu, s, cells
+    s.close()
+
+
+def test_gradient_48p2_euler_identity(grad48):
+    """nu -> c nu scales A by c, so sum_K dL/dlog nu_K = -lambda^T A u = -lambda^T f."""
+    prob, nu, f, ut, u, g_f, g_lognu, s, cells = grad48
+    lam_f = g_f @ f
+    assert abs(g_lognu.sum() + lam_f) <= 1e-8 * abs(lam_f)
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 2, 3])
+def test_gradient_48p2_finite_differences(grad48, chunk):
+    """dL/dlog nu on 20 random cells (5 per chunk) against central finite
+    differences (h = 1e-6): u(nu e^{+-h}) - u(nu) solved directly to 1e-11.
+    Bound: |fd - adj| <= 1e-5 |fd| + 1e-9 max|adj|."""
+    prob, nu, f, ut, u, g_f, g_lognu, s, cells = grad48
+    h = 1e-6
+    gmax = np.abs(g_lognu).max()
+    t = time.time()
+    for c in cells[5 * chunk: 5 * chunk + 5]:
+        nup, num = nu.copy(), nu.copy()
+        nup[c] *= np.exp(h)
+        num[c] *= np.exp(-h)
+        dp = _delta(prob, s, nup, u, 1e-11)
+        dm = _delta(prob, s, num, u, 1e-11)
+        fd = ((dp - dm) @ (u - ut) + 0.5 * (dp @ dp - dm @ dm)) / (2 * h)
+        err = abs(fd - g_lognu[c])
+        say(f"cell {c}: adjoint {g_lognu[c]:.9e}, finite difference {fd:.9e}, rel. {err / abs(fd):.1e}")
+        assert err <= 1e-5 * abs(fd) + 1e-9 * gmax, (c, fd, g_lognu[c])
+    say(f"chunk {chunk}: {time.time() - t:.1f} s")
+
+
+def test_forward_96p1_checkpointed():
+    """96^3 P1 (3.54M DOFs, 5 levels) forward solve through the autograd
+    Function, which keeps only (f, log nu, u) and frees the hierarchy."""
+    prob = synth.make_problem(96, 1)
+    assert prob.n_levels == 5 and prob.n_dofs == 3538944
+    nu = synth.nu_sphere(96, 96, 96, prob.h)
+    f = cuda(synth.rhs(prob.n_dofs, 0)).requires_grad_(True)
+    lognu = cuda(np.log(nu)).requires_grad_(True)
+    fn = omg().solve_fn()
+    t = time.time()
+    u = fn.apply(f, lognu, grid_of(prob), 1e-10, None)
+    torch.cuda.synchronize()
+    say(f"96^3 P1 checkpointed forward: {time.time() - t:.1f} s")
+    assert u.grad_fn is not None
+    o = oracle.Oracle.from_sip(prob, nu)
+    r = o.spmv(host(u), 0, host(f.detach()))
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(host(f.detach()))

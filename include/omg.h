@@ -183,14 +183,15 @@ omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
  * fp32 = 1 uses the FP32 operator copies (inputs rounded to FP32, FP32
  * arithmetic, results widened to FP64). OMG_EUNSUPPORTED for bs > 16. */
 enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
-/* Launch configurations the autotuners chose on a level, host shapes[15]:
+/* Launch configurations the autotuners chose on a level, host shapes[16]:
  * [0..11] the multi-right-hand-side kernels (tuned on the first batched
  * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
  * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..5 is
  * (wavefronts per block, 16-column tiles per wavefront) = (4,2), (2,2),
- * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..14] the persistent
+ * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..15] the persistent
  * residual-minimisation kernel (tuned at setup): blocks, vector entries per
- * thread, directions per grid exchange; -1 if the level does not use it. */
+ * thread, directions per grid exchange, exchange form (0 all-to-all, 1
+ * leader block); -1 if the level does not use it. */
 omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
 omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
                            const double *X, const double *B, double *Y);

@@ -289,8 +289,8 @@ class Solver:
 
     def level_tuning(self, l):
         """Autotuned launch configurations of level l: (multi-RHS shapes
-        [op][fp32][two tiles], (RM blocks, entries per thread, MGS block))."""
-        out = np.zeros(15, dtype=np.int32)
+        [op][fp32][two tiles], (RM blocks, entries per thread, MGS block, leader exchange))."""
+        out = np.zeros(16, dtype=np.int32)
         _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
         return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:])
 

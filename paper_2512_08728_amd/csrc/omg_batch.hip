@@ -194,35 +194,187 @@ omg_status smoother_b(Group& g, const std::vector<int>& act, int l, int sweeps, 
     return OMG_OK;
 }
 
+// Launch configuration of the multi-column RM for m columns of N entries:
+// the tuned single-column form (entries per thread, directions per exchange,
+// exchange form) with entries per thread raised until all m columns' blocks
+// are co-resident in one launch, else the most columns per launch.
+RmConfig multi_config(const RmConfig& tuned, int64_t N, int m) {
+    static const int epts[] = {1, 2, 4, 8, 10, 16, 20};
+    RmConfig best = tuned;
+    int best_cols = 0;
+    for (int e : epts) {
+        if (e < tuned.ept) continue;
+        for (int b : {tuned.B, 2, 1}) {
+            if (b > tuned.B) continue;
+            const int G = (int)((N + (int64_t)kThreads * e - 1) / ((int64_t)kThreads * e));
+            const int cap = rm_multi_capacity(e, b, tuned.lead);
+            if (G > kMaxRedBlocks || cap < G) continue;
+            const int cols = std::min(m, cap / G);
+            if (cols > best_cols) {
+                best_cols = cols;
+                best = RmConfig{G, e, b, tuned.lead};
+            }
+            if (cols == m) return best;
+        }
+    }
+    return best;
+}
+
+// The RM state of every group member at level l in the level's device table
+// (uploaded when it changed: a new direction chunk moves the pointer arrays).
+omg_status refresh_rm_table(Group& g, int l) {
+    omg_solver* P = g.P;
+    const int m = (int)g.col.size();
+    if (!P->btab[l] && hipMalloc((void**)&P->btab[l], sizeof(RmCol) * kMaxCols) != hipSuccess) return OMG_ENOMEM;
+    std::vector<RmCol> h(m);
+    for (int i = 0; i < m; ++i) {
+        RmCol& c = h[i];
+        std::memset(&c, 0, sizeof(c));
+        if (l >= g.col[i]->nlev || !g.col[i]->lev[l].persist) continue; // member has no RM state here
+        Level& L = LV(g.col[i], l);
+        c.N = L.N;
+        c.Wp = L.dWp;
+        c.Zp = L.dZp;
+        c.w = L.w;
+        c.z = L.z;
+        c.zcor = L.zcor;
+        c.r = L.r;
+        c.slots = L.xslots;
+        c.part_rn = L.part + 4 * kMaxRedBlocks;
+        c.scal = L.scal;
+        c.hist = L.hist;
+        c.gammas = L.gammas;
+        c.alphas = L.alphas;
+        c.gram = L.gram;
+    }
+    std::vector<RmCol>& H = P->btab_host[l];
+    const bool same = H.size() == h.size() && std::memcmp(H.data(), h.data(), sizeof(RmCol) * h.size()) == 0;
+    if (!same) { // rare (a new chunk of directions): copy and wait, so the source may change afterwards
+        H = h;
+        HIP_OK(hipMemcpyAsync(P->btab[l], H.data(), sizeof(RmCol) * m, hipMemcpyHostToDevice, g.st));
+        HIP_OK(hipStreamSynchronize(g.st));
+    }
+    return OMG_OK;
+}
+
+// Launch configuration of member c's RM in a batched launch at level l.
+inline RmConfig member_config(const Group& g, int c, int l) {
+    return g.shared ? g.P->lev[l].rmc_multi : g.col[c]->lev[l].rmc;
+}
+
+// RM of the active persistent members in multi-column launches: members with
+// the same launch configuration share a launch as long as their blocks are
+// co-resident; each keeps its own exchange words, phase and storage.
+omg_status rm_multi(Group& g, const std::vector<int>& act, int l, bool zcor) {
+    omg_solver* P = g.P;
+    for (int c : act) OMG_TRY(engine_ensure_dir(g.col[c], l));
+    OMG_TRY(refresh_rm_table(g, l));
+    const int k = LV(g.col[act[0]], l).k;
+    for (int c : act)
+        if ((int)LV(g.col[c], l).dcap <= k) return OMG_EINVAL; // direction k must have storage
+    std::vector<RmConfig> cfg(act.size());
+    for (size_t i = 0; i < act.size(); ++i) {
+        const Level& L = LV(g.col[act[i]], l);
+        if (L.k != k) return OMG_EINVAL; // lockstep members share k
+        cfg[i] = member_config(g, act[i], l);
+    }
+    std::vector<int> done(act.size(), 0);
+    for (size_t i0 = 0; i0 < act.size(); ++i0) {
+        if (done[i0]) continue;
+        const RmConfig c0 = cfg[i0];
+        const int cap = rm_multi_capacity(c0.ept, c0.B, c0.lead);
+        RmMulti M;
+        std::memset(&M, 0, sizeof(M));
+        M.tab = P->btab[l];
+        M.k = k;
+        M.zcor = zcor ? 1 : 0;
+        M.breakdown = P->opt.breakdown;
+        M.abort_flag = P->babort;
+        std::vector<int> members;
+        int blocks = 0;
+        for (size_t i = i0; i < act.size() && M.ncol < kMaxCols; ++i) {
+            if (done[i] || cfg[i].ept != c0.ept || cfg[i].B != c0.B || cfg[i].lead != c0.lead) continue;
+            if (M.ncol > 0 && blocks + cfg[i].G > cap) continue;
+            M.idx[M.ncol] = act[i];
+            M.blk0[M.ncol] = blocks;
+            M.g0[M.ncol] = LV(g.col[act[i]], l).phase;
+            blocks += cfg[i].G;
+            M.ncol++;
+            done[i] = 1;
+            members.push_back((int)i);
+        }
+        M.blk0[M.ncol] = blocks;
+        if (blocks > cap) return OMG_EINVAL; // a single member larger than the device
+        HIP_OK(launch_rm_multi(c0.ept, c0.B, c0.lead, M, g.st));
+        P->kcount[OMG_K_RMP][l]++;
+        for (int i : members) {
+            Level& L = LV(g.col[act[i]], l);
+            L.phase += (unsigned long long)((k + c0.B - 1) / c0.B) + 2;
+            L.Grn = cfg[i].G;
+            L.k++;
+        }
+    }
+    return OMG_OK;
+}
+
 // RM (Algorithm 1) of every active member with its direction z (or zcor):
-// one SpMV launch for all, then the per-member orthogonalisation and update.
+// one SpMV launch for all, then the orthogonalisation and update of the
+// persistent members in multi-column launches (others one by one).
 omg_status rm_b(Group& g, const std::vector<int>& act, int l, bool zcor) {
     const bool f32 = engine_use32(g.col[act[0]], l, true);
     const ColPtrs Z = pack(act, [&](int c, int) { return zcor ? LV(g.col[c], l).zcor : LV(g.col[c], l).z; });
     const ColPtrs W = pack(act, [&](int c, int) { return LV(g.col[c], l).w; });
     OMG_TRY(op_spmv(g, act, l, f32, Z, nullptr, W));
-    for (size_t i = 0; i < act.size(); ++i) OMG_TRY(engine_rm_apply(g.col[act[i]], l, Z.p[i], g.st));
+    std::vector<int> multi;
+    for (size_t i = 0; i < act.size(); ++i) {
+        omg_solver* s = g.col[act[i]];
+        bool ok = LV(s, l).persist && g.P->babort && !g.P->batch_rm_off;
+        if (ok && g.shared) ok = g.P->lev[l].rmc_multi_m > 0;
+        if (ok) {
+            const RmConfig c = member_config(g, act[i], l);
+            ok = c.G <= rm_multi_capacity(c.ept, c.B, c.lead);
+        }
+        if (ok) multi.push_back(act[i]);
+        else OMG_TRY(engine_rm_apply(s, l, Z.p[i], g.st));
+    }
+    if (!multi.empty()) OMG_TRY(rm_multi(g, multi, l, zcor));
     return OMG_OK;
 }
 
 omg_status mg_b(Group& g, std::vector<int> act, int l, int variant);
 
 // z_i (or zcor_i) = P_l MG_{l+1}(P_l^T r_i, 0) for the active members.
+// Transfer table of the active members between levels l and l+1.
+XferTable xfer_table(Group& g, const std::vector<int>& act, int l, bool up, bool zcor) {
+    XferTable T;
+    std::memset(&T, 0, sizeof(T));
+    T.count = (int)act.size();
+    for (size_t i = 0; i < act.size(); ++i) {
+        const Level& F = LV(g.col[act[i]], l);
+        const Level& C = LV(g.col[act[i]], l + 1);
+        T.fnx[i] = F.nx;
+        T.fny[i] = F.ny;
+        T.fn[i] = F.n;
+        T.cnx[i] = C.nx;
+        T.cny[i] = C.ny;
+        T.cn[i] = C.n;
+        T.in[i] = up ? F.r : C.xout;
+        T.out[i] = up ? C.b : (zcor ? F.zcor : F.z);
+    }
+    return T;
+}
+
 omg_status coarse_path(Group& g, const std::vector<int>& act, int l, int variant, bool zcor) {
     omg_solver* P = g.P;
-    for (int c : act) {
-        omg_solver* s = g.col[c];
-        HIP_OK(launch_restrict(LV(s, l), LV(s, l + 1), s->bs, engine_use32(s, l, false), s->E, s->E32, LV(s, l).r,
-                               LV(s, l + 1).b, g.st));
-    }
+    omg_solver* s0 = g.col[act[0]];
+    const bool f32 = engine_use32(s0, l, false);
+    XferTable up = xfer_table(g, act, l, true, zcor);
+    HIP_OK(launch_restrict_grouped(s0->bs, f32, s0->E, s0->E32, up, g.st));
     OMG_TRY(mg_b(g, act, l + 1, variant));
-    for (int c : act) {
-        omg_solver* s = g.col[c];
-        HIP_OK(launch_prolong(LV(s, l), LV(s, l + 1), s->bs, engine_use32(s, l, false), s->E, s->E32,
-                              LV(s, l + 1).xout, zcor ? LV(s, l).zcor : LV(s, l).z, g.st));
-    }
-    P->kcount[OMG_K_RESTRICT][l] += (int64_t)act.size();
-    P->kcount[OMG_K_PROLONG][l] += (int64_t)act.size();
+    XferTable down = xfer_table(g, act, l, false, zcor);
+    HIP_OK(launch_prolong_grouped(s0->bs, f32, s0->E, s0->E32, down, g.st));
+    P->kcount[OMG_K_RESTRICT][l]++;
+    P->kcount[OMG_K_PROLONG][l]++;
     return OMG_OK;
 }
 
@@ -243,11 +395,23 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
     }
     const int m = (int)act.size();
     if (m == 0) return OMG_OK;
-    for (int c : act) {
-        Level& L = LV(g.col[c], l);
-        L.k = 0;
-        HIP_OK(launch_level_init(L.N, L.G, L.b, L.x, L.r, L.part + 4 * kMaxRedBlocks, g.st));
-        L.Grn = L.G;
+    {
+        InitTable T;
+        std::memset(&T, 0, sizeof(T));
+        int G[kMaxCols];
+        T.count = m;
+        for (int i = 0; i < m; ++i) {
+            Level& L = LV(g.col[act[i]], l);
+            L.k = 0;
+            T.N[i] = L.N;
+            T.b[i] = L.b;
+            T.x[i] = L.x;
+            T.r[i] = L.r;
+            T.part[i] = L.part + 4 * kMaxRedBlocks;
+            G[i] = L.G;
+            L.Grn = L.G;
+        }
+        HIP_OK(launch_level_init_grouped(T, G, g.st));
     }
     std::vector<double> r0;
     OMG_TRY(read_norms(g, act, l, r0));
@@ -292,6 +456,8 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
             rn[pos[q]] = nv[q];
         }
     }
+    RecTable T;
+    std::memset(&T, 0, sizeof(T));
     for (int i = 0; i < m; ++i) {
         const int c = act[i];
         omg_solver* s = g.col[c];
@@ -302,13 +468,23 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
             if (!std::isfinite(rn[i])) g.stat[c] = OMG_EINVAL;
             else if (rn[i] > g.tol[c] * r0[i]) g.stat[c] = OMG_ENOCONV;
         }
-        if (L.persist) {
-            HIP_OK(launch_recon(L.k, L.hist, L.gammas, L.alphas, L.dvec, g.st));
-            HIP_OK(launch_lincomb(L.N, L.k, L.dvec, L.dZp, L.xout, g.st));
+        if (L.persist && L.k > 0) { // x = sum_k d_k z~_k, all such members in one pair of launches
+            const int q = T.count++;
+            T.K[q] = L.k;
+            T.N[q] = L.N;
+            T.hist[q] = L.hist;
+            T.gammas[q] = L.gammas;
+            T.alphas[q] = L.alphas;
+            T.d[q] = L.dvec;
+            T.V[q] = L.dZp;
+            T.out[q] = L.xout;
+        } else if (L.persist) {
+            HIP_OK(launch_lincomb(L.N, 0, L.dvec, L.dZp, L.xout, g.st)); // no directions: x = 0
         } else {
             HIP_OK(launch_copy(L.xout, L.x, L.N, g.st));
         }
     }
+    if (T.count > 0) HIP_OK(launch_recon_combine_grouped(T, g.st));
     return OMG_OK;
 }
 
@@ -419,6 +595,27 @@ omg_status solve_group(Group& g, double tol, std::vector<omg_report>& R, std::ve
     return OMG_OK;
 }
 
+// The abort flag of batched RM launches led by P (zero while all is well).
+omg_status ensure_batch_flag(omg_solver* P) {
+    if (P->babort) return OMG_OK;
+    if (hipMalloc((void**)&P->babort, sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipMemsetAsync(P->babort, 0, sizeof(unsigned), P->stream));
+    return OMG_OK;
+}
+
+// After a batched solve: a raised abort flag means a bounded wait of a
+// batched RM launch expired; the results are not trustworthy and later
+// batched solves of P run RM one member at a time.
+omg_status check_batch_flag(omg_solver* P) {
+    unsigned f = 0;
+    HIP_OK(hipMemcpy(&f, P->babort, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (f) {
+        P->batch_rm_off = 1;
+        return OMG_EHIP;
+    }
+    return OMG_OK;
+}
+
 // Column solvers and block copies of solver s for m columns.
 omg_status prepare_columns(omg_solver* s, int m) {
     for (Level& L : s->lev) HIP_OK(build_blocks(L, s->bs, s->bsh, s->stream));
@@ -430,6 +627,13 @@ omg_status prepare_columns(omg_solver* s, int m) {
             return e;
         }
         s->columns.push_back(c);
+    }
+    // multi-column RM configuration for m columns
+    for (int l = 0; l < s->nlev; ++l) {
+        Level& L = s->lev[l];
+        if (L.coarsest || !L.persist || L.rmc_multi_m == m) continue;
+        L.rmc_multi = multi_config(L.rmc, L.N, m);
+        L.rmc_multi_m = m;
     }
     // launch shapes of the multi-RHS kernels, tuned once per level and tile count
     const int ti = m > 16 ? 1 : 0;
@@ -458,6 +662,7 @@ omg_status solve_columns(omg_solver* s, const double* b, double* x, int nrhs, do
         const int m = std::min(kMaxCols, nrhs - c0);
         auto t0 = std::chrono::steady_clock::now();
         OMG_TRY(prepare_columns(s, m));
+        OMG_TRY(ensure_batch_flag(s));
         Group g;
         g.P = s;
         g.shared = true;
@@ -476,6 +681,7 @@ omg_status solve_columns(omg_solver* s, const double* b, double* x, int nrhs, do
         for (auto& r : R) std::memset(&r, 0, sizeof(r));
         std::vector<omg_status> stat(m, OMG_OK);
         omg_status e = solve_group(g, tol, R, stat);
+        if (e == OMG_OK) e = check_batch_flag(s);
         for (omg_solver* c : g.col) // launch counts of the per-column kernels
             for (int k = 0; k < OMG_K_COUNT; ++k)
                 for (int l = 0; l < OMG_MAX_LEVELS; ++l) {
@@ -522,6 +728,7 @@ omg_status solve_instances(omg_solver* const* s, int n, const double* const* b, 
         g.P = s[i0];
         g.shared = false;
         g.st = g.P->stream;
+        OMG_TRY(ensure_batch_flag(g.P));
         for (int i = 0; i < m; ++i) {
             omg_solver* si = s[i0 + i];
             g.col.push_back(si);
@@ -532,6 +739,7 @@ omg_status solve_instances(omg_solver* const* s, int n, const double* const* b, 
         for (auto& r : R) std::memset(&r, 0, sizeof(r));
         std::vector<omg_status> stat(m, OMG_OK);
         OMG_TRY(solve_group(g, tol, R, stat));
+        OMG_TRY(check_batch_flag(g.P));
         for (int i = 0; i < m; ++i) {
             omg_solver* si = g.col[i];
             HIP_OK(launch_from_soa(si->bufB, x[i0 + i], si->lev[0].n, si->bs, g.st));
@@ -625,9 +833,10 @@ extern "C" omg_status omg_level_tuning(const omg_solver* s, int32_t level, int32
     for (int op = 0; op < 3; ++op)
         for (int f = 0; f < 2; ++f)
             for (int t = 0; t < 2; ++t) shapes[q++] = L.mr_shape[op][f][t] - 1;
-    shapes[q++] = L.persist ? L.Gp : -1;
-    shapes[q++] = L.persist ? L.ept : -1;
-    shapes[q++] = L.persist ? L.rmB : -1;
+    shapes[q++] = L.persist ? L.rmc.G : -1;
+    shapes[q++] = L.persist ? L.rmc.ept : -1;
+    shapes[q++] = L.persist ? L.rmc.B : -1;
+    shapes[q++] = L.persist ? L.rmc.lead : -1;
     return OMG_OK;
 }
 

@@ -53,6 +53,34 @@ enum Scal : int {
     S_COUNT = 8
 };
 
+// Launch configuration of the persistent RM kernel on one level.
+struct RmConfig {
+    int G = 0;    // blocks (all co-resident)
+    int ept = 0;  // vector entries per thread
+    int B = 1;    // MGS directions resolved per grid exchange
+    int lead = 0; // exchange form: 0 all-to-all, 1 leader block
+};
+// exchange words: two sets of [kMaxRedBlocks][kRmBlock + 1] block words, then
+// two sets of kRmBlock + 1 total words (leader form)
+constexpr size_t kRmSlotWords = 2 * (size_t)kMaxRedBlocks * (kRmBlock + 1) + 2 * (kRmBlock + 1);
+
+// Per-column state of the multi-column RM kernel (device table entry).
+struct RmCol {
+    int64_t N;
+    double* const* Wp;                 // direction pointer arrays (device)
+    double* const* Zp;
+    const double* w;                   // A z
+    const double* z;                   // the direction handed to RM (z or zcor)
+    const double* zcor;
+    double* r;
+    unsigned long long* slots;
+    double* part_rn;
+    double* scal;
+    double* hist;
+    double* gammas;
+    double* alphas;
+    double* gram;
+};
 // One level of the hierarchy. Vectors are stored component-major inside the
 // library ("SoA"): entry k of cell c at k*n + c, so that a wavefront of
 // consecutive cells reads consecutive addresses.
@@ -107,10 +135,13 @@ struct Level {
     double** dWp = nullptr;            // device copies of the W / Z pointer arrays
     double** dZp = nullptr;
     size_t dcap = 0;
-    // persistent residual minimisation (one co-resident grid of Gp blocks)
-    int persist = 0, Gp = 0, ept = 0, rmB = 1; // grid, vector entries per thread, MGS block
+    // persistent residual minimisation (one co-resident grid)
+    int persist = 0;
+    RmConfig rmc;                      // launch configuration (tuned at setup)
+    RmConfig rmc_multi;                // configuration for multi-column launches of rmc_multi_m columns
+    int rmc_multi_m = 0;
     unsigned* bar = nullptr;           // [2]: [1] = abort flag of the persistent kernel's waits
-    unsigned long long* xslots = nullptr; // exchange words [2][kMaxRedBlocks][kRmBlock + 1]
+    unsigned long long* xslots = nullptr; // exchange words (kRmSlotWords)
     unsigned long long phase = 0;      // next exchange phase of this level (host counter)
     // implicit search directions (persistent levels): raw directions + MGS coefficients
     double* hist = nullptr;            // packed beta rows, ucap*(ucap-1)/2
@@ -164,6 +195,12 @@ struct omg_solver {
     // (work vectors and search directions of their own), created on demand
     omg_solver* owner = nullptr;       // set on a column solver: the solver whose operator it uses
     std::vector<omg_solver*> columns;
+    // batched RM launches led by this solver: per level, the device table of
+    // the members' RM state and what it holds; the launches' abort flag
+    omg::RmCol* btab[OMG_MAX_LEVELS] = {};
+    std::vector<omg::RmCol> btab_host[OMG_MAX_LEVELS];
+    unsigned* babort = nullptr;
+    int batch_rm_off = 0;              // set when a batched RM launch's wait expired
     double* bnorm_host = nullptr;      // [kMaxCols] pinned, mapped: norms of batched members
     double* bnorm_dev = nullptr;       // its device address
 };
@@ -228,19 +265,45 @@ struct RmArgs {
     double* alphas;                    // alpha of every direction
     double* gram;                      // [.][kRmBlock-1] intra-block Gram entries
 };
-struct RmConfig {
-    int G, ept, B; // blocks, vector entries per thread, MGS directions per exchange
+struct RmMulti {
+    const RmCol* tab;                  // device table
+    int k;                             // directions stored before this RM (same for all columns)
+    int zcor;                          // 1: the direction is zcor
+    double breakdown;
+    unsigned* abort_flag;
+    int ncol;
+    int idx[kMaxCols];                 // table entry of column q
+    int blk0[kMaxCols + 1];            // block range of column q
+    unsigned long long g0[kMaxCols];   // first exchange phase of column q
 };
+int rm_multi_capacity(int ept, int B, int lead);
+hipError_t launch_rm_multi(int ept, int B, int lead, const RmMulti& M, hipStream_t st);
+
 // co-resident configurations for N entries, most preferred first; returns the count
+constexpr int kMaxRmConfigs = 96;
 int rm_persistent_candidates(int64_t N, RmConfig* out, int cap);
-bool rm_persistent_config(int64_t N, int* G, int* ept, int* B);
-hipError_t launch_rm_persistent(int G, int ept, int B, const RmArgs& args, hipStream_t st);
+bool rm_persistent_config(int64_t N, RmConfig* cfg);
+hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st);
 // d = coefficients of x = sum_k alpha_k z_k in the raw directions
 hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,
                         hipStream_t st);
 // out = sum_m d[m] V_m
 hipError_t launch_lincomb(int64_t N, int k, const double* d, const double* const* V, double* out,
                           hipStream_t st);
+// launch_recon + launch_lincomb for several members (K[q] >= 1 directions each)
+struct RecTable {
+    int count;
+    int blk0[kMaxCols + 1];
+    int K[kMaxCols];
+    int64_t N[kMaxCols];
+    const double* hist[kMaxCols];
+    const double* gammas[kMaxCols];
+    const double* alphas[kMaxCols];
+    double* d[kMaxCols];
+    const double* const* V[kMaxCols];
+    double* out[kMaxCols];
+};
+hipError_t launch_recon_combine_grouped(RecTable& T, hipStream_t st);
 
 // multi-right-hand-side kernels (omg_multi.hip): nr <= kMaxCols columns that
 // share the operator of L; B may be null (then Y = A X, else Y = B - A X)
@@ -256,6 +319,30 @@ hipError_t launch_dense_mr(const Level& L, int nr, const ColPtrs& X, const ColPt
 // the fastest per (operation, precision, tile count); best_us[6] (nullable)
 hipError_t tune_mr(Level& L, int bs, int nr, const ColPtrs& X, const ColPtrs& Y, const ColPtrs& T, int reps,
                    hipStream_t st, double* best_us);
+// Grid transfers of several members in one launch (segment per member).
+struct XferTable {
+    int count;
+    int blk0[kMaxCols + 1];
+    int fnx[kMaxCols], fny[kMaxCols], fn[kMaxCols], cnx[kMaxCols], cny[kMaxCols], cn[kMaxCols];
+    const double* in[kMaxCols];
+    double* out[kMaxCols];
+};
+// Level entry (x = 0, r = b, ||b||^2 partials) of several members.
+struct InitTable {
+    int count;
+    int blk0[kMaxCols + 1];
+    int64_t N[kMaxCols];
+    const double* b[kMaxCols];
+    double* x[kMaxCols];
+    double* r[kMaxCols];
+    double* part[kMaxCols];
+};
+hipError_t launch_restrict_grouped(int bs, bool fp32, const double* E, const float* E32, XferTable& T,
+                                   hipStream_t st);
+hipError_t launch_prolong_grouped(int bs, bool fp32, const double* E, const float* E32, XferTable& T,
+                                  hipStream_t st);
+// G[q]: reduction blocks of member q (its partials as launch_level_init's)
+hipError_t launch_level_init_grouped(InitTable& T, const int* G, hipStream_t st);
 // grouped forms over T.count instances of one block size (blk0 is filled in):
 // SpMV y = A x or b - A x; first block-Jacobi iteration y = omega D^-1 b;
 // fused iteration y = x + omega D^-1 (b - A x)
@@ -281,6 +368,8 @@ omg_status engine_rm_apply(omg_solver* s, int l, double* z, hipStream_t st);
 // a column solver for batched solves: shares the operator of `owner`
 omg_status engine_make_column(omg_solver* owner, omg_solver** out);
 omg_status engine_finish_report(omg_solver* s, const double* b, const double* x, omg_report* R);
+// storage for direction L.k of level l (and the k + 1 <= capacity check)
+omg_status engine_ensure_dir(omg_solver* s, int l);
 void engine_reset_logs(omg_solver* s);
 
 } // namespace omg

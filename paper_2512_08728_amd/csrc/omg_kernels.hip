@@ -14,6 +14,20 @@ template <typename T> struct Pair;
 template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
+// Operator loads: nontemporal (NT) on levels whose operator is streamed once
+// per sweep and does not fit in the last-level cache, so that it does not
+// evict the vectors; ordinary loads otherwise.
+template <bool NT, typename V> __device__ __forceinline__ V ld_op(const V* p) {
+    if constexpr (NT) {
+        V v;
+        v.x = __builtin_nontemporal_load(&p->x);
+        v.y = __builtin_nontemporal_load(&p->y);
+        return v;
+    } else {
+        return *p;
+    }
+}
+
 // ----------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
     // butterfly: a + b == b + a exactly, so every lane ends with the same value
@@ -59,7 +73,7 @@ __global__ void k_from_soa(const double* __restrict__ in, double* __restrict__ o
 // ----------------------------------------------------------------- block SpMV
 // y = A x, or y = b - A x, for cell i. MT is the storage type of A and the
 // arithmetic type (FP32 mixed forms accumulate in float).
-template <int BS, typename MT>
+template <int BS, typename MT, bool NT>
 __device__ __forceinline__ void spmv_cell(int i, int n, int width, const int* __restrict__ col,
                                           const typename Pair<MT>::type* __restrict__ val,
                                           const double* __restrict__ x, const double* __restrict__ b,
@@ -79,7 +93,7 @@ __device__ __forceinline__ void spmv_cell(int i, int n, int width, const int* __
         for (int r = 0; r < BS; ++r) {
 #pragma unroll
             for (int cp = 0; cp < BSH; ++cp) {
-                const typename Pair<MT>::type a = vj[(int64_t)(r * BSH + cp) * n];
+                const typename Pair<MT>::type a = ld_op<NT>(&vj[(int64_t)(r * BSH + cp) * n]);
                 acc[r] = fma(a.x, xv[2 * cp], acc[r]);
                 acc[r] = fma(a.y, xv[2 * cp + 1], acc[r]);
             }
@@ -100,12 +114,12 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, int width, const int* 
                                                    double* __restrict__ y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    spmv_cell<BS, MT>(i, n, width, col, val, x, b, y);
+    spmv_cell<BS, MT, true>(i, n, width, col, val, x, b, y);
 }
 
 // ----------------------------------------------------------------- block-Jacobi
 // First iteration from x0 = 0: x = omega D^-1 r.
-template <int BS, typename MT>
+template <int BS, typename MT, bool NT>
 __device__ __forceinline__ void bj_first_cell(int i, int n, const typename Pair<MT>::type* __restrict__ dinv,
                                               MT omega, const double* __restrict__ r, double* __restrict__ x) {
     constexpr int BSH = (BS + 1) / 2;
@@ -118,7 +132,7 @@ __device__ __forceinline__ void bj_first_cell(int i, int n, const typename Pair<
         MT s = MT(0);
 #pragma unroll
         for (int cp = 0; cp < BSH; ++cp) {
-            const typename Pair<MT>::type d = dinv[(int64_t)(rr * BSH + cp) * n + i];
+            const typename Pair<MT>::type d = ld_op<NT>(&dinv[(int64_t)(rr * BSH + cp) * n + i]);
             s = fma(d.x, rv[2 * cp], s);
             s = fma(d.y, rv[2 * cp + 1], s);
         }
@@ -132,11 +146,11 @@ __global__ __launch_bounds__(kThreads) void k_bj_first(int n, const typename Pai
                                                        double* __restrict__ x) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    bj_first_cell<BS, MT>(i, n, dinv, omega, r, x);
+    bj_first_cell<BS, MT, true>(i, n, dinv, omega, r, x);
 }
 
 // Fused iteration k >= 2: xout = xin + omega D^-1 (r - A xin).
-template <int BS, typename MT>
+template <int BS, typename MT, bool NT>
 __device__ __forceinline__ void bj_sweep_cell(int i, int n, int width, const int* __restrict__ col,
                                               const typename Pair<MT>::type* __restrict__ val,
                                               const typename Pair<MT>::type* __restrict__ dinv, MT omega,
@@ -157,7 +171,7 @@ __device__ __forceinline__ void bj_sweep_cell(int i, int n, int width, const int
         for (int q = 0; q < BS; ++q) {
 #pragma unroll
             for (int cp = 0; cp < BSH; ++cp) {
-                const typename Pair<MT>::type a = vj[(int64_t)(q * BSH + cp) * n];
+                const typename Pair<MT>::type a = ld_op<NT>(&vj[(int64_t)(q * BSH + cp) * n]);
                 acc[q] = fma(a.x, xv[2 * cp], acc[q]);
                 acc[q] = fma(a.y, xv[2 * cp + 1], acc[q]);
             }
@@ -172,7 +186,7 @@ __device__ __forceinline__ void bj_sweep_cell(int i, int n, int width, const int
         MT s = MT(0);
 #pragma unroll
         for (int cp = 0; cp < BSH; ++cp) {
-            const typename Pair<MT>::type d = dinv[(int64_t)(rr * BSH + cp) * n + i];
+            const typename Pair<MT>::type d = ld_op<NT>(&dinv[(int64_t)(rr * BSH + cp) * n + i]);
             s = fma(d.x, t[2 * cp], s);
             s = fma(d.y, t[2 * cp + 1], s);
         }
@@ -189,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_bj_sweep(int n, int width, const i
                                                        const double* __restrict__ xin, double* __restrict__ xout) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    bj_sweep_cell<BS, MT>(i, n, width, col, val, dinv, omega, r, xin, xout);
+    bj_sweep_cell<BS, MT, true>(i, n, width, col, val, dinv, omega, r, xin, xout);
 }
 
 // ----------------------------------------------------------------- grouped
@@ -208,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_grouped(SegTable T) {
     const int q = segment_of(T, blockIdx.x);
     const int i = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
     if (i >= T.n[q]) return;
-    spmv_cell<BS, MT>(i, T.n[q], T.width[q], T.col[q], (const typename Pair<MT>::type*)T.val[q], T.x[q], T.b[q],
+    spmv_cell<BS, MT, false>(i, T.n[q], T.width[q], T.col[q], (const typename Pair<MT>::type*)T.val[q], T.x[q], T.b[q],
                       T.y[q]);
 }
 
@@ -217,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void k_bj_first_grouped(SegTable T, MT om
     const int q = segment_of(T, blockIdx.x);
     const int i = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
     if (i >= T.n[q]) return;
-    bj_first_cell<BS, MT>(i, T.n[q], (const typename Pair<MT>::type*)T.dinv[q], omega, T.b[q], T.y[q]);
+    bj_first_cell<BS, MT, false>(i, T.n[q], (const typename Pair<MT>::type*)T.dinv[q], omega, T.b[q], T.y[q]);
 }
 
 template <int BS, typename MT>
@@ -225,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_bj_sweep_grouped(SegTable T, MT om
     const int q = segment_of(T, blockIdx.x);
     const int i = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
     if (i >= T.n[q]) return;
-    bj_sweep_cell<BS, MT>(i, T.n[q], T.width[q], T.col[q], (const typename Pair<MT>::type*)T.val[q],
+    bj_sweep_cell<BS, MT, false>(i, T.n[q], T.width[q], T.col[q], (const typename Pair<MT>::type*)T.val[q],
                           (const typename Pair<MT>::type*)T.dinv[q], omega, T.b[q], T.x[q], T.y[q]);
 }
 
@@ -323,11 +337,9 @@ __global__ __launch_bounds__(64 * BS) void k_bj_sweep_rows(int n, int width, con
 // children in slot order s = sx + 2 sy + 4 sz. E is [8][BS][BS] (fine row,
 // coarse column).
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_restrict(int fnx, int fny, int fn, int cnx, int cny, int cn,
-                                                       const MT* __restrict__ E, const double* __restrict__ r,
-                                                       double* __restrict__ rc) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= cn) return;
+__device__ __forceinline__ void restrict_cell(int I, int fnx, int fny, int fn, int cnx, int cny, int cn,
+                                              const MT* __restrict__ E, const double* __restrict__ r,
+                                              double* __restrict__ rc) {
     const int ci = I % cnx, cj = (I / cnx) % cny, ck = I / (cnx * cny);
     MT out[BS];
 #pragma unroll
@@ -350,13 +362,20 @@ __global__ __launch_bounds__(kThreads) void k_restrict(int fnx, int fny, int fn,
     for (int c = 0; c < BS; ++c) rc[(int64_t)c * cn + I] = (double)out[c];
 }
 
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_restrict(int fnx, int fny, int fn, int cnx, int cny, int cn,
+                                                       const MT* __restrict__ E, const double* __restrict__ r,
+                                                       double* __restrict__ rc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= cn) return;
+    restrict_cell<BS, MT>(I, fnx, fny, fn, cnx, cny, cn, E, r, rc);
+}
+
 // Prolongation z = P z_c: z_K = E_{slot(K)} z_{parent(K)}.
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_prolong(int fnx, int fny, int fn, int cnx, int cny, int cn,
-                                                      const MT* __restrict__ E, const double* __restrict__ zc,
-                                                      double* __restrict__ z) {
-    const int K = blockIdx.x * blockDim.x + threadIdx.x;
-    if (K >= fn) return;
+__device__ __forceinline__ void prolong_cell(int K, int fnx, int fny, int fn, int cnx, int cny, int cn,
+                                             const MT* __restrict__ E, const double* __restrict__ zc,
+                                             double* __restrict__ z) {
     const int i = K % fnx, j = (K / fnx) % fny, k = K / (fnx * fny);
     const int I = (i >> 1) + cnx * ((j >> 1) + cny * (k >> 1));
     const int s = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
@@ -371,6 +390,60 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int fnx, int fny, int fn, 
         for (int c = 0; c < BS; ++c) a = fma(Es[r * BS + c], zv[c], a);
         z[(int64_t)r * fn + K] = (double)a;
     }
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_prolong(int fnx, int fny, int fn, int cnx, int cny, int cn,
+                                                      const MT* __restrict__ E, const double* __restrict__ zc,
+                                                      double* __restrict__ z) {
+    const int K = blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= fn) return;
+    prolong_cell<BS, MT>(K, fnx, fny, fn, cnx, cny, cn, E, zc, z);
+}
+
+// Grouped transfers over several members (segment q: blocks [blk0[q], blk0[q+1])).
+template <class TT> __device__ __forceinline__ int seg_of(const TT& T, int block) {
+    int q = 0;
+    while (q + 1 < T.count && block >= T.blk0[q + 1]) ++q;
+    return q;
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_restrict_grouped(XferTable T, const MT* __restrict__ E) {
+    const int q = seg_of(T, blockIdx.x);
+    const int I = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
+    if (I >= T.cn[q]) return;
+    restrict_cell<BS, MT>(I, T.fnx[q], T.fny[q], T.fn[q], T.cnx[q], T.cny[q], T.cn[q], E, T.in[q], T.out[q]);
+}
+
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_prolong_grouped(XferTable T, const MT* __restrict__ E) {
+    const int q = seg_of(T, blockIdx.x);
+    const int K = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
+    if (K >= T.fn[q]) return;
+    prolong_cell<BS, MT>(K, T.fnx[q], T.fny[q], T.fn[q], T.cnx[q], T.cny[q], T.cn[q], E, T.in[q], T.out[q]);
+}
+
+// Level entry for several members: segment q runs k_level_init's loop on its
+// own G_q blocks (same partials as the single launch).
+__global__ __launch_bounds__(kThreads) void k_level_init_grouped(InitTable T) {
+    __shared__ double sh[kThreads / 64];
+    const int q = seg_of(T, blockIdx.x);
+    const int bq = blockIdx.x - T.blk0[q];
+    const int64_t N = T.N[q];
+    const int64_t stride = (int64_t)(T.blk0[q + 1] - T.blk0[q]) * blockDim.x;
+    const double* b = T.b[q];
+    double* x = T.x[q];
+    double* r = T.r[q];
+    double s2 = 0.0;
+    for (int64_t e = (int64_t)bq * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double v = b[e];
+        x[e] = 0.0;
+        r[e] = v;
+        s2 = fma(v, v, s2);
+    }
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) T.part[q][bq] = s2;
 }
 
 // ----------------------------------------------------------------- dense GEMV
@@ -440,14 +513,21 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(int n, const double* __
     }
 }
 
+// One block per 64-row tile: the four wavefronts sum four contiguous ranges
+// of column tiles, then the ranges are added in order.
 __global__ __launch_bounds__(kThreads) void k_symv_reduce(int n, int nt, const double* __restrict__ part,
                                                           double* __restrict__ y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int I = i / kSymT, il = i % kSymT;
+    __shared__ double sh[kThreads / 64][kSymT];
+    const int I = blockIdx.x, il = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int per = (nt + 3) / 4, J0 = q * per, J1 = min(nt, J0 + per);
+    const double* p = part + (size_t)I * nt * kSymT + il;
     double s = 0.0;
-    for (int J = 0; J < nt; ++J) s += part[((size_t)I * nt + J) * kSymT + il];
-    y[i] = s;
+#pragma unroll 4
+    for (int J = J0; J < J1; ++J) s += p[(size_t)J * kSymT];
+    sh[q][il] = s;
+    __syncthreads();
+    const int i = I * kSymT + threadIdx.x;
+    if (threadIdx.x < kSymT && i < n) y[i] = ((sh[0][il] + sh[1][il]) + sh[2][il]) + sh[3][il];
 }
 
 // Pack the lower-triangle tiles of the dense A (row-major, leading dim np).
@@ -761,6 +841,58 @@ hipError_t launch_bj_sweep_grouped(int bs, bool fp32, double omega, SegTable& T,
     return hipGetLastError();
 }
 
+hipError_t launch_restrict_grouped(int bs, bool fp32, const double* E, const float* E32, XferTable& T,
+                                   hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxCols) return hipErrorInvalidValue;
+    int b = 0;
+    for (int q = 0; q < T.count; ++q) {
+        T.blk0[q] = b;
+        b += cdiv(T.cn[q], kThreads);
+    }
+    T.blk0[T.count] = b;
+    if (b == 0) return hipSuccess;
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict_grouped<BSV, float>), dim3(b), dim3(kThreads), 0, st, T,
+                                               E32));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict_grouped<BSV, double>), dim3(b), dim3(kThreads), 0, st, T,
+                                               E));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_grouped(int bs, bool fp32, const double* E, const float* E32, XferTable& T,
+                                  hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxCols) return hipErrorInvalidValue;
+    int b = 0;
+    for (int q = 0; q < T.count; ++q) {
+        T.blk0[q] = b;
+        b += cdiv(T.fn[q], kThreads);
+    }
+    T.blk0[T.count] = b;
+    if (b == 0) return hipSuccess;
+    if (fp32) {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong_grouped<BSV, float>), dim3(b), dim3(kThreads), 0, st, T,
+                                               E32));
+    } else {
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong_grouped<BSV, double>), dim3(b), dim3(kThreads), 0, st, T,
+                                               E));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_level_init_grouped(InitTable& T, const int* G, hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxCols) return hipErrorInvalidValue;
+    int b = 0;
+    for (int q = 0; q < T.count; ++q) {
+        T.blk0[q] = b;
+        b += G[q];
+    }
+    T.blk0[T.count] = b;
+    hipLaunchKernelGGL(k_level_init_grouped, dim3(b), dim3(kThreads), 0, st, T);
+    return hipGetLastError();
+}
+
 hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
                            const double* r, double* rc, hipStream_t st) {
     dim3 grid(cdiv(C.n, kThreads)), block(kThreads);
@@ -793,7 +925,7 @@ hipError_t launch_gemv(const Level& L, const double* x, double* y, hipStream_t s
         const int nt = L.ntile;
         hipLaunchKernelGGL(k_symv_tiles, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kThreads), 0, st, n, L.atile, x,
                            L.spart, nt);
-        hipLaunchKernelGGL(k_symv_reduce, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, n, nt, L.spart, y);
+        hipLaunchKernelGGL(k_symv_reduce, dim3(nt), dim3(kThreads), 0, st, n, nt, L.spart, y);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, st, n, L.np, L.ainv, x, y);

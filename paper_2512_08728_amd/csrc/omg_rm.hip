@@ -38,6 +38,7 @@
 // The grid is sized from the occupancy query so that every block is resident
 // at once; the launch is an ordinary one (cooperative launches carry a large
 // per-launch cost on this runtime).
+#include <algorithm>
 #include <cstdlib>
 
 #include "omg_internal.h"
@@ -98,10 +99,10 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
 // are written every phase (unused ones as zero), so the previous value of any
 // word is always from phase g-2 and carries a different tag.
 template <int SW>
-__device__ __forceinline__ void publish(unsigned long long* slots, int G, unsigned long long g, const double* v,
-                                        int nw) {
+__device__ __forceinline__ void publish(unsigned long long* slots, int G, int bid, unsigned long long g,
+                                        const double* v, int nw) {
     if (threadIdx.x == 0) {
-        unsigned long long* p = slots + ((g & 1) * (unsigned long long)G + blockIdx.x) * SW;
+        unsigned long long* p = slots + ((g & 1) * (unsigned long long)G + bid) * SW;
         const unsigned tag = (unsigned)(g % 3);
         for (int i = 0; i < SW; ++i)
             __hip_atomic_store(p + i, tag_pack(i < nw ? v[i] : 0.0, tag), __ATOMIC_RELAXED,
@@ -109,39 +110,63 @@ __device__ __forceinline__ void publish(unsigned long long* slots, int G, unsign
     }
 }
 
+// Wait until the word carries `tag` (bounded; an expired wait raises the
+// abort flag, and a raised flag ends every wait). Returns the word (0 after
+// an abort).
+__device__ __forceinline__ unsigned long long wait_word(const unsigned long long* p, unsigned tag,
+                                                        unsigned* abort_flag) {
+    unsigned spins = 0;
+    for (;;) {
+        const unsigned long long b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned)(b & 3ull) == tag) return b;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinMax ||
+            ((spins & 127) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+    }
+}
+
 // Sum over blocks of words [0, nw) of phase g; every thread gets the totals.
-template <int SW>
-__device__ __forceinline__ void collect(unsigned long long* slots, int G, unsigned long long g, int nw, double* out,
-                                        double* sh, unsigned* abort_flag) {
+// All-to-all form (LEAD = false): every block reads all G blocks' words.
+// Leader form (LEAD = true): block 0 reads them and publishes the totals
+// (phase-tagged, two alternating sets after the block words) and the other
+// blocks wait for those nw words: 2G word reads per exchange instead of G^2,
+// for one more hop of latency. Every block, block 0 included, uses the
+// tag-truncated totals, so all blocks hold identical values.
+template <int SW, bool LEAD>
+__device__ __forceinline__ void collect(unsigned long long* slots, int G, int bid, unsigned long long g, int nw,
+                                        double* out, double* sh, unsigned* abort_flag) {
     const unsigned tag = (unsigned)(g % 3);
     const unsigned long long* base = slots + (g & 1) * (unsigned long long)G * SW;
+    unsigned long long* tot = slots + 2ull * kMaxRedBlocks * (kRmBlock + 1) + (g & 1) * SW;
     double v[SW];
 #pragma unroll
     for (int w = 0; w < SW; ++w) v[w] = 0.0;
-    for (int i = threadIdx.x; i < G; i += blockDim.x) {
+    if (!LEAD || bid == 0) {
+        for (int i = threadIdx.x; i < G; i += blockDim.x) {
 #pragma unroll
-        for (int w = 0; w < SW; ++w) {
-            if (w < nw) {
-                unsigned long long b = 0;
-                unsigned spins = 0;
-                for (;;) {
-                    b = __hip_atomic_load(base + (unsigned long long)i * SW + w, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                    if ((unsigned)(b & 3ull) == tag) break;
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > kSpinMax ||
-                        ((spins & 127) == 0 &&
-                         __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        b = 0;
-                        break;
-                    }
-                }
-                v[w] += tag_value(b);
-            }
+            for (int w = 0; w < SW; ++w)
+                if (w < nw) v[w] += tag_value(wait_word(base + (unsigned long long)i * SW + w, tag, abort_flag));
         }
+        bsum_n<SW>(v, nw, sh);
+        if (LEAD) {
+            if (threadIdx.x == 0)
+                for (int w = 0; w < SW; ++w)
+                    __hip_atomic_store(tot + w, tag_pack(w < nw ? v[w] : 0.0, tag), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int w = 0; w < SW; ++w) v[w] = tag_value(tag_pack(v[w], tag));
+        }
+    } else {
+        if (threadIdx.x < nw) sh[threadIdx.x] = tag_value(wait_word(tot + threadIdx.x, tag, abort_flag));
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < SW; ++w)
+            if (w < nw) v[w] = sh[w];
+        __syncthreads();
     }
-    bsum_n<SW>(v, nw, sh);
 #pragma unroll
     for (int w = 0; w < SW; ++w)
         if (w < nw) out[w] = v[w];
@@ -150,13 +175,12 @@ __device__ __forceinline__ void collect(unsigned long long* slots, int G, unsign
 // Every vector is handled as a flat array of N entries (RM has no cell
 // structure): thread t of a grid of T threads owns entries t + j T, j < EPT,
 // so consecutive threads touch consecutive addresses.
-template <int EPT, int B>
-__global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
+// The RM of one vector set on G blocks; this block is block `bid` of them.
+template <int EPT, int B, bool LEAD>
+__device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int bid, double* sh) {
     constexpr int SW = B + 1;
-    __shared__ double sh[kMaxVals * (kThreads / 64)];
-    const int G = gridDim.x;
     const int64_t T = (int64_t)G * blockDim.x;
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = (int64_t)bid * blockDim.x + threadIdx.x;
     const int64_t N = A.N;
     const int k = A.k;
     double w[EPT], a[B][EPT], an[B][EPT];
@@ -200,14 +224,14 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
             vals[t] = s;
         }
         bsum_n<SW>(vals, SW, sh);
-        publish<SW>(A.slots, G, g, vals, SW);
+        publish<SW>(A.slots, G, bid, g, vals, SW);
     }
     double nin2 = 0.0, nout2 = 0.0;
     double tot[SW];
     for (int b = 0; b < nblk; ++b) {
         const int j0 = b * B;
         const int bb = min(B, k - j0);
-        collect<SW>(A.slots, G, g, (b == 0) ? SW : bb, tot, sh, A.abort_flag);
+        collect<SW, LEAD>(A.slots, G, bid, g, (b == 0) ? SW : bb, tot, sh, A.abort_flag);
         if (b == 0) nin2 = tot[B];
         double beta[B];
 #pragma unroll
@@ -219,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
             }
             beta[t] = bt;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) // row k of the coefficient history
+        if (bid == 0 && threadIdx.x == 0) // row k of the coefficient history
             for (int t = 0; t < bb; ++t) A.hist[(int64_t)k * (k - 1) / 2 + j0 + t] = beta[t];
 #pragma unroll
         for (int t = 0; t < B; ++t)
@@ -240,20 +264,20 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
                 vals[t] = s;
             }
             bsum_n<SW>(vals, B, sh);
-            publish<SW>(A.slots, G, g, vals, B);
+            publish<SW>(A.slots, G, bid, g, vals, B);
         } else {
             double s = 0.0;
 #pragma unroll
             for (int j = 0; j < EPT; ++j) s = fma(w[j], w[j], s);
             vals[0] = s;
             bsum_n<SW>(vals, 1, sh);
-            publish<SW>(A.slots, G, g, vals, 1);
-            collect<SW>(A.slots, G, g, 1, tot, sh, A.abort_flag);
+            publish<SW>(A.slots, G, bid, g, vals, 1);
+            collect<SW, LEAD>(A.slots, G, bid, g, 1, tot, sh, A.abort_flag);
             nout2 = tot[0];
         }
     }
     if (k == 0) {
-        collect<SW>(A.slots, G, g, SW, tot, sh, A.abort_flag);
+        collect<SW, LEAD>(A.slots, G, bid, g, SW, tot, sh, A.abort_flag);
         nin2 = tot[B];
         nout2 = nin2;
     }
@@ -285,8 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
 #pragma unroll
     for (int t = 0; t < B - 1; ++t) vals[1 + t] = s_g[t];
     bsum_n<SW>(vals, B, sh);
-    publish<SW>(A.slots, G, g, vals, B);
-    collect<SW>(A.slots, G, g, B, tot, sh, A.abort_flag);
+    publish<SW>(A.slots, G, bid, g, vals, B);
+    collect<SW, LEAD>(A.slots, G, bid, g, B, tot, sh, A.abort_flag);
     const double alpha = tot[0];
     double s_r = 0.0;
 #pragma unroll
@@ -297,14 +321,52 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
     }
     s_r = bsum(s_r, sh);
     if (threadIdx.x == 0) {
-        A.part_rn[blockIdx.x] = s_r;
-        if (blockIdx.x == 0) {
+        A.part_rn[bid] = s_r;
+        if (bid == 0) {
             A.alphas[k] = alpha;
             A.gammas[k] = gamma;
             for (int t = 0; t < B - 1; ++t) A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? tot[1 + t] : 0.0;
             if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
         }
     }
+}
+
+template <int EPT, int B, bool LEAD>
+__global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
+    __shared__ double sh[kMaxVals * (kThreads / 64)];
+    rm_body<EPT, B, LEAD>(A, gridDim.x, blockIdx.x, sh);
+}
+
+// RM of several vector sets (columns of a batched solve, or independent
+// solvers of one level configuration) in one launch: column q owns blocks
+// [blk0[q], blk0[q+1]) and exchanges only among them, with its own words,
+// phase and storage (table entry idx[q]); all columns share k.
+template <int EPT, int B, bool LEAD>
+__global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
+    __shared__ double sh[kMaxVals * (kThreads / 64)];
+    int q = 0;
+    while (q + 1 < M.ncol && (int)blockIdx.x >= M.blk0[q + 1]) ++q;
+    const RmCol& C = M.tab[M.idx[q]];
+    RmArgs A;
+    A.N = C.N;
+    A.k = M.k;
+    A.Wp = C.Wp;
+    A.Wk = C.Wp[M.k];
+    A.Zk = C.Zp[M.k];
+    A.w = C.w;
+    A.z = M.zcor ? C.zcor : C.z;
+    A.r = C.r;
+    A.slots = C.slots;
+    A.g0 = M.g0[q];
+    A.part_rn = C.part_rn;
+    A.breakdown = M.breakdown;
+    A.scal = C.scal;
+    A.abort_flag = M.abort_flag;
+    A.hist = C.hist;
+    A.gammas = C.gammas;
+    A.alphas = C.alphas;
+    A.gram = C.gram;
+    rm_body<EPT, B, LEAD>(A, M.blk0[q + 1] - M.blk0[q], (int)blockIdx.x - M.blk0[q], sh);
 }
 
 // Coefficients of x = sum_k alpha_k z_k in the raw directions: with
@@ -338,36 +400,98 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t N, int k, const do
     }
 }
 
+// Several members at once: block q of the recombination runs k_recon for
+// member q; the combination's segment q runs k_combine's loop for member q.
+__global__ __launch_bounds__(64) void k_recon_grouped(RecTable T) {
+    extern __shared__ double c[];
+    const int q = blockIdx.x;
+    const int K = T.K[q];
+    const double* hist = T.hist[q];
+    const double* gammas = T.gammas[q];
+    double* d = T.d[q];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) c[i] = T.alphas[q][i];
+    __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {
+        const double dk = c[k] * gammas[k];
+        __syncthreads();
+        if (threadIdx.x == 0) d[k] = dk;
+        const double* hk = hist + (int64_t)k * (k - 1) / 2;
+        for (int i = threadIdx.x; i < k; i += blockDim.x) c[i] = fma(-dk, hk[i], c[i]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_combine_grouped(RecTable T) {
+    int q = 0;
+    while (q + 1 < T.count && (int)blockIdx.x >= T.blk0[q + 1]) ++q;
+    const int64_t N = T.N[q];
+    const int k = T.K[q];
+    const double* const* V = T.V[q];
+    const double* d = T.d[q];
+    double* out = T.out[q];
+    const int64_t stride = (int64_t)(T.blk0[q + 1] - T.blk0[q]) * blockDim.x;
+    for (int64_t e = (int64_t)(blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double s = 0.0;
+        for (int m = 0; m < k; ++m) s = fma(d[m], V[m][e], s);
+        out[e] = s;
+    }
+}
+
 __global__ void k_zero(double* __restrict__ out, int64_t N) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) out[e] = 0.0;
 }
 
-template <int EPT, int B>
-static const void* rm_kernel() {
-    return reinterpret_cast<const void*>(&k_rm_blk<EPT, B>);
+template <int EPT, int B, bool LEAD>
+static const void* rm_kernel(bool multi) {
+    return multi ? reinterpret_cast<const void*>(&k_rm_multi<EPT, B, LEAD>)
+                 : reinterpret_cast<const void*>(&k_rm_blk<EPT, B, LEAD>);
 }
 
-// Instantiations: entries per thread EPT, MGS block B in {1, 2, 4}.
+// Instantiations: entries per thread EPT, MGS block B in {1, 2, 4}, exchange
+// form (all-to-all or leader).
 constexpr int kEpts[] = {1, 2, 4, 8, 10, 16, 20};
-template <int EPT>
-static const void* pick_b(int b) {
-    if (b == 4) return rm_kernel<EPT, 4>();
-    if (b == 2) return rm_kernel<EPT, 2>();
-    if (b == 1) return rm_kernel<EPT, 1>();
+template <int EPT, bool LEAD>
+static const void* pick_b(int b, bool multi) {
+    if (b == 4) return rm_kernel<EPT, 4, LEAD>(multi);
+    if (b == 2) return rm_kernel<EPT, 2, LEAD>(multi);
+    if (b == 1) return rm_kernel<EPT, 1, LEAD>(multi);
     return nullptr;
 }
-static const void* pick(int ept, int b) {
+template <int EPT>
+static const void* pick_x(int b, int lead, bool multi) {
+    return lead ? pick_b<EPT, true>(b, multi) : pick_b<EPT, false>(b, multi);
+}
+static const void* pick(int ept, int b, int lead, bool multi = false) {
     switch (ept) {
-    case 1: return pick_b<1>(b);
-    case 2: return pick_b<2>(b);
-    case 4: return pick_b<4>(b);
-    case 8: return pick_b<8>(b);
-    case 10: return pick_b<10>(b);
-    case 16: return pick_b<16>(b);
-    case 20: return pick_b<20>(b);
+    case 1: return pick_x<1>(b, lead, multi);
+    case 2: return pick_x<2>(b, lead, multi);
+    case 4: return pick_x<4>(b, lead, multi);
+    case 8: return pick_x<8>(b, lead, multi);
+    case 10: return pick_x<10>(b, lead, multi);
+    case 16: return pick_x<16>(b, lead, multi);
+    case 20: return pick_x<20>(b, lead, multi);
     }
     return nullptr;
+}
+
+// Blocks of the multi-column kernel in this configuration that fit at once.
+int rm_multi_capacity(int ept, int B, int lead) {
+    int dev = 0, cus = 0, per_cu = 0;
+    const void* f = pick(ept, B, lead, true);
+    if (!f || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_rm_multi(int ept, int B, int lead, const RmMulti& M, hipStream_t st) {
+    const void* f = pick(ept, B, lead, true);
+    if (!f || M.ncol < 1 || M.ncol > kMaxCols) return hipErrorInvalidValue;
+    RmMulti a = M;
+    void* params[] = {&a};
+    return hipLaunchKernel(f, dim3(M.blk0[M.ncol]), dim3(kThreads), params, 0, st);
 }
 
 // Co-resident launch configurations for a level of N entries: grids of at
@@ -383,29 +507,29 @@ int rm_persistent_candidates(int64_t N, RmConfig* out, int cap) {
         for (int e : kEpts) {
             const int64_t need = (N + (int64_t)kThreads * e - 1) / ((int64_t)kThreads * e);
             if (pass == 0 ? need > 512 : (need <= 512 || need > kMaxRedBlocks)) continue;
-            for (int b : {4, 2, 1}) {
-                const void* f = pick(e, b);
-                int per_cu = 0;
-                if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess ||
-                    per_cu < 1 || need > (int64_t)per_cu * cus)
-                    continue;
-                if (n < cap) out[n++] = RmConfig{(int)need, e, b};
-            }
+            for (int b : {4, 2, 1})
+                for (int lead : {0, 1}) {
+                    const void* f = pick(e, b, lead);
+                    int per_cu = 0;
+                    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess ||
+                        per_cu < 1 || need > (int64_t)per_cu * cus)
+                        continue;
+                    if (n < cap) out[n++] = RmConfig{(int)need, e, b, lead};
+                }
         }
     return n;
 }
 
-bool rm_persistent_config(int64_t N, int* G, int* ept, int* B) {
-    RmConfig c[64];
-    if (rm_persistent_candidates(N, c, 64) < 1) return false;
-    *G = c[0].G;
-    *ept = c[0].ept;
-    *B = c[0].B;
+bool rm_persistent_config(int64_t N, RmConfig* cfg) {
+    RmConfig c[kMaxRmConfigs];
+    if (rm_persistent_candidates(N, c, kMaxRmConfigs) < 1) return false;
+    *cfg = c[0];
     return true;
 }
 
-hipError_t launch_rm_persistent(int G, int ept, int B, const RmArgs& args, hipStream_t st) {
-    const void* f = pick(ept, B);
+hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st) {
+    const void* f = pick(c.ept, c.B, c.lead);
+    const int G = c.G;
     if (!f) return hipErrorInvalidValue;
     RmArgs a = args;
     void* params[] = {&a};
@@ -416,6 +540,24 @@ hipError_t launch_recon(int K, const double* hist, const double* gammas, const d
                         hipStream_t st) {
     if (K == 0) return hipSuccess;
     hipLaunchKernelGGL(k_recon, dim3(1), dim3(64), sizeof(double) * (size_t)K, st, K, hist, gammas, alphas, d);
+    return hipGetLastError();
+}
+
+// x of several members: d by the backward recurrence, then x = sum_k d_k z~_k.
+hipError_t launch_recon_combine_grouped(RecTable& T, hipStream_t st) {
+    if (T.count < 1 || T.count > kMaxCols) return hipErrorInvalidValue;
+    int kmax = 0, b = 0;
+    for (int q = 0; q < T.count; ++q) {
+        if (T.K[q] < 1) return hipErrorInvalidValue; // members with directions only
+        kmax = std::max(kmax, T.K[q]);
+        T.blk0[q] = b;
+        int64_t blocks = (T.N[q] + kThreads - 1) / kThreads;
+        if (blocks > 2048) blocks = 2048;
+        b += (int)blocks;
+    }
+    T.blk0[T.count] = b;
+    hipLaunchKernelGGL(k_recon_grouped, dim3(T.count), dim3(64), sizeof(double) * (size_t)kmax, st, T);
+    hipLaunchKernelGGL(k_combine_grouped, dim3(b), dim3(kThreads), 0, st, T);
     return hipGetLastError();
 }
 

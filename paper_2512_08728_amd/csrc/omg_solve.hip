@@ -17,8 +17,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+
+#include <map>
+#include <mutex>
 
 #include "omg_internal.h"
 
@@ -128,6 +132,8 @@ extern "C" void omg_destroy(omg_solver* s) {
     for (omg_solver* c : s->columns) omg_destroy(c);
     s->columns.clear();
     if (s->bnorm_host) hipHostFree(s->bnorm_host);
+    for (auto* t : s->btab) hipFree(t);
+    hipFree(s->babort);
     if (s->owner) { // column solver: E, E32 belong to the owner
         s->E = nullptr;
         s->E32 = nullptr;
@@ -229,7 +235,7 @@ static omg_status alloc_rm_state(omg_solver* s, Level& L, int l) {
     L.ucap = per_it * std::max(its, 1) + 4;
     if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
     HIP_OK(hipMemset(L.bar, 0, 2 * sizeof(unsigned)));
-    const size_t xs = sizeof(unsigned long long) * 2 * kMaxRedBlocks * (kRmBlock + 1);
+    const size_t xs = sizeof(unsigned long long) * kRmSlotWords;
     if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
     HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
     L.phase = 0;
@@ -247,17 +253,43 @@ static omg_status alloc_rm_state(omg_solver* s, Level& L, int l) {
 static omg_status ensure_dir(omg_solver* s, Level& L, int k);
 
 // Launch configuration of the persistent RM kernel on level l: time every
-// co-resident configuration (entries per thread, MGS block, grid) with kt
-// stored directions (zero data: the traffic and exchanges do not depend on
-// the values) and keep the fastest. The directions' storage is the level's
-// own; the solve overwrites everything these launches write.
+// co-resident configuration (entries per thread, MGS block, exchange form,
+// grid) with kt stored directions, half the level's capacity (at most 256:
+// the exchange latency and the streaming share depend on k), zero data (the
+// traffic and exchanges do not depend on the values), best of two trials,
+// and keep the fastest. The directions' storage is the level's own; the
+// solve overwrites everything these launches write.
+//
+// The configuration sets the order of the kernel's partial sums, so it is
+// chosen once per (device, level size) for the whole process: every solver
+// of that size then runs the same arithmetic, and results do not depend on
+// which solver was timed.
+static std::mutex g_rm_mu;
+static std::map<std::pair<int, int64_t>, RmConfig> g_rm_cache;
+
 static omg_status tune_rm(omg_solver* s, int l) {
     Level& L = s->lev[l];
-    RmConfig c[64];
-    const int nc = rm_persistent_candidates(L.N, c, 64);
-    if (nc <= 1 || std::getenv("OMG_RM_NOTUNE")) return OMG_OK;
-    const int kt = std::min(L.ucap - 1, 40);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    const std::pair<int, int64_t> key(dev, L.N);
+    {
+        std::lock_guard<std::mutex> lk(g_rm_mu);
+        auto it = g_rm_cache.find(key);
+        if (it != g_rm_cache.end()) {
+            L.rmc = it->second;
+            return OMG_OK;
+        }
+    }
+    RmConfig c[kMaxRmConfigs];
+    const int nc = rm_persistent_candidates(L.N, c, kMaxRmConfigs);
+    if (nc <= 1 || std::getenv("OMG_RM_NOTUNE")) {
+        std::lock_guard<std::mutex> lk(g_rm_mu);
+        g_rm_cache.emplace(key, L.rmc);
+        return OMG_OK;
+    }
+    const int kt = std::max(1, std::min((L.ucap - 1) / 2, 256));
     OMG_TRY(ensure_dir(s, L, kt));
+    if ((int)L.W.size() <= kt || (int)L.dcap <= kt) return OMG_EINVAL;
     hipStream_t st = s->stream;
     for (int i = 0; i <= kt; ++i) HIP_OK(launch_fill(L.W[i], 0.0, L.N, st));
     HIP_OK(launch_fill(L.w, 0.0, L.N, st));
@@ -287,20 +319,28 @@ static omg_status tune_rm(omg_solver* s, int l) {
     float best = 1e30f;
     int bi = 0;
     omg_status res = OMG_OK;
+    const bool log = std::getenv("OMG_RM_TUNE_LOG") != nullptr;
     for (int q = 0; q < nc && res == OMG_OK; ++q) {
-        const int reps = 3;
-        for (int r = 0; r <= reps && res == OMG_OK; ++r) {
-            if (r == 1 && hipEventRecord(e0, st) != hipSuccess) res = OMG_EHIP;
-            a.g0 = L.phase;
-            if (res == OMG_OK && launch_rm_persistent(c[q].G, c[q].ept, c[q].B, a, st) != hipSuccess) res = OMG_EHIP;
-            L.phase += (unsigned long long)((kt + c[q].B - 1) / c[q].B) + 2;
+        float tbest = 1e30f;
+        for (int trial = 0; trial < 2 && res == OMG_OK; ++trial) {
+            const int reps = 3;
+            for (int r = 0; r <= reps && res == OMG_OK; ++r) {
+                if (r == 1 && hipEventRecord(e0, st) != hipSuccess) res = OMG_EHIP;
+                a.g0 = L.phase;
+                if (res == OMG_OK && launch_rm_persistent(c[q], a, st) != hipSuccess) res = OMG_EHIP;
+                L.phase += (unsigned long long)((kt + c[q].B - 1) / c[q].B) + 2;
+            }
+            float ms = 0.f;
+            if (res == OMG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                res = OMG_EHIP;
+            tbest = std::min(tbest, ms);
         }
-        float ms = 0.f;
-        if (res == OMG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            res = OMG_EHIP;
-        if (res == OMG_OK && ms < best) {
-            best = ms;
+        if (log)
+            std::fprintf(stderr, "[omg] RM tuning N=%lld k=%d: G=%d ept=%d B=%d lead=%d: %.1f us\n", (long long)L.N,
+                         kt, c[q].G, c[q].ept, c[q].B, c[q].lead, 1e3 * tbest / 3);
+        if (res == OMG_OK && tbest < best) {
+            best = tbest;
             bi = q;
         }
     }
@@ -310,9 +350,9 @@ static omg_status tune_rm(omg_solver* s, int l) {
     unsigned flags[2] = {0, 0};
     HIP_OK(hipMemcpy(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost));
     if (flags[1]) return OMG_EHIP; // a bounded wait expired
-    L.Gp = c[bi].G;
-    L.ept = c[bi].ept;
-    L.rmB = c[bi].B;
+    std::lock_guard<std::mutex> lk(g_rm_mu);
+    const RmConfig& pick = g_rm_cache.emplace(key, c[bi]).first->second; // first tuner of this size wins
+    L.rmc = pick;
     return OMG_OK;
 }
 
@@ -332,7 +372,7 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
             // variant the coarse levels (second stream) keep the per-step kernels
             const bool eligible = !std::getenv("OMG_NO_PERSISTENT_RM") &&
                                   !(s->opt.variant == OMG_OVERLAP_DET && l > 0);
-            if (eligible) L.persist = rm_persistent_config(L.N, &L.Gp, &L.ept, &L.rmB);
+            if (eligible) L.persist = rm_persistent_config(L.N, &L.rmc);
             if (L.persist) {
                 OMG_TRY(alloc_rm_state(s, L, l));
                 OMG_TRY(tune_rm(s, l));
@@ -447,7 +487,7 @@ static double alg_bytes(const omg_solver* s, int kind, int l, int k) {
     case OMG_K_BJ32: return nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8;
     case OMG_K_BJFIRST: return L.n * bb * 8 + 2 * N * 8;
     case OMG_K_MGS: return 2 * N * 8;                 // W_i and Z_i; w and z stay resident
-    case OMG_K_RMP: return (k + 6.0 + k % L.rmB) * N * 8; // W_i (i < k), w, z~ in, W_k, Z~_k out, r in/out, Gram reads
+    case OMG_K_RMP: return (k + 6.0 + k % L.rmc.B) * N * 8; // W_i (i < k), w, z~ in, W_k, Z~_k out, r in/out, Gram reads
     case OMG_K_RMFIN: return 8 * N * 8;
     case OMG_K_COARSE: return N * N * 8 + 2 * N * 8;
     }
@@ -456,17 +496,20 @@ static double alg_bytes(const omg_solver* s, int kind, int l, int k) {
 
 // Make room for direction index k on level l (chunks of 32 directions).
 static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
+    if (k < 0) return OMG_EINVAL;
     if (k < (int)L.W.size()) return OMG_OK;
     const int chunk = 32;
-    double* mem = nullptr;
-    if (hipMalloc((void**)&mem, sizeof(double) * (size_t)L.N * 2 * chunk) != hipSuccess) {
-        (void)hipGetLastError();
-        return OMG_ENOMEM;
-    }
-    L.chunks.push_back(mem);
-    for (int c = 0; c < chunk; ++c) {
-        L.W.push_back(mem + (size_t)L.N * (2 * c));
-        L.Z.push_back(mem + (size_t)L.N * (2 * c + 1));
+    while (k >= (int)L.W.size()) { // as many chunks as index k needs
+        double* mem = nullptr;
+        if (hipMalloc((void**)&mem, sizeof(double) * (size_t)L.N * 2 * chunk) != hipSuccess) {
+            (void)hipGetLastError();
+            return OMG_ENOMEM;
+        }
+        L.chunks.push_back(mem);
+        for (int c = 0; c < chunk; ++c) {
+            L.W.push_back(mem + (size_t)L.N * (2 * c));
+            L.Z.push_back(mem + (size_t)L.N * (2 * c + 1));
+        }
     }
     // device copies of the pointer arrays (read by the persistent RM kernel)
     double **dW = nullptr, **dZ = nullptr;
@@ -534,11 +577,11 @@ static omg_status rm_apply(omg_solver* s, int l, double* z, hipStream_t st) {
         a.alphas = L.alphas;
         a.gram = L.gram;
         probe_begin(s, OMG_K_RMP, l, st);
-        HIP_OK(launch_rm_persistent(L.Gp, L.ept, L.rmB, a, st));
+        HIP_OK(launch_rm_persistent(L.rmc, a, st));
         probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
-        L.phase += (unsigned long long)((L.k + L.rmB - 1) / L.rmB) + 2;
+        L.phase += (unsigned long long)((L.k + L.rmc.B - 1) / L.rmc.B) + 2;
         s->kcount[OMG_K_RMP][l]++;
-        L.Grn = L.Gp;
+        L.Grn = L.rmc.G;
         L.k++;
         return OMG_OK;
     }
@@ -888,6 +931,12 @@ omg_status engine_rm_apply(omg_solver* s, int l, double* z, hipStream_t st) { re
 omg_status engine_finish_report(omg_solver* s, const double* b, const double* x, omg_report* R) {
     return finish_report(s, b, x, R);
 }
+omg_status engine_ensure_dir(omg_solver* s, int l) {
+    Level& L = s->lev[l];
+    OMG_TRY(ensure_dir(s, L, L.k));
+    if (L.persist && L.k + 1 > L.ucap) return OMG_ENOMEM;
+    return OMG_OK;
+}
 void engine_reset_logs(omg_solver* s) { reset_logs(s); }
 
 // A column solver: the owner's operator arrays (shared, not copied), its own
@@ -939,9 +988,7 @@ omg_status engine_make_column(omg_solver* o, omg_solver** out) {
         OMG_TRY(omg_alloc_level_vectors(s, L));
         if (!L.coarsest && P.persist) {
             L.persist = 1;
-            L.Gp = P.Gp;
-            L.ept = P.ept;
-            L.rmB = P.rmB;
+            L.rmc = P.rmc;
             OMG_TRY(alloc_rm_state(s, L, l));
         }
     }
@@ -1187,6 +1234,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
     if (kind == OMG_K_RMP) {
         if (!L.persist || L.ucap < kb + 1) return OMG_EUNSUPPORTED;
         OMG_TRY(ensure_dir(s, L, kb));
+        if ((int)L.W.size() <= kb) return OMG_EINVAL;
         for (int i = 0; i <= kb; ++i) {
             HIP_OK(launch_fill(L.W[i], 1.0 / std::sqrt(N), L.N, st));
             HIP_OK(launch_fill(L.Z[i], 0.0, L.N, st));
@@ -1252,8 +1300,8 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
             a.gammas = L.gammas;
             a.alphas = L.alphas;
             a.gram = L.gram;
-            hipError_t e = launch_rm_persistent(L.Gp, L.ept, L.rmB, a, st);
-            L.phase += (unsigned long long)((kb + L.rmB - 1) / L.rmB) + 2;
+            hipError_t e = launch_rm_persistent(L.rmc, a, st);
+            L.phase += (unsigned long long)((kb + L.rmc.B - 1) / L.rmc.B) + 2;
             return e;
         }
         }

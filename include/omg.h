@@ -195,6 +195,23 @@ enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
 omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
 omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
                            const double *X, const double *B, double *Y);
+/* One residual-minimisation step (Algorithm 1 after w = A z) with level l's
+ * persistent kernel on caller data: the vectors are flat device arrays of
+ * N_l entries (RM has no cell structure); W holds k orthonormal directions
+ * as rows of a k x N_l array; cfg (host, nullable) = (blocks, entries per
+ * thread, directions per exchange, leader exchange) selects one of the
+ * co-resident configurations of omg_level_rm_configs (NULL: the tuned one).
+ * Outputs: Wk (the new orthonormal direction), r_new, and host
+ * coeff[k + 2] = (beta_0..beta_{k-1}, gamma, alpha). The level's own work
+ * storage is overwritten. OMG_EUNSUPPORTED if the level does not use the
+ * persistent kernel. */
+omg_status omg_level_rm_step(omg_solver *s, int32_t level, int32_t k, const double *W, const double *w,
+                             const double *z, const double *r, const int32_t *cfg, double *Wk, double *r_new,
+                             double *coeff);
+/* The co-resident launch configurations of level l's persistent RM kernel:
+ * host out[4*cap] (blocks, entries per thread, directions per exchange,
+ * leader), their count in *n (out nullable to query the count). */
+omg_status omg_level_rm_configs(const omg_solver *s, int32_t level, int32_t *out, int32_t cap, int32_t *n);
 /* Stored directions of level l after the last solve (device, cell-major,
  * [k][N] each); W or Z nullable. */
 omg_status omg_get_dirs(const omg_solver *s, int32_t level, double *W, double *Z);

@@ -64,7 +64,7 @@ EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "om
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
            "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay", "omg_bench_kernel",
            "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result", "omg_level_multi",
-           "omg_level_tuning"]
+           "omg_level_tuning", "omg_level_rm_step", "omg_level_rm_configs"]
 MR_SPMV, MR_SMOOTHER, MR_COARSE = 0, 1, 2
 K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST, K_RMP, K_COPY = range(12)
 K_NAMES = ["spmv", "spmv32", "bj_sweep", "bj_sweep32", "mgs_step", "restrict", "prolong", "coarse_gemv",
@@ -108,6 +108,8 @@ def lib():
         L.omg_probe_result.argtypes = [P, P, P, P]
         L.omg_level_multi.argtypes = [P, i32, i32, i32, i32, i32, P, P, P]
         L.omg_level_tuning.argtypes = [P, i32, P]
+        L.omg_level_rm_step.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P]
+        L.omg_level_rm_configs.argtypes = [P, i32, P, i32, P]
         for name in EXPORTS:
             if name not in ("omg_default_options", "omg_destroy", "omg_strerror"):
                 getattr(L, name).restype = ctypes.c_int
@@ -293,6 +295,28 @@ class Solver:
         out = np.zeros(16, dtype=np.int32)
         _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
         return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:])
+
+    def rm_configs(self, l=0):
+        """Co-resident launch configurations of level l's persistent RM kernel."""
+        n = ctypes.c_int32()
+        _check(lib().omg_level_rm_configs(self._h, l, None, 0, ctypes.byref(n)), "rm_configs")
+        out = np.zeros(4 * max(n.value, 1), dtype=np.int32)
+        _check(lib().omg_level_rm_configs(self._h, l, out.ctypes.data, n.value, ctypes.byref(n)), "rm_configs")
+        return [tuple(int(v) for v in out[4 * i:4 * i + 4]) for i in range(n.value)]
+
+    def rm_step(self, l, W, w, z, r, cfg=None):
+        """One RM step on flat vectors (see omg_level_rm_step): returns
+        (Wk, r_new, betas, gamma, alpha)."""
+        import torch
+        k = 0 if W is None else W.shape[0]
+        Wk = torch.empty_like(w)
+        rn = torch.empty_like(w)
+        coeff = np.zeros(k + 2)
+        c = None if cfg is None else np.ascontiguousarray(np.asarray(cfg, dtype=np.int32))
+        _check(lib().omg_level_rm_step(self._h, l, k, None if W is None else _ptr(W.contiguous()), _ptr(w), _ptr(z),
+                                       _ptr(r), None if c is None else c.ctypes.data, _ptr(Wk), _ptr(rn),
+                                       coeff.ctypes.data), "rm_step")
+        return Wk, rn, coeff[:k], coeff[k], coeff[k + 1]
 
     def dirs(self, l=0):
         import torch

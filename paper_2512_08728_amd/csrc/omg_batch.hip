@@ -295,6 +295,7 @@ omg_status rm_multi(Group& g, const std::vector<int>& act, int l, bool zcor) {
         for (size_t i = i0; i < act.size() && M.ncol < kMaxCols; ++i) {
             if (done[i] || cfg[i].ept != c0.ept || cfg[i].B != c0.B || cfg[i].lead != c0.lead) continue;
             if (M.ncol > 0 && blocks + cfg[i].G > cap) continue;
+            HIP_OK(prepare_slots(LV(g.col[act[i]], l), cfg[i], g.st));
             M.idx[M.ncol] = act[i];
             M.blk0[M.ncol] = blocks;
             M.g0[M.ncol] = LV(g.col[act[i]], l).phase;

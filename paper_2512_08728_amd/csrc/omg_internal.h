@@ -15,6 +15,10 @@ namespace omg {
 // deterministic two-stage reductions (partials are always summed in the same
 // order, so a result does not depend on timing).
 constexpr int kThreads = 256;
+// Every level work vector and stored direction has kVecPad zero entries past
+// N: the persistent RM kernel covers G * kThreads * EPT >= N entries with
+// EPT <= 20 and reads and writes all of them without masks.
+constexpr int64_t kVecPad = 20 * kThreads;
 constexpr int kMaxRedBlocks = 1024;
 // largest number of stored directions per grid-wide exchange in the
 // persistent RM kernel, and the stride of the stored intra-block Gram entries
@@ -142,6 +146,10 @@ struct Level {
     int rmc_multi_m = 0;
     unsigned* bar = nullptr;           // [2]: [1] = abort flag of the persistent kernel's waits
     unsigned long long* xslots = nullptr; // exchange words (kRmSlotWords)
+    // layout (blocks, words per block, exchange form) of the last launch on
+    // xslots: a stale word is only guaranteed to carry a foreign tag while
+    // the layout stays the same, so the words are reset when it changes
+    int slot_G = -1, slot_SW = -1, slot_lead = -1;
     unsigned long long phase = 0;      // next exchange phase of this level (host counter)
     // implicit search directions (persistent levels): raw directions + MGS coefficients
     double* hist = nullptr;            // packed beta rows, ucap*(ucap-1)/2
@@ -284,6 +292,9 @@ constexpr int kMaxRmConfigs = 96;
 int rm_persistent_candidates(int64_t N, RmConfig* out, int cap);
 bool rm_persistent_config(int64_t N, RmConfig* cfg);
 hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st);
+// Reset L's exchange words to "empty" if configuration c lays them out
+// differently from the last launch on them (call before every launch).
+hipError_t prepare_slots(Level& L, const RmConfig& c, hipStream_t st);
 // d = coefficients of x = sum_k alpha_k z_k in the raw directions
 hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,
                         hipStream_t st);

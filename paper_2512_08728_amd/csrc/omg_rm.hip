@@ -39,6 +39,7 @@
 // at once; the launch is an ordinary one (cooperative launches carry a large
 // per-launch cost on this runtime).
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 
 #include "omg_internal.h"
@@ -175,6 +176,21 @@ __device__ __forceinline__ void collect(unsigned long long* slots, int G, int bi
 // Every vector is handled as a flat array of N entries (RM has no cell
 // structure): thread t of a grid of T threads owns entries t + j T, j < EPT,
 // so consecutive threads touch consecutive addresses.
+// Vector accesses of the persistent kernel go through raw buffer
+// instructions: a resource (base address, size) in scalar registers, the
+// uniform part of the offset (entry j of every thread: j T 8 bytes) as a
+// scalar offset, and one 32-bit per-thread offset shared by all accesses,
+// so no per-entry 64-bit addresses occupy vector registers. The resource's
+// fourth word is the raw-buffer format of the gfx9 family.
+constexpr int kBufWord3 = 0x00020000;
+typedef unsigned int BufData __attribute__((vector_size(2 * sizeof(unsigned int)))); // the 64-bit payload
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int bytes) {
+    const uint64_t v = (uint64_t)p; // every lane holds the same pointer: keep it in scalar registers
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0, bytes, kBufWord3);
+}
+
 // The RM of one vector set on G blocks; this block is block `bid` of them.
 template <int EPT, int B, bool LEAD>
 __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int bid, double* sh) {
@@ -183,24 +199,42 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
     const int64_t t0 = (int64_t)bid * blockDim.x + threadIdx.x;
     const int64_t N = A.N;
     const int k = A.k;
+    // Entry j of this thread is entry t0 + j T of every vector (byte j T 8 +
+    // t0 8). The vectors carry kVecPad zero entries past N and this grid
+    // covers fewer than N + kVecPad entries, so loads need no masks; stores
+    // are masked to [0, N), which keeps the tails zero.
+    const int toff = (int)t0 * 8;
+    const int stride = (int)T * 8;
+    const int bytes = (int)((N + kVecPad) * 8);
+    auto ld = [&](__amdgpu_buffer_rsrc_t r, int j) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, toff, j * stride, 0));
+    };
+    auto st = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        if (t0 + j * T < N) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufData, v), r, toff, j * stride, 0);
+    };
     double w[EPT], a[B][EPT], an[B][EPT];
-    bool valid[EPT];
     // w in registers; the raw direction z~ is stored as direction k
-    double* Zk = A.Zk;
+    {
+        const __amdgpu_buffer_rsrc_t rw = buffer_of(A.w, bytes), rz = buffer_of(A.z, bytes),
+                                     rk = buffer_of(A.Zk, bytes);
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int64_t e = t0 + j * T;
-        valid[j] = e < N;
-        w[j] = valid[j] ? A.w[e] : 0.0;
-        if (valid[j]) Zk[e] = A.z[e];
+        for (int j = 0; j < EPT; ++j) {
+            w[j] = ld(rw, j);
+            st(rk, j, ld(rz, j));
+        }
     }
     auto load_block = [&](double (&dst)[B][EPT], int j0) {
 #pragma unroll
         for (int t = 0; t < B; ++t) {
-            const bool have = j0 + t < k;
-            const double* Wt = have ? A.Wp[j0 + t] : nullptr;
+            const bool have = j0 + t < k; // uniform
+            if (have) {
+                const __amdgpu_buffer_rsrc_t rt = buffer_of(A.Wp[j0 + t], bytes);
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) dst[t][j] = (have && valid[j]) ? Wt[t0 + j * T] : 0.0;
+                for (int j = 0; j < EPT; ++j) dst[t][j] = ld(rt, j);
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) dst[t][j] = 0.0;
+            }
         }
     };
     const int nblk = (k + B - 1) / B;
@@ -290,15 +324,12 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
     double s_a = 0.0, s_g[B];
 #pragma unroll
     for (int t = 0; t < B; ++t) s_g[t] = 0.0;
+    const __amdgpu_buffer_rsrc_t rwk = buffer_of(A.Wk, bytes), rr = buffer_of(A.r, bytes);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         w[j] *= gamma;
-        double rv = 0.0;
-        if (valid[j]) {
-            const int64_t e = t0 + j * T;
-            A.Wk[e] = w[j];
-            rv = A.r[e];
-        }
+        st(rwk, j, w[j]);
+        const double rv = ld(rr, j);
         an[0][j] = rv; // r kept in registers
         s_a = fma(w[j], rv, s_a);
 #pragma unroll
@@ -316,7 +347,7 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const double rn = fma(-alpha, w[j], an[0][j]);
-        if (valid[j]) A.r[t0 + j * T] = rn;
+        st(rr, j, rn);
         s_r = fma(rn, rn, s_r);
     }
     s_r = bsum(s_r, sh);
@@ -451,6 +482,8 @@ static const void* rm_kernel(bool multi) {
 // Instantiations: entries per thread EPT, MGS block B in {1, 2, 4}, exchange
 // form (all-to-all or leader).
 constexpr int kEpts[] = {1, 2, 4, 8, 10, 16, 20};
+// byte offsets of the buffer accesses are 32-bit
+static_assert(((int64_t)kMaxRedBlocks * kThreads * 20 + kVecPad) * 8 < (int64_t)1 << 31, "RM offsets");
 template <int EPT, bool LEAD>
 static const void* pick_b(int b, bool multi) {
     if (b == 4) return rm_kernel<EPT, 4, LEAD>(multi);
@@ -525,6 +558,22 @@ bool rm_persistent_config(int64_t N, RmConfig* cfg) {
     if (rm_persistent_candidates(N, c, kMaxRmConfigs) < 1) return false;
     *cfg = c[0];
     return true;
+}
+
+// Every word written in a phase g of a fixed layout is overwritten two
+// phases later, so a reader waiting for phase g can only meet the tag of g-2
+// or g itself. A word last written under another layout (other grid, other
+// words per block, other exchange form) can hold any phase's value; the
+// words are therefore set to the empty tag (3) whenever the layout changes.
+hipError_t prepare_slots(Level& L, const RmConfig& c, hipStream_t st) {
+    const int sw = c.B + 1;
+    if (L.slot_G == c.G && L.slot_SW == sw && L.slot_lead == c.lead) return hipSuccess;
+    hipError_t e = hipMemsetAsync(L.xslots, 0xFF, sizeof(unsigned long long) * kRmSlotWords, st);
+    if (e != hipSuccess) return e;
+    L.slot_G = c.G;
+    L.slot_SW = sw;
+    L.slot_lead = c.lead;
+    return hipSuccess;
 }
 
 hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st) {

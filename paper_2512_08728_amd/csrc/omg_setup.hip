@@ -556,7 +556,7 @@ static omg_status dmalloc(void** p, size_t bytes) {
 }
 
 omg_status omg_alloc_level_vectors(omg_solver* s, Level& L) {
-    const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(L.N, 1);
+    const size_t vb = sizeof(double) * (size_t)(std::max<int64_t>(L.N, 1) + kVecPad);
     OMG_TRY(dmalloc((void**)&L.b, vb));
     OMG_TRY(dmalloc((void**)&L.xout, vb));
     OMG_TRY(dmalloc((void**)&L.scal, sizeof(double) * S_COUNT));
@@ -568,6 +568,8 @@ omg_status omg_alloc_level_vectors(omg_solver* s, Level& L) {
     OMG_TRY(dmalloc((void**)&L.t, vb));
     OMG_TRY(dmalloc((void**)&L.t2, vb));
     OMG_TRY(dmalloc((void**)&L.zcor, vb));
+    for (double* v : {L.b, L.xout, L.r, L.x, L.z, L.w, L.t, L.t2, L.zcor}) // zero tails
+        OMG_TRY_HIP(hipMemsetAsync(v, 0, vb, s->stream));
     OMG_TRY(dmalloc((void**)&L.part, sizeof(double) * 16 * kMaxRedBlocks));
     return OMG_OK;
 }

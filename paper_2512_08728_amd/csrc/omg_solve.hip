@@ -327,6 +327,7 @@ static omg_status tune_rm(omg_solver* s, int l) {
             for (int r = 0; r <= reps && res == OMG_OK; ++r) {
                 if (r == 1 && hipEventRecord(e0, st) != hipSuccess) res = OMG_EHIP;
                 a.g0 = L.phase;
+                if (res == OMG_OK && prepare_slots(L, c[q], st) != hipSuccess) res = OMG_EHIP;
                 if (res == OMG_OK && launch_rm_persistent(c[q], a, st) != hipSuccess) res = OMG_EHIP;
                 L.phase += (unsigned long long)((kt + c[q].B - 1) / c[q].B) + 2;
             }
@@ -499,16 +500,21 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
     if (k < 0) return OMG_EINVAL;
     if (k < (int)L.W.size()) return OMG_OK;
     const int chunk = 32;
+    const size_t vn = (size_t)(L.N + kVecPad); // with the zero tail
     while (k >= (int)L.W.size()) { // as many chunks as index k needs
         double* mem = nullptr;
-        if (hipMalloc((void**)&mem, sizeof(double) * (size_t)L.N * 2 * chunk) != hipSuccess) {
+        if (hipMalloc((void**)&mem, sizeof(double) * vn * 2 * chunk) != hipSuccess) {
             (void)hipGetLastError();
             return OMG_ENOMEM;
         }
+        // zero tails; finished before any stream (the overlap form's coarse
+        // stream included) can use the chunk
+        HIP_OK(hipMemsetAsync(mem, 0, sizeof(double) * vn * 2 * chunk, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
         L.chunks.push_back(mem);
         for (int c = 0; c < chunk; ++c) {
-            L.W.push_back(mem + (size_t)L.N * (2 * c));
-            L.Z.push_back(mem + (size_t)L.N * (2 * c + 1));
+            L.W.push_back(mem + vn * (2 * c));
+            L.Z.push_back(mem + vn * (2 * c + 1));
         }
     }
     // device copies of the pointer arrays (read by the persistent RM kernel)
@@ -525,7 +531,6 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
     L.dWp = dW;
     L.dZp = dZ;
     L.dcap = L.W.size();
-    (void)s;
     return OMG_OK;
 }
 
@@ -577,6 +582,7 @@ static omg_status rm_apply(omg_solver* s, int l, double* z, hipStream_t st) {
         a.alphas = L.alphas;
         a.gram = L.gram;
         probe_begin(s, OMG_K_RMP, l, st);
+        HIP_OK(prepare_slots(L, L.rmc, st));
         HIP_OK(launch_rm_persistent(L.rmc, a, st));
         probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
         L.phase += (unsigned long long)((L.k + L.rmc.B - 1) / L.rmc.B) + 2;
@@ -1020,6 +1026,95 @@ extern "C" omg_status omg_solve_backward(omg_solver* s, const double* u, const d
 }
 
 // ------------------------------------------------------------------ inspection
+// One RM step of level l's persistent kernel on caller data (flat vectors:
+// RM has no cell structure): k directions W (rows of a k x N device array,
+// orthonormal), w = A z, z, r; configuration cfg[4] = (blocks, entries per
+// thread, directions per exchange, leader exchange) or NULL for the tuned
+// one. Outputs: Wk (new direction), r_new, and host coeff[k + 2] =
+// (beta_0..beta_{k-1}, gamma, alpha).
+extern "C" omg_status omg_level_rm_step(omg_solver* s, int32_t level, int32_t k, const double* W, const double* w,
+                                        const double* z, const double* r, const int32_t* cfg, double* Wk,
+                                        double* r_new, double* coeff) {
+    if (!s || level < 0 || level >= s->nlev || k < 0 || !w || !z || !r || !Wk || !r_new || !coeff || (k > 0 && !W))
+        return OMG_EINVAL;
+    Level& L = s->lev[level];
+    if (!L.persist || k + 1 > L.ucap) return OMG_EUNSUPPORTED;
+    RmConfig c = L.rmc;
+    if (cfg) {
+        RmConfig cand[kMaxRmConfigs];
+        const int nc = rm_persistent_candidates(L.N, cand, kMaxRmConfigs);
+        bool found = false;
+        for (int q = 0; q < nc && !found; ++q)
+            if (cand[q].G == cfg[0] && cand[q].ept == cfg[1] && cand[q].B == cfg[2] && cand[q].lead == cfg[3]) {
+                c = cand[q];
+                found = true;
+            }
+        if (!found) return OMG_EINVAL; // only co-resident configurations are launched
+    }
+    hipStream_t st = s->stream;
+    OMG_TRY(ensure_dir(s, L, k));
+    if ((int)L.W.size() <= k) return OMG_EINVAL;
+    for (int i = 0; i < k; ++i)
+        HIP_OK(hipMemcpyAsync(L.W[i], W + (size_t)i * L.N, sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(L.w, w, sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(L.z, z, sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(L.r, r, sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
+    // the stored intra-block Gram entries of orthonormal directions are zero
+    HIP_OK(launch_fill(L.gram, 0.0, (int64_t)L.ucap * kGramStride, st));
+    RmArgs a;
+    a.N = L.N;
+    a.k = k;
+    a.Wp = L.dWp;
+    a.Wk = L.W[k];
+    a.Zk = L.Z[k];
+    a.w = L.w;
+    a.z = L.z;
+    a.r = L.r;
+    a.slots = L.xslots;
+    a.g0 = L.phase;
+    a.part_rn = L.part + 4 * kMaxRedBlocks;
+    a.breakdown = s->opt.breakdown;
+    a.scal = L.scal;
+    a.abort_flag = L.bar + 1;
+    a.hist = L.hist;
+    a.gammas = L.gammas;
+    a.alphas = L.alphas;
+    a.gram = L.gram;
+    HIP_OK(prepare_slots(L, c, st));
+    HIP_OK(launch_rm_persistent(c, a, st));
+    L.phase += (unsigned long long)((k + c.B - 1) / c.B) + 2;
+    HIP_OK(hipMemcpyAsync(Wk, L.W[k], sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(r_new, L.r, sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
+    std::vector<double> h((size_t)k + 2);
+    if (k > 0) HIP_OK(hipMemcpyAsync(h.data(), L.hist + (size_t)k * (k - 1) / 2, sizeof(double) * k,
+                                     hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&h[k], L.gammas + k, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&h[k + 1], L.alphas + k, sizeof(double), hipMemcpyDeviceToHost, st));
+    unsigned flags[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (flags[1]) return OMG_EHIP;
+    for (int i = 0; i < k + 2; ++i) coeff[i] = h[i];
+    return OMG_OK;
+}
+
+// Co-resident RM launch configurations of level l (host out[4*cap]: blocks,
+// entries per thread, directions per exchange, leader); count in *n.
+extern "C" omg_status omg_level_rm_configs(const omg_solver* s, int32_t level, int32_t* out, int32_t cap,
+                                           int32_t* n) {
+    if (!s || level < 0 || level >= s->nlev || !n) return OMG_EINVAL;
+    const Level& L = s->lev[level];
+    RmConfig cand[kMaxRmConfigs];
+    const int nc = L.persist ? rm_persistent_candidates(L.N, cand, kMaxRmConfigs) : 0;
+    *n = nc;
+    for (int q = 0; q < nc && q < cap && out; ++q) {
+        out[4 * q] = cand[q].G;
+        out[4 * q + 1] = cand[q].ept;
+        out[4 * q + 2] = cand[q].B;
+        out[4 * q + 3] = cand[q].lead;
+    }
+    return OMG_OK;
+}
 extern "C" omg_status omg_level_info(const omg_solver* s, int32_t level, int32_t* n_cells, int32_t* ell_width,
                                      int32_t* k_dirs) {
     if (!s || level < 0 || level >= s->nlev) return OMG_EINVAL;
@@ -1300,7 +1395,8 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
             a.gammas = L.gammas;
             a.alphas = L.alphas;
             a.gram = L.gram;
-            hipError_t e = launch_rm_persistent(L.rmc, a, st);
+            hipError_t e = prepare_slots(L, L.rmc, st);
+            if (e == hipSuccess) e = launch_rm_persistent(L.rmc, a, st);
             L.phase += (unsigned long long)((kb + L.rmc.B - 1) / L.rmc.B) + 2;
             return e;
         }

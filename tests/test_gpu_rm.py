@@ -1,0 +1,66 @@
+"""The persistent residual-minimisation kernel (Algorithm 1 after w = A z) in
+every co-resident launch configuration (entries per thread, directions per
+grid exchange, exchange form, grid) against the sequential modified
+Gram-Schmidt step written out in numpy (FP64): MGS coefficients beta_i =
+W_i . w (w updated after each), gamma = 1/||w||, the new direction gamma w,
+alpha = w_k . r and the updated residual. k covers no direction, fewer
+directions than one exchange block, and partial last blocks."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def omg():
+    import paper_2512_08728_amd as m
+    return m
+
+
+def reference(W, w, r):
+    w = w.copy()
+    betas = []
+    for Wi in W:
+        b = Wi @ w
+        betas.append(b)
+        w -= b * Wi
+    gamma = 1.0 / np.linalg.norm(w)
+    wk = gamma * w
+    alpha = wk @ r
+    return np.array(betas), gamma, wk, alpha, r - alpha * wk
+
+
+@pytest.mark.parametrize("n,p", [(8, 1), (16, 2)])
+def test_rm_step_every_configuration(n, p):
+    prob = synth.make_problem(n, p, n_levels=2)
+    nu = synth.nu_sphere(n, n, n, prob.h)
+    g = omg().Solver.from_sip(omg().Solver.make_grid(n, n, n, p, 2, prob.h), torch.tensor(nu, device="cuda"))
+    N = prob.n_dofs
+    rng = np.random.default_rng(7)
+    configs = g.rm_configs(0)
+    assert configs, "finest level uses the persistent kernel"
+    for k in (0, 1, 4, 7, 40):
+        W = np.linalg.qr(rng.standard_normal((N, k)))[0].T.copy() if k else np.zeros((0, N))
+        w = rng.standard_normal(N)
+        z = rng.standard_normal(N)
+        r = rng.standard_normal(N)
+        betas, gamma, wk, alpha, rn = reference(W, w, r)
+        dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+        for cfg in configs:
+            Wk, rn_g, b_g, gm_g, al_g = g.rm_step(0, dev(W) if k else None, dev(w), dev(z), dev(r), cfg)
+            Wk, rn_g = Wk.cpu().numpy(), rn_g.cpu().numpy()
+            what = f"k={k} config={cfg}"
+            assert np.abs(b_g - betas).max(initial=0) <= 1e-12 * np.abs(w).max(), what
+            assert abs(gm_g - gamma) <= 1e-12 * gamma, what
+            assert abs(al_g - alpha) <= 1e-12 * np.linalg.norm(r), what
+            assert np.abs(Wk - wk).max() <= 1e-12, what
+            assert np.abs(rn_g - rn).max() <= 1e-12 * np.abs(r).max(), what

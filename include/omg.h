@@ -183,15 +183,16 @@ omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
  * fp32 = 1 uses the FP32 operator copies (inputs rounded to FP32, FP32
  * arithmetic, results widened to FP64). OMG_EUNSUPPORTED for bs > 16. */
 enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
-/* Launch configurations the autotuners chose on a level, host shapes[16]:
+/* Launch configurations the autotuners chose on a level, host shapes[17]:
  * [0..11] the multi-right-hand-side kernels (tuned on the first batched
  * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
  * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..5 is
  * (wavefronts per block, 16-column tiles per wavefront) = (4,2), (2,2),
- * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..15] the persistent
+ * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..16] the persistent
  * residual-minimisation kernel (tuned at setup): blocks, vector entries per
  * thread, directions per grid exchange, exchange form (0 all-to-all, 1
- * leader block); -1 if the level does not use it. */
+ * leader block), compute waves per block of the exchange-wave form (0:
+ * plain form); -1 if the level does not use it. */
 omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
 omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
                            const double *X, const double *B, double *Y);
@@ -199,8 +200,9 @@ omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrh
  * persistent kernel on caller data: the vectors are flat device arrays of
  * N_l entries (RM has no cell structure); W holds k orthonormal directions
  * as rows of a k x N_l array; cfg (host, nullable) = (blocks, entries per
- * thread, directions per exchange, leader exchange) selects one of the
- * co-resident configurations of omg_level_rm_configs (NULL: the tuned one).
+ * thread, directions per exchange, leader exchange, compute waves) selects
+ * one of the co-resident configurations of omg_level_rm_configs (NULL: the
+ * tuned one).
  * Outputs: Wk (the new orthonormal direction), r_new, and host
  * coeff[k + 2] = (beta_0..beta_{k-1}, gamma, alpha). The level's own work
  * storage is overwritten. OMG_EUNSUPPORTED if the level does not use the
@@ -209,8 +211,10 @@ omg_status omg_level_rm_step(omg_solver *s, int32_t level, int32_t k, const doub
                              const double *z, const double *r, const int32_t *cfg, double *Wk, double *r_new,
                              double *coeff);
 /* The co-resident launch configurations of level l's persistent RM kernel:
- * host out[4*cap] (blocks, entries per thread, directions per exchange,
- * leader), their count in *n (out nullable to query the count). */
+ * host out[5*cap] (blocks, entries per thread, directions per exchange,
+ * leader exchange, compute waves: 0 for the plain form, 3 or 4 for the
+ * exchange-wave form, where one more wave per block performs the grid
+ * exchanges), their count in *n (out nullable to query the count). */
 omg_status omg_level_rm_configs(const omg_solver *s, int32_t level, int32_t *out, int32_t cap, int32_t *n);
 /* Stored directions of level l after the last solve (device, cell-major,
  * [k][N] each); W or Z nullable. */

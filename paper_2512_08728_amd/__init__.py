@@ -291,8 +291,9 @@ class Solver:
 
     def level_tuning(self, l):
         """Autotuned launch configurations of level l: (multi-RHS shapes
-        [op][fp32][two tiles], (RM blocks, entries per thread, MGS block, leader exchange))."""
-        out = np.zeros(16, dtype=np.int32)
+        [op][fp32][two tiles], (RM blocks, entries per thread, MGS block, leader exchange,
+        compute waves of the exchange-wave form or 0))."""
+        out = np.zeros(17, dtype=np.int32)
         _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
         return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:])
 
@@ -300,9 +301,9 @@ class Solver:
         """Co-resident launch configurations of level l's persistent RM kernel."""
         n = ctypes.c_int32()
         _check(lib().omg_level_rm_configs(self._h, l, None, 0, ctypes.byref(n)), "rm_configs")
-        out = np.zeros(4 * max(n.value, 1), dtype=np.int32)
+        out = np.zeros(5 * max(n.value, 1), dtype=np.int32)
         _check(lib().omg_level_rm_configs(self._h, l, out.ctypes.data, n.value, ctypes.byref(n)), "rm_configs")
-        return [tuple(int(v) for v in out[4 * i:4 * i + 4]) for i in range(n.value)]
+        return [tuple(int(v) for v in out[5 * i:5 * i + 5]) for i in range(n.value)]
 
     def rm_step(self, l, W, w, z, r, cfg=None):
         """One RM step on flat vectors (see omg_level_rm_step): returns

@@ -203,7 +203,7 @@ RmConfig multi_config(const RmConfig& tuned, int64_t N, int m) {
     RmConfig best = tuned;
     int best_cols = 0;
     for (int e : epts) {
-        if (e < tuned.ept) continue;
+        if (e < std::min(tuned.ept, 20)) continue;
         for (int b : {tuned.B, 2, 1}) {
             if (b > tuned.B) continue;
             const int G = (int)((N + (int64_t)kThreads * e - 1) / ((int64_t)kThreads * e));
@@ -310,7 +310,7 @@ omg_status rm_multi(Group& g, const std::vector<int>& act, int l, bool zcor) {
         P->kcount[OMG_K_RMP][l]++;
         for (int i : members) {
             Level& L = LV(g.col[act[i]], l);
-            L.phase += (unsigned long long)((k + c0.B - 1) / c0.B) + 2;
+            L.phase += rm_phases(k, c0.B);
             L.Grn = cfg[i].G;
             L.k++;
         }
@@ -838,6 +838,7 @@ extern "C" omg_status omg_level_tuning(const omg_solver* s, int32_t level, int32
     shapes[q++] = L.persist ? L.rmc.ept : -1;
     shapes[q++] = L.persist ? L.rmc.B : -1;
     shapes[q++] = L.persist ? L.rmc.lead : -1;
+    shapes[q++] = L.persist ? L.rmc.cw : -1;
     return OMG_OK;
 }
 

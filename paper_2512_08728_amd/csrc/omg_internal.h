@@ -18,7 +18,7 @@ constexpr int kThreads = 256;
 // Every level work vector and stored direction has kVecPad zero entries past
 // N: the persistent RM kernel covers G * kThreads * EPT >= N entries with
 // EPT <= 20 and reads and writes all of them without masks.
-constexpr int64_t kVecPad = 20 * kThreads;
+constexpr int64_t kVecPad = 32 * kThreads;
 constexpr int kMaxRedBlocks = 1024;
 // largest number of stored directions per grid-wide exchange in the
 // persistent RM kernel, and the stride of the stored intra-block Gram entries
@@ -63,7 +63,12 @@ struct RmConfig {
     int ept = 0;  // vector entries per thread
     int B = 1;    // MGS directions resolved per grid exchange
     int lead = 0; // exchange form: 0 all-to-all, 1 leader block
+    int cw = 0;   // compute waves per block of the exchange-wave form (0: plain form)
 };
+// Grid exchanges (phases) of one persistent RM launch with k stored
+// directions: one per MGS block of B directions, then one for the norm of
+// the orthogonalised vector, its dot product with r and its Gram entries.
+inline unsigned long long rm_phases(int k, int B) { return (unsigned long long)((k + B - 1) / B) + 1; }
 // exchange words: two sets of [kMaxRedBlocks][kRmBlock + 1] block words, then
 // two sets of kRmBlock + 1 total words (leader form)
 constexpr size_t kRmSlotWords = 2 * (size_t)kMaxRedBlocks * (kRmBlock + 1) + 2 * (kRmBlock + 1);

@@ -46,16 +46,32 @@
 
 namespace omg {
 
-constexpr unsigned kSpinMax = 1u << 25;
+constexpr unsigned kSpinMax = 1u << 22;
 
 __device__ __forceinline__ unsigned long long tag_pack(double v, unsigned tag) {
     return ((unsigned long long)__double_as_longlong(v) & ~3ull) | tag;
 }
 __device__ __forceinline__ double tag_value(unsigned long long b) { return __longlong_as_double(b & ~3ull); }
 
+// v from another lane of the same row by a DPP permutation (both halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// Wavefront sum by pairwise exchanges (each step adds the value of a partner
+// lane, the partner relation being symmetric), so every lane ends with the
+// same bits: lane i ^ 1, i ^ 2 (quad permutations), 7 - i and 15 - i within
+// rows (half-row and row mirrors), then i ^ 16 and i ^ 32.
 __device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 // Block sums of nv values at once (one pair of barriers for all of them);
@@ -201,16 +217,21 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
     const int k = A.k;
     // Entry j of this thread is entry t0 + j T of every vector (byte j T 8 +
     // t0 8). The vectors carry kVecPad zero entries past N and this grid
-    // covers fewer than N + kVecPad entries, so loads need no masks; stores
-    // are masked to [0, N), which keeps the tails zero.
+    // covers fewer than N + kVecPad entries, so loads need no masks. Computed
+    // values are stored to [0, N) only, which keeps the tails zero whatever
+    // the data; the copy of z~ moves its (zero) tail along unmasked, so that
+    // its loads are all issued before the first store.
     const int toff = (int)t0 * 8;
     const int stride = (int)T * 8;
     const int bytes = (int)((N + kVecPad) * 8);
     auto ld = [&](__amdgpu_buffer_rsrc_t r, int j) -> double {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, toff, j * stride, 0));
     };
+    auto st_all = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufData, v), r, toff, j * stride, 0);
+    };
     auto st = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
-        if (t0 + j * T < N) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufData, v), r, toff, j * stride, 0);
+        if (t0 + j * T < N) st_all(r, j, v);
     };
     double w[EPT], a[B][EPT], an[B][EPT];
     // w in registers; the raw direction z~ is stored as direction k
@@ -220,8 +241,10 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             w[j] = ld(rw, j);
-            st(rk, j, ld(rz, j));
+            an[0][j] = ld(rz, j);
         }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) st_all(rk, j, an[0][j]);
     }
     auto load_block = [&](double (&dst)[B][EPT], int j0) {
 #pragma unroll
@@ -238,13 +261,21 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
         }
     };
     const int nblk = (k + B - 1) / B;
+    const int gk = k % B; // directions of the new direction's MGS block stored before it
+    const __amdgpu_buffer_rsrc_t rr = buffer_of(A.r, bytes);
     unsigned long long g = A.g0;
     double vals[SW];
-    // phase g0: dots of the first block and ||w||^2; the next block is loaded
-    // meanwhile. Block b+2 is requested as soon as block b+1 becomes current,
-    // so loads stay in flight through every reduction, publish and wait.
+    // phase g0: dots of the first block and ||w||^2 (with no stored direction:
+    // w.r and ||w||^2, the only exchange). The next block is loaded meanwhile;
+    // block b+2 is requested as soon as block b+1 becomes current, and r (kept
+    // in registers) as soon as no block is left to request.
     load_block(a, 0);
-    if (nblk > 1) load_block(an, B);
+    if (nblk > 1) {
+        load_block(an, B);
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) an[0][j] = ld(rr, j);
+    }
     {
         double s_in = 0.0;
 #pragma unroll
@@ -257,10 +288,16 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
             for (int j = 0; j < EPT; ++j) s = fma(a[t][j], w[j], s);
             vals[t] = s;
         }
+        if (k == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) s = fma(w[j], an[0][j], s);
+            vals[0] = s;
+        }
         bsum_n<SW>(vals, SW, sh);
         publish<SW>(A.slots, G, bid, g, vals, SW);
     }
-    double nin2 = 0.0, nout2 = 0.0;
+    double nin2 = 0.0, nout2 = 0.0, wr = 0.0;
     double tot[SW];
     for (int b = 0; b < nblk; ++b) {
         const int j0 = b * B;
@@ -289,7 +326,12 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
             for (int t = 0; t < B; ++t)
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) a[t][j] = an[t][j];
-            if (b + 2 < nblk) load_block(an, j0 + 2 * B);
+            if (b + 2 < nblk) {
+                load_block(an, j0 + 2 * B);
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) an[0][j] = ld(rr, j);
+            }
 #pragma unroll
             for (int t = 0; t < B; ++t) {
                 double s = 0.0;
@@ -300,53 +342,50 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
             bsum_n<SW>(vals, B, sh);
             publish<SW>(A.slots, G, bid, g, vals, B);
         } else {
-            double s = 0.0;
+            // the orthogonalised w: ||w||^2, w.r and the dots with the earlier
+            // directions of the new direction's MGS block (a holds that block)
+            double s = 0.0, q = 0.0;
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) s = fma(w[j], w[j], s);
+            for (int j = 0; j < EPT; ++j) {
+                s = fma(w[j], w[j], s);
+                q = fma(w[j], an[0][j], q);
+            }
             vals[0] = s;
-            bsum_n<SW>(vals, 1, sh);
-            publish<SW>(A.slots, G, bid, g, vals, 1);
-            collect<SW, LEAD>(A.slots, G, bid, g, 1, tot, sh, A.abort_flag);
-            nout2 = tot[0];
+            vals[1] = q;
+#pragma unroll
+            for (int t = 0; t < B - 1; ++t) {
+                double h = 0.0;
+                if (t < gk) {
+#pragma unroll
+                    for (int j = 0; j < EPT; ++j) h = fma(a[t][j], w[j], h);
+                }
+                vals[2 + t] = h;
+            }
+            bsum_n<SW>(vals, SW, sh);
+            publish<SW>(A.slots, G, bid, g, vals, SW);
         }
     }
+    // the last exchange (phase g0 when no direction is stored)
+    collect<SW, LEAD>(A.slots, G, bid, g, SW, tot, sh, A.abort_flag);
     if (k == 0) {
-        collect<SW, LEAD>(A.slots, G, bid, g, SW, tot, sh, A.abort_flag);
         nin2 = tot[B];
         nout2 = nin2;
+        wr = tot[0];
+    } else {
+        nout2 = tot[0];
+        wr = tot[1];
     }
     const double nin = sqrt(nin2), nout = sqrt(nout2);
     const bool keep = nout > A.breakdown * nin; // false for NaN and for nout == 0
     const double gamma = keep ? 1.0 / nout : 0.0;
-    // new direction W_k = gamma w; Gram entries with the earlier directions of its block
-    const int jk0 = k - (k % B), gk = k % B;
-    load_block(a, jk0); // entries t >= gk are zero (directions not stored yet)
-    double s_a = 0.0, s_g[B];
-#pragma unroll
-    for (int t = 0; t < B; ++t) s_g[t] = 0.0;
-    const __amdgpu_buffer_rsrc_t rwk = buffer_of(A.Wk, bytes), rr = buffer_of(A.r, bytes);
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        w[j] *= gamma;
-        st(rwk, j, w[j]);
-        const double rv = ld(rr, j);
-        an[0][j] = rv; // r kept in registers
-        s_a = fma(w[j], rv, s_a);
-#pragma unroll
-        for (int t = 0; t < B; ++t) s_g[t] = fma(a[t][j], w[j], s_g[t]);
-    }
-    ++g;
-    vals[0] = s_a;
-#pragma unroll
-    for (int t = 0; t < B - 1; ++t) vals[1 + t] = s_g[t];
-    bsum_n<SW>(vals, B, sh);
-    publish<SW>(A.slots, G, bid, g, vals, B);
-    collect<SW, LEAD>(A.slots, G, bid, g, B, tot, sh, A.abort_flag);
-    const double alpha = tot[0];
+    const double alpha = gamma * wr; // w_k . r with w_k = gamma w
+    const __amdgpu_buffer_rsrc_t rwk = buffer_of(A.Wk, bytes);
     double s_r = 0.0;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const double rn = fma(-alpha, w[j], an[0][j]);
+        const double wk = w[j] * gamma;
+        st(rwk, j, wk);
+        const double rn = fma(-alpha, wk, an[0][j]);
         st(rr, j, rn);
         s_r = fma(rn, rn, s_r);
     }
@@ -356,7 +395,8 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
         if (bid == 0) {
             A.alphas[k] = alpha;
             A.gammas[k] = gamma;
-            for (int t = 0; t < B - 1; ++t) A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? tot[1 + t] : 0.0;
+            for (int t = 0; t < B - 1; ++t)
+                A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? gamma * tot[2 + t] : 0.0;
             if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
         }
     }
@@ -398,6 +438,426 @@ __global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
     A.alphas = C.alphas;
     A.gram = C.gram;
     rm_body<EPT, B, LEAD>(A, M.blk0[q + 1] - M.blk0[q], (int)blockIdx.x - M.blk0[q], sh);
+}
+
+// ---------------------------------------------------------------------------
+// Exchange-wave form of the same kernel. The vector memory reads of one wave
+// return in issue order, so in the form above a wave's wait for an exchange
+// word also waits for every direction load it issued earlier: a direction
+// costs a load latency plus an exchange latency. Here each block has a fifth
+// wave that issues no vector-stream loads. It performs every grid exchange
+// (block sum of the compute waves' partials, publish, wait, grid sum), the
+// MGS coefficient recursion and the bookkeeping stores, and it reads the
+// direction pointers two MGS blocks ahead into shared memory. The four
+// compute waves stream the vectors and meet it at two barriers per exchange
+// (partials written, results written), so their direction loads stay in
+// flight while it waits. Every sum is formed in the order of the form above
+// (per-thread sums over blocks t, t + 256, ..., wave butterflies, then the
+// four waves in turn), so both forms give bitwise identical results for the
+// same configuration.
+// The form is instantiated with NC = 4 compute waves (the plain form's thread
+// layout, hence its summation order) and with NC = 3 for the largest
+// entries-per-thread counts, where four waves of registers per block would
+// leave only one block per compute unit.
+constexpr int kCwWaves = kThreads / 64; // lane groups of the exchange wave's gather
+// blocks per exchange-wave lane and lane group: grids up to 512 blocks for
+// at most 3 words per block, up to 256 blocks for more
+template <int SW>
+constexpr int cw_rounds() { return SW <= 3 ? 2 : 1; }
+int cw_max_blocks(int B) { return 256 * (B + 1 <= 3 ? 2 : 1); }
+
+struct CwShared {
+    double part[kMaxVals][kCwWaves];     // wave partials of the compute waves
+    double res[kMaxVals];                // results of the last exchange
+    unsigned long long ptr[4][kRmBlock]; // direction pointers of MGS blocks (ring of 4)
+};
+
+// Grid sums of words [0, nw) of one phase (all-to-all), by the exchange wave:
+// lane l reads the words of blocks 64 q + l + 256 r (q < 4, r < R) all at
+// once and re-reads only those not yet carrying the tag. Every lane returns
+// the same totals.
+template <int SW, int R>
+__device__ __forceinline__ void cw_gather(const unsigned long long* base, int G, int nw, unsigned tag,
+                                          unsigned* abort_flag, double (&tot)[SW]) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long v[kCwWaves][R][SW];
+#pragma unroll
+    for (int q = 0; q < kCwWaves; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int w = 0; w < SW; ++w) {
+                const int i = 64 * q + lane + 256 * r;
+                v[q][r][w] = (i < G && w < nw) ? __hip_atomic_load(base + (int64_t)i * SW + w, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT)
+                                               : (unsigned long long)tag; // unused: counts as arrived
+            }
+    unsigned spins = 0;
+    for (;;) {
+        bool ready = true;
+#pragma unroll
+        for (int q = 0; q < kCwWaves; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int w = 0; w < SW; ++w) ready = ready && (unsigned)(v[q][r][w] & 3ull) == tag;
+        if (__all(ready)) break;
+        __builtin_amdgcn_s_sleep(1);
+        ++spins;
+        bool stop = spins > kSpinMax;
+        if ((spins & 127) == 0)
+            stop = stop || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (__any(stop)) {
+            if (lane == 0) __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+#pragma unroll
+        for (int q = 0; q < kCwWaves; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int w = 0; w < SW; ++w)
+                    if ((unsigned)(v[q][r][w] & 3ull) != tag)
+                        v[q][r][w] = __hip_atomic_load(base + (int64_t)(64 * q + lane + 256 * r) * SW + w,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int w = 0; w < SW; ++w) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kCwWaves; ++q) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (64 * q + lane + 256 * r < G && w < nw) s += tag_value(v[q][r][w]);
+            t += wsum(s);
+        }
+        tot[w] = t;
+    }
+}
+
+// Totals of words [0, nw) of phase g by the exchange wave, in either exchange
+// form (see collect); every lane returns the same values.
+template <int SW, int R, bool LEAD>
+__device__ __forceinline__ void cw_collect(unsigned long long* slots, int G, int bid, unsigned long long g, int nw,
+                                           unsigned* abort_flag, double (&tot)[SW]) {
+    const int lane = threadIdx.x & 63;
+    const unsigned tag = (unsigned)(g % 3);
+    const unsigned long long* base = slots + (g & 1) * (unsigned long long)G * SW;
+    unsigned long long* totw = slots + 2ull * kMaxRedBlocks * (kRmBlock + 1) + (g & 1) * SW;
+    if (!LEAD || bid == 0) {
+        cw_gather<SW, R>(base, G, nw, tag, abort_flag, tot);
+        if (LEAD) {
+            double mine = 0.0;
+#pragma unroll
+            for (int w = 0; w < SW; ++w)
+                if (w == lane && w < nw) mine = tot[w];
+            if (lane < SW)
+                __hip_atomic_store(totw + lane, tag_pack(mine, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int w = 0; w < SW; ++w) tot[w] = tag_value(tag_pack(tot[w], tag));
+        }
+    } else {
+        unsigned long long b = (lane < nw) ? __hip_atomic_load(totw + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                           : (unsigned long long)tag;
+        unsigned spins = 0;
+        while (!__all((unsigned)(b & 3ull) == tag)) {
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            bool stop = spins > kSpinMax;
+            if ((spins & 127) == 0)
+                stop = stop || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+            if (__any(stop)) {
+                if (lane == 0) __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            if ((unsigned)(b & 3ull) != tag)
+                b = __hip_atomic_load(totw + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const double mine = tag_value(b);
+#pragma unroll
+        for (int w = 0; w < SW; ++w) tot[w] = (w < nw) ? __shfl(mine, w, 64) : 0.0;
+    }
+}
+
+template <int EPT, int B, bool LEAD, int NC>
+__device__ __forceinline__ void rm_body_cw(const RmArgs& A, const int G, const int bid, CwShared& S) {
+    constexpr int SW = B + 1;
+    constexpr int kThr = 64 * NC; // compute threads per block
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int k = A.k;
+    const int nblk = (k + B - 1) / B;
+    const int gk = k % B; // directions of the new direction's MGS block stored before it
+    if (wid == NC) {
+        // ------------------------------------------------ exchange wave
+        constexpr int R = cw_rounds<SW>();
+        unsigned long long g = A.g0;
+        if (lane < B) {
+            for (int blk = 0; blk < 2; ++blk) {
+                const int j = blk * B + lane;
+                if (j < k) S.ptr[blk][lane] = (unsigned long long)A.Wp[j];
+            }
+        }
+        __syncthreads(); // pointers of blocks 0 and 1 in place
+        double tot[SW];
+        // one exchange of nw words: pointers of MGS block `ahead` are read
+        // meanwhile; gram entries of block `blk` (if any) are returned in gm
+        auto exchange = [&](int nw, int ahead, int blk, double (&gm)[B][B]) {
+            unsigned long long pa = 0;
+            const int ja = ahead * B + lane;
+            const bool want = lane < B && ahead < nblk && ja < k;
+            if (want) pa = (unsigned long long)A.Wp[ja];
+#pragma unroll
+            for (int t = 0; t < B; ++t)
+#pragma unroll
+                for (int m = 0; m < B; ++m) gm[t][m] = 0.0;
+            if (blk >= 0) {
+                const int j0 = blk * B, bb = min(B, k - j0);
+#pragma unroll
+                for (int t = 1; t < B; ++t)
+                    if (t < bb)
+#pragma unroll
+                        for (int m = 0; m < t; ++m) gm[t][m] = A.gram[(int64_t)(j0 + t) * kGramStride + m];
+            }
+            __syncthreads(); // compute waves' partials in place
+            const unsigned tag = (unsigned)(g % 3);
+            double bs = 0.0;
+            if (lane < nw)
+                for (int q = 0; q < NC; ++q) bs += S.part[lane][q];
+            if (lane < SW)
+                __hip_atomic_store(A.slots + ((g & 1) * (unsigned long long)G + bid) * SW + lane, tag_pack(bs, tag),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cw_collect<SW, R, LEAD>(A.slots, G, bid, g, nw, A.abort_flag, tot);
+            if (want) S.ptr[ahead & 3][lane] = pa;
+            ++g;
+        };
+        // MGS coefficients of block blk from its dot products
+        auto coefficients = [&](int blk, const double (&gm)[B][B]) {
+            const int j0 = blk * B, bb = min(B, k - j0);
+            double beta[B];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                double bt = 0.0;
+                if (t < bb) {
+                    bt = tot[t];
+#pragma unroll
+                    for (int m = 0; m < t; ++m) bt = fma(-gm[t][m], beta[m], bt);
+                }
+                beta[t] = bt;
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int t = 0; t < B; ++t) S.res[t] = beta[t];
+                if (bid == 0) // row k of the coefficient history
+                    for (int t = 0; t < bb; ++t) A.hist[(int64_t)k * (k - 1) / 2 + j0 + t] = beta[t];
+            }
+        };
+        double gm[B][B];
+        double nin2 = 0.0, nout2 = 0.0, wr = 0.0;
+        // gamma and alpha of the new direction from ||w|| before and after MGS
+        // and w.r; the bookkeeping of direction k
+        auto finish = [&]() {
+            const double nin = sqrt(nin2), nout = sqrt(nout2);
+            const bool keep = nout > A.breakdown * nin; // false for NaN and for nout == 0
+            const double gamma = keep ? 1.0 / nout : 0.0;
+            const double alpha = gamma * wr; // w_k . r with w_k = gamma w
+            if (lane == 0) {
+                S.res[0] = gamma;
+                S.res[1] = alpha;
+                if (bid == 0) {
+                    A.alphas[k] = alpha;
+                    A.gammas[k] = gamma;
+                    for (int t = 0; t < B - 1; ++t)
+                        A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? gamma * tot[2 + t] : 0.0;
+                    if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
+                }
+            }
+        };
+        exchange(SW, 2, k > 0 ? 0 : -1, gm); // dots of block 0 and ||w||^2 (no direction: w.r, ||w||^2)
+        nin2 = tot[B];
+        if (k > 0) {
+            coefficients(0, gm);
+        } else {
+            nout2 = nin2;
+            wr = tot[0];
+            finish();
+        }
+        __syncthreads(); // results in place
+        for (int b = 0; b < nblk; ++b) {
+            if (b + 1 < nblk) {
+                exchange(min(B, k - (b + 1) * B), b + 3, b + 1, gm);
+                coefficients(b + 1, gm);
+            } else {
+                exchange(SW, nblk, -1, gm); // ||w||^2 after MGS, w.r, Gram dots
+                nout2 = tot[0];
+                wr = tot[1];
+                finish();
+            }
+            __syncthreads(); // results in place
+        }
+        __syncthreads(); // partials of ||r||^2 in place
+        if (lane == 0) {
+            double s = 0.0;
+            for (int q = 0; q < NC; ++q) s += S.part[0][q];
+            A.part_rn[bid] = s;
+        }
+        return;
+    }
+    // ---------------------------------------------------- compute waves
+    const int64_t T = (int64_t)G * kThr;
+    const int64_t t0 = (int64_t)bid * kThr + threadIdx.x;
+    const int64_t N = A.N;
+    const int toff = (int)t0 * 8;
+    const int stride = (int)T * 8;
+    const int bytes = (int)((N + kVecPad) * 8);
+    auto ld = [&](__amdgpu_buffer_rsrc_t r, int j) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, toff, j * stride, 0));
+    };
+    auto st_all = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufData, v), r, toff, j * stride, 0);
+    };
+    auto st = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        if (t0 + j * T < N) st_all(r, j, v);
+    };
+    // wave partials of nv values to shared memory (lane 0 of each wave)
+    auto partials = [&](const double* v, int nv) {
+#pragma unroll
+        for (int i = 0; i < kMaxVals; ++i)
+            if (i < nv) {
+                const double s = wsum(v[i]);
+                if (lane == 0) S.part[i][wid] = s;
+            }
+    };
+    double w[EPT], a[B][EPT], an[B][EPT];
+    {
+        const __amdgpu_buffer_rsrc_t rw = buffer_of(A.w, bytes), rz = buffer_of(A.z, bytes),
+                                     rk = buffer_of(A.Zk, bytes);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            w[j] = ld(rw, j);
+            an[0][j] = ld(rz, j);
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) st_all(rk, j, an[0][j]);
+    }
+    __syncthreads(); // pointers of blocks 0 and 1 in place
+    auto load_block = [&](double (&dst)[B][EPT], int blk) {
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            if (blk * B + t < k) { // uniform
+                const __amdgpu_buffer_rsrc_t rt = buffer_of((const void*)S.ptr[blk & 3][t], bytes);
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) dst[t][j] = ld(rt, j);
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) dst[t][j] = 0.0;
+            }
+        }
+    };
+    const __amdgpu_buffer_rsrc_t rr = buffer_of(A.r, bytes);
+    load_block(a, 0);
+    if (nblk > 1) {
+        load_block(an, 1);
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) an[0][j] = ld(rr, j);
+    }
+    double vals[kMaxVals];
+    {
+        double s_in = 0.0;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) s_in = fma(w[j], w[j], s_in);
+        vals[B] = s_in;
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) s = fma(a[t][j], w[j], s);
+            vals[t] = s;
+        }
+        if (k == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) s = fma(w[j], an[0][j], s);
+            vals[0] = s;
+        }
+        partials(vals, SW);
+    }
+    __syncthreads(); // partials in place
+    __syncthreads(); // results in place
+    for (int b = 0; b < nblk; ++b) {
+        double beta[B];
+#pragma unroll
+        for (int t = 0; t < B; ++t) beta[t] = S.res[t];
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) w[j] = fma(-beta[t], a[t][j], w[j]);
+        if (b + 1 < nblk) {
+#pragma unroll
+            for (int t = 0; t < B; ++t)
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) a[t][j] = an[t][j];
+            if (b + 2 < nblk) {
+                load_block(an, b + 2);
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) an[0][j] = ld(rr, j);
+            }
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) s = fma(a[t][j], w[j], s);
+                vals[t] = s;
+            }
+            partials(vals, B);
+        } else {
+            // the orthogonalised w: ||w||^2, w.r and the dots with the earlier
+            // directions of the new direction's MGS block (a holds that block)
+            double s = 0.0, q = 0.0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                s = fma(w[j], w[j], s);
+                q = fma(w[j], an[0][j], q);
+            }
+            vals[0] = s;
+            vals[1] = q;
+#pragma unroll
+            for (int t = 0; t < B - 1; ++t) {
+                double h = 0.0;
+                if (t < gk) {
+#pragma unroll
+                    for (int j = 0; j < EPT; ++j) h = fma(a[t][j], w[j], h);
+                }
+                vals[2 + t] = h;
+            }
+            partials(vals, SW);
+        }
+        __syncthreads(); // partials in place
+        __syncthreads(); // results in place
+    }
+    const double gamma = S.res[0], alpha = S.res[1];
+    const __amdgpu_buffer_rsrc_t rwk = buffer_of(A.Wk, bytes);
+    double s_r = 0.0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const double wk = w[j] * gamma;
+        st(rwk, j, wk);
+        const double rn = fma(-alpha, wk, an[0][j]);
+        st(rr, j, rn);
+        s_r = fma(rn, rn, s_r);
+    }
+    vals[0] = s_r;
+    partials(vals, 1);
+    __syncthreads(); // partials of ||r||^2 in place
+}
+
+template <int EPT, int B, bool LEAD, int NC>
+__global__ __launch_bounds__(64 * (NC + 1)) void k_rm_cw(RmArgs A) {
+    __shared__ CwShared S;
+    rm_body_cw<EPT, B, LEAD, NC>(A, gridDim.x, blockIdx.x, S);
 }
 
 // Coefficients of x = sum_k alpha_k z_k in the raw directions: with
@@ -473,46 +933,66 @@ __global__ void k_zero(double* __restrict__ out, int64_t N) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) out[e] = 0.0;
 }
 
+// nc: compute waves of the exchange-wave form, 0 for the plain form
 template <int EPT, int B, bool LEAD>
-static const void* rm_kernel(bool multi) {
-    return multi ? reinterpret_cast<const void*>(&k_rm_multi<EPT, B, LEAD>)
-                 : reinterpret_cast<const void*>(&k_rm_blk<EPT, B, LEAD>);
+static const void* rm_kernel(bool multi, int nc) {
+    if constexpr (EPT > 20) { // three compute waves only
+        if constexpr (B <= 2)
+            if (!multi && nc == 3) return reinterpret_cast<const void*>(&k_rm_cw<EPT, B, LEAD, 3>);
+        return nullptr;
+    } else {
+        if (multi) return nc ? nullptr : reinterpret_cast<const void*>(&k_rm_multi<EPT, B, LEAD>);
+        if (nc == 4) return reinterpret_cast<const void*>(&k_rm_cw<EPT, B, LEAD, 4>);
+        return nc ? nullptr : reinterpret_cast<const void*>(&k_rm_blk<EPT, B, LEAD>);
+    }
 }
 
 // Instantiations: entries per thread EPT, MGS block B in {1, 2, 4}, exchange
-// form (all-to-all or leader).
+// form (all-to-all or leader); the exchange-wave form with four compute waves
+// for every EPT of kEpts, with three for kEpts3.
 constexpr int kEpts[] = {1, 2, 4, 8, 10, 16, 20};
+constexpr int kEpts3[] = {24, 28};
+// every grid covers fewer than N + kVecPad entries (64 NC EPT < kVecPad) and
 // byte offsets of the buffer accesses are 32-bit
+static_assert(kThreads * 20 < kVecPad && 64 * 3 * 28 < kVecPad, "RM grid reach");
 static_assert(((int64_t)kMaxRedBlocks * kThreads * 20 + kVecPad) * 8 < (int64_t)1 << 31, "RM offsets");
+static_assert(((int64_t)512 * 64 * 3 * 28 + kVecPad) * 8 < (int64_t)1 << 31, "RM offsets");
 template <int EPT, bool LEAD>
-static const void* pick_b(int b, bool multi) {
-    if (b == 4) return rm_kernel<EPT, 4, LEAD>(multi);
-    if (b == 2) return rm_kernel<EPT, 2, LEAD>(multi);
-    if (b == 1) return rm_kernel<EPT, 1, LEAD>(multi);
+static const void* pick_b(int b, bool multi, int nc) {
+    if (b == 4) return rm_kernel<EPT, 4, LEAD>(multi, nc);
+    if (b == 2) return rm_kernel<EPT, 2, LEAD>(multi, nc);
+    if (b == 1) return rm_kernel<EPT, 1, LEAD>(multi, nc);
     return nullptr;
 }
 template <int EPT>
-static const void* pick_x(int b, int lead, bool multi) {
-    return lead ? pick_b<EPT, true>(b, multi) : pick_b<EPT, false>(b, multi);
+static const void* pick_x(int b, int lead, bool multi, int nc) {
+    return lead ? pick_b<EPT, true>(b, multi, nc) : pick_b<EPT, false>(b, multi, nc);
 }
-static const void* pick(int ept, int b, int lead, bool multi = false) {
+static const void* pick(int ept, int b, int lead, bool multi = false, int nc = 0) {
     switch (ept) {
-    case 1: return pick_x<1>(b, lead, multi);
-    case 2: return pick_x<2>(b, lead, multi);
-    case 4: return pick_x<4>(b, lead, multi);
-    case 8: return pick_x<8>(b, lead, multi);
-    case 10: return pick_x<10>(b, lead, multi);
-    case 16: return pick_x<16>(b, lead, multi);
-    case 20: return pick_x<20>(b, lead, multi);
+    case 1: return pick_x<1>(b, lead, multi, nc);
+    case 2: return pick_x<2>(b, lead, multi, nc);
+    case 4: return pick_x<4>(b, lead, multi, nc);
+    case 8: return pick_x<8>(b, lead, multi, nc);
+    case 10: return pick_x<10>(b, lead, multi, nc);
+    case 16: return pick_x<16>(b, lead, multi, nc);
+    case 20: return pick_x<20>(b, lead, multi, nc);
+    case 24: return nc == 3 ? pick_x<24>(b, lead, multi, nc) : nullptr;
+    case 28: return nc == 3 ? pick_x<28>(b, lead, multi, nc) : nullptr;
     }
     return nullptr;
 }
+// threads per block and compute threads per block of a configuration
+static int rm_block_threads(int nc) { return nc ? 64 * (nc + 1) : kThreads; }
+static int rm_compute_threads(int nc) { return nc ? 64 * nc : kThreads; }
 
 // Blocks of the multi-column kernel in this configuration that fit at once.
 int rm_multi_capacity(int ept, int B, int lead) {
     int dev = 0, cus = 0, per_cu = 0;
     const void* f = pick(ept, B, lead, true);
-    if (!f || hipGetDevice(&dev) != hipSuccess ||
+    hipFuncAttributes fa;
+    if (!f || hipFuncGetAttributes(&fa, f) != hipSuccess || fa.localSizeBytes > 0) return 0; // see candidates
+    if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess)
         return 0;
@@ -530,26 +1010,44 @@ hipError_t launch_rm_multi(int ept, int B, int lead, const RmMulti& M, hipStream
 // Co-resident launch configurations for a level of N entries: grids of at
 // most kMaxRedBlocks blocks whose blocks all fit at once (occupancy query),
 // in order of preference (fewest entries per thread, then the largest MGS
-// block, then at most 512 blocks before larger grids).
+// block, then at most 512 blocks before larger grids; the exchange-wave form
+// before the plain one where both fit). Kernels that need scratch memory are
+// left out: the runtime may limit the waves in flight of such a kernel to what
+// its scratch allocation covers, below what the occupancy query reports.
 int rm_persistent_candidates(int64_t N, RmConfig* out, int cap) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int n = 0;
-    for (int pass = 0; pass < 2; ++pass)
-        for (int e : kEpts) {
-            const int64_t need = (N + (int64_t)kThreads * e - 1) / ((int64_t)kThreads * e);
-            if (pass == 0 ? need > 512 : (need <= 512 || need > kMaxRedBlocks)) continue;
+    auto consider = [&](int pass, int e, int b, int lead, int nc) {
+        const int64_t per = (int64_t)rm_compute_threads(nc) * e;
+        const int64_t need = (N + per - 1) / per;
+        if (pass == 0 ? need > 512 : (need <= 512 || need > kMaxRedBlocks)) return;
+        if (nc && need > cw_max_blocks(b)) return;
+        const void* f = pick(e, b, lead, false, nc);
+        if (!f) return;
+        hipFuncAttributes fa;
+        int per_cu = 0;
+        if (hipFuncGetAttributes(&fa, f) != hipSuccess || fa.localSizeBytes > 0) return;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, rm_block_threads(nc), 0) != hipSuccess ||
+            per_cu < 1)
+            return;
+        // Five-wave blocks do not split evenly over a compute unit's four
+        // SIMDs; two of them per unit have failed to be resident together
+        // although the occupancy query allowed it, so they get one unit each.
+        if (nc == 4) per_cu = 1;
+        if (need > (int64_t)per_cu * cus) return;
+        if (n < cap) out[n++] = RmConfig{(int)need, e, b, lead, nc};
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int e : kEpts)
             for (int b : {4, 2, 1})
-                for (int lead : {0, 1}) {
-                    const void* f = pick(e, b, lead);
-                    int per_cu = 0;
-                    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess ||
-                        per_cu < 1 || need > (int64_t)per_cu * cus)
-                        continue;
-                    if (n < cap) out[n++] = RmConfig{(int)need, e, b, lead};
-                }
-        }
+                for (int lead : {0, 1})
+                    for (int nc : {4, 0}) consider(pass, e, b, lead, nc);
+        for (int e : kEpts3)
+            for (int b : {2, 1})
+                for (int lead : {0, 1}) consider(pass, e, b, lead, 3);
+    }
     return n;
 }
 
@@ -577,12 +1075,14 @@ hipError_t prepare_slots(Level& L, const RmConfig& c, hipStream_t st) {
 }
 
 hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st) {
-    const void* f = pick(c.ept, c.B, c.lead);
+    const void* f = pick(c.ept, c.B, c.lead, false, c.cw);
     const int G = c.G;
-    if (!f) return hipErrorInvalidValue;
+    if (!f || (c.cw && G > cw_max_blocks(c.B)) ||
+        (int64_t)G * rm_compute_threads(c.cw) * c.ept < args.N) // the grid must cover the vectors
+        return hipErrorInvalidValue;
     RmArgs a = args;
     void* params[] = {&a};
-    return hipLaunchKernel(f, dim3(G), dim3(kThreads), params, 0, st);
+    return hipLaunchKernel(f, dim3(G), dim3(rm_block_threads(c.cw)), params, 0, st);
 }
 
 hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,

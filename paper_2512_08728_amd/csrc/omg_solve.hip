@@ -329,7 +329,7 @@ static omg_status tune_rm(omg_solver* s, int l) {
                 a.g0 = L.phase;
                 if (res == OMG_OK && prepare_slots(L, c[q], st) != hipSuccess) res = OMG_EHIP;
                 if (res == OMG_OK && launch_rm_persistent(c[q], a, st) != hipSuccess) res = OMG_EHIP;
-                L.phase += (unsigned long long)((kt + c[q].B - 1) / c[q].B) + 2;
+                L.phase += rm_phases(kt, c[q].B);
             }
             float ms = 0.f;
             if (res == OMG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -337,9 +337,19 @@ static omg_status tune_rm(omg_solver* s, int l) {
                 res = OMG_EHIP;
             tbest = std::min(tbest, ms);
         }
+        if (res == OMG_OK) { // a configuration whose bounded waits expired is not used
+            unsigned flags[2] = {0, 0};
+            if (hipMemcpy(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess) res = OMG_EHIP;
+            if (res == OMG_OK && flags[1]) {
+                if (log) std::fprintf(stderr, "[omg] RM tuning: configuration %d aborted\n", q);
+                tbest = 1e30f;
+                L.slot_G = 0; // words in unknown state: reset before the next launch
+                if (hipMemset(L.bar + 1, 0, sizeof(unsigned)) != hipSuccess) res = OMG_EHIP;
+            }
+        }
         if (log)
-            std::fprintf(stderr, "[omg] RM tuning N=%lld k=%d: G=%d ept=%d B=%d lead=%d: %.1f us\n", (long long)L.N,
-                         kt, c[q].G, c[q].ept, c[q].B, c[q].lead, 1e3 * tbest / 3);
+            std::fprintf(stderr, "[omg] RM tuning N=%lld k=%d: G=%d ept=%d B=%d lead=%d cw=%d: %.1f us\n",
+                         (long long)L.N, kt, c[q].G, c[q].ept, c[q].B, c[q].lead, c[q].cw, 1e3 * tbest / 3);
         if (res == OMG_OK && tbest < best) {
             best = tbest;
             bi = q;
@@ -488,7 +498,7 @@ static double alg_bytes(const omg_solver* s, int kind, int l, int k) {
     case OMG_K_BJ32: return nnzb * bb * 4 + nnzb * 4 + L.n * bb * 4 + 3 * N * 8;
     case OMG_K_BJFIRST: return L.n * bb * 8 + 2 * N * 8;
     case OMG_K_MGS: return 2 * N * 8;                 // W_i and Z_i; w and z stay resident
-    case OMG_K_RMP: return (k + 6.0 + k % L.rmc.B) * N * 8; // W_i (i < k), w, z~ in, W_k, Z~_k out, r in/out, Gram reads
+    case OMG_K_RMP: return (k + 6.0) * N * 8; // W_i (i < k), w, z~ in, W_k, Z~_k out, r in/out
     case OMG_K_RMFIN: return 8 * N * 8;
     case OMG_K_COARSE: return N * N * 8 + 2 * N * 8;
     }
@@ -585,7 +595,7 @@ static omg_status rm_apply(omg_solver* s, int l, double* z, hipStream_t st) {
         HIP_OK(prepare_slots(L, L.rmc, st));
         HIP_OK(launch_rm_persistent(L.rmc, a, st));
         probe_end(s, OMG_K_RMP, l, st, alg_bytes(s, OMG_K_RMP, l, L.k));
-        L.phase += (unsigned long long)((L.k + L.rmc.B - 1) / L.rmc.B) + 2;
+        L.phase += rm_phases(L.k, L.rmc.B);
         s->kcount[OMG_K_RMP][l]++;
         L.Grn = L.rmc.G;
         L.k++;
@@ -1045,7 +1055,8 @@ extern "C" omg_status omg_level_rm_step(omg_solver* s, int32_t level, int32_t k,
         const int nc = rm_persistent_candidates(L.N, cand, kMaxRmConfigs);
         bool found = false;
         for (int q = 0; q < nc && !found; ++q)
-            if (cand[q].G == cfg[0] && cand[q].ept == cfg[1] && cand[q].B == cfg[2] && cand[q].lead == cfg[3]) {
+            if (cand[q].G == cfg[0] && cand[q].ept == cfg[1] && cand[q].B == cfg[2] && cand[q].lead == cfg[3] &&
+                cand[q].cw == cfg[4]) {
                 c = cand[q];
                 found = true;
             }
@@ -1080,9 +1091,10 @@ extern "C" omg_status omg_level_rm_step(omg_solver* s, int32_t level, int32_t k,
     a.gammas = L.gammas;
     a.alphas = L.alphas;
     a.gram = L.gram;
+    HIP_OK(hipMemsetAsync(L.bar + 1, 0, sizeof(unsigned), st)); // each call starts with the abort flag clear
     HIP_OK(prepare_slots(L, c, st));
     HIP_OK(launch_rm_persistent(c, a, st));
-    L.phase += (unsigned long long)((k + c.B - 1) / c.B) + 2;
+    L.phase += rm_phases(k, c.B);
     HIP_OK(hipMemcpyAsync(Wk, L.W[k], sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(r_new, L.r, sizeof(double) * L.N, hipMemcpyDeviceToDevice, st));
     std::vector<double> h((size_t)k + 2);
@@ -1093,13 +1105,17 @@ extern "C" omg_status omg_level_rm_step(omg_solver* s, int32_t level, int32_t k,
     unsigned flags[2] = {0, 0};
     HIP_OK(hipMemcpyAsync(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    if (flags[1]) return OMG_EHIP;
+    if (flags[1]) {
+        L.slot_G = 0; // words in unknown state: reset before the next launch
+        return OMG_EHIP;
+    }
     for (int i = 0; i < k + 2; ++i) coeff[i] = h[i];
     return OMG_OK;
 }
 
-// Co-resident RM launch configurations of level l (host out[4*cap]: blocks,
-// entries per thread, directions per exchange, leader); count in *n.
+// Co-resident RM launch configurations of level l (host out[5*cap]: blocks,
+// entries per thread, directions per exchange, leader, exchange wave); count
+// in *n.
 extern "C" omg_status omg_level_rm_configs(const omg_solver* s, int32_t level, int32_t* out, int32_t cap,
                                            int32_t* n) {
     if (!s || level < 0 || level >= s->nlev || !n) return OMG_EINVAL;
@@ -1108,10 +1124,11 @@ extern "C" omg_status omg_level_rm_configs(const omg_solver* s, int32_t level, i
     const int nc = L.persist ? rm_persistent_candidates(L.N, cand, kMaxRmConfigs) : 0;
     *n = nc;
     for (int q = 0; q < nc && q < cap && out; ++q) {
-        out[4 * q] = cand[q].G;
-        out[4 * q + 1] = cand[q].ept;
-        out[4 * q + 2] = cand[q].B;
-        out[4 * q + 3] = cand[q].lead;
+        out[5 * q] = cand[q].G;
+        out[5 * q + 1] = cand[q].ept;
+        out[5 * q + 2] = cand[q].B;
+        out[5 * q + 3] = cand[q].lead;
+        out[5 * q + 4] = cand[q].cw;
     }
     return OMG_OK;
 }
@@ -1397,7 +1414,7 @@ extern "C" omg_status omg_bench_kernel(omg_solver* s, int32_t kind, int32_t leve
             a.gram = L.gram;
             hipError_t e = prepare_slots(L, L.rmc, st);
             if (e == hipSuccess) e = launch_rm_persistent(L.rmc, a, st);
-            L.phase += (unsigned long long)((kb + L.rmc.B - 1) / L.rmc.B) + 2;
+            L.phase += rm_phases(kb, L.rmc.B);
             return e;
         }
         }

@@ -1,10 +1,12 @@
 """The persistent residual-minimisation kernel (Algorithm 1 after w = A z) in
 every co-resident launch configuration (entries per thread, directions per
-grid exchange, exchange form, grid) against the sequential modified
-Gram-Schmidt step written out in numpy (FP64): MGS coefficients beta_i =
-W_i . w (w updated after each), gamma = 1/||w||, the new direction gamma w,
-alpha = w_k . r and the updated residual. k covers no direction, fewer
-directions than one exchange block, and partial last blocks."""
+grid exchange, exchange form, exchange wave, grid) against the sequential
+modified Gram-Schmidt step written out in numpy (FP64): MGS coefficients
+beta_i = W_i . w (w updated after each), gamma = 1/||w||, the new direction
+gamma w, alpha = w_k . r and the updated residual. k covers no direction,
+fewer directions than one exchange block, and partial last blocks. The
+exchange-wave form with four compute waves sums in the same order as the
+plain form, so the two are compared bit for bit."""
 import numpy as np
 import pytest
 
@@ -64,3 +66,25 @@ def test_rm_step_every_configuration(n, p):
             assert abs(al_g - alpha) <= 1e-12 * np.linalg.norm(r), what
             assert np.abs(Wk - wk).max() <= 1e-12, what
             assert np.abs(rn_g - rn).max() <= 1e-12 * np.abs(r).max(), what
+
+
+@pytest.mark.parametrize("n,p", [(8, 2), (16, 2)])
+def test_rm_step_exchange_wave_is_bitwise_plain(n, p):
+    prob = synth.make_problem(n, p, n_levels=2)
+    nu = synth.nu_sphere(n, n, n, prob.h)
+    g = omg().Solver.from_sip(omg().Solver.make_grid(n, n, n, p, 2, prob.h), torch.tensor(nu, device="cuda"))
+    N = prob.n_dofs
+    rng = np.random.default_rng(8)
+    configs = g.rm_configs(0)
+    pairs = [(c, c[:4] + (0,)) for c in configs if c[4] == 4 and c[:4] + (0,) in configs]
+    assert pairs, "some configuration has both forms"
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    for k in (0, 3, 9, 33):
+        W = np.linalg.qr(rng.standard_normal((N, k)))[0].T.copy() if k else np.zeros((0, N))
+        w, z, r = (rng.standard_normal(N) for _ in range(3))
+        for cw, plain in pairs:
+            a = g.rm_step(0, dev(W) if k else None, dev(w), dev(z), dev(r), cw)
+            b = g.rm_step(0, dev(W) if k else None, dev(w), dev(z), dev(r), plain)
+            what = f"k={k} config={cw}"
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), what
+            assert np.array_equal(a[2], b[2]) and a[3] == b[3] and a[4] == b[4], what

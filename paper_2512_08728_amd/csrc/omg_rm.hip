@@ -207,9 +207,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int b
     return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0, bytes, kBufWord3);
 }
 
+// Direction pointers read into shared memory at the start of a launch (the
+// first kPtrLds of them), so that requesting a direction costs no global
+// memory round trip in the MGS loop.
+constexpr int kPtrLds = 1024;
+
 // The RM of one vector set on G blocks; this block is block `bid` of them.
 template <int EPT, int B, bool LEAD>
-__device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int bid, double* sh) {
+__device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int bid, double* sh,
+                                        unsigned long long* ptab) {
     constexpr int SW = B + 1;
     const int64_t T = (int64_t)G * blockDim.x;
     const int64_t t0 = (int64_t)bid * blockDim.x + threadIdx.x;
@@ -246,12 +252,15 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
 #pragma unroll
         for (int j = 0; j < EPT; ++j) st_all(rk, j, an[0][j]);
     }
+    for (int i = threadIdx.x; i < min(k, kPtrLds); i += blockDim.x) ptab[i] = (unsigned long long)A.Wp[i];
+    __syncthreads();
     auto load_block = [&](double (&dst)[B][EPT], int j0) {
 #pragma unroll
         for (int t = 0; t < B; ++t) {
-            const bool have = j0 + t < k; // uniform
-            if (have) {
-                const __amdgpu_buffer_rsrc_t rt = buffer_of(A.Wp[j0 + t], bytes);
+            const int j = j0 + t;
+            if (j < k) { // uniform
+                const __amdgpu_buffer_rsrc_t rt =
+                    buffer_of(j < kPtrLds ? (const void*)ptab[j] : (const void*)A.Wp[j], bytes);
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) dst[t][j] = ld(rt, j);
             } else {
@@ -405,7 +414,8 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
 template <int EPT, int B, bool LEAD>
 __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
     __shared__ double sh[kMaxVals * (kThreads / 64)];
-    rm_body<EPT, B, LEAD>(A, gridDim.x, blockIdx.x, sh);
+    __shared__ unsigned long long ptab[kPtrLds];
+    rm_body<EPT, B, LEAD>(A, gridDim.x, blockIdx.x, sh, ptab);
 }
 
 // RM of several vector sets (columns of a batched solve, or independent
@@ -415,6 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
 template <int EPT, int B, bool LEAD>
 __global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
     __shared__ double sh[kMaxVals * (kThreads / 64)];
+    __shared__ unsigned long long ptab[kPtrLds];
     int q = 0;
     while (q + 1 < M.ncol && (int)blockIdx.x >= M.blk0[q + 1]) ++q;
     const RmCol& C = M.tab[M.idx[q]];
@@ -437,7 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
     A.gammas = C.gammas;
     A.alphas = C.alphas;
     A.gram = C.gram;
-    rm_body<EPT, B, LEAD>(A, M.blk0[q + 1] - M.blk0[q], (int)blockIdx.x - M.blk0[q], sh);
+    rm_body<EPT, B, LEAD>(A, M.blk0[q + 1] - M.blk0[q], (int)blockIdx.x - M.blk0[q], sh, ptab);
 }
 
 // ---------------------------------------------------------------------------

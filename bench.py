@@ -252,6 +252,20 @@ def main():
                     "avg_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg}
             break
 
+    # SpMV and block-Jacobi sweep against the HBM peak (isolated launches,
+    # algorithmic bytes: stored blocks, column indices, vectors once)
+    hbm_kernels = {}
+    for kind in (omg.K_SPMV, omg.K_BJ):
+        for l in range(min(2, prob.n_levels - 1)):
+            try:
+                ms, by = s.bench_kernel(kind, l, reps=10)
+            except omg.OmgError:
+                continue
+            gbs = by / (ms * 1e-3) / 1e9
+            hbm_kernels[f"{omg.K_NAMES[kind]}@L{l}"] = {"GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                                       "us": round(ms * 1e3, 2), "alg_bytes": by}
+    log(f"SpMV / smoother HBM: {hbm_kernels}")
+
     mixed = None
     if not args.no_mixed:
         mixed = {}
@@ -297,6 +311,7 @@ def main():
                    "iters_fine": rep["iters_fine"], "n_dirs_fine": rep["n_dirs_fine"],
                    "rel_res_true": rep["rel_res_true"], "setup_s": round(t_setup, 3),
                    "wall_s": round(wall, 3)},
+        "hbm_kernels": hbm_kernels,
         "mixed": mixed,
         "batched": batched,
         "roofline": roof,

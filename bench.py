@@ -62,8 +62,11 @@ def profile_traffic(alg_bytes):
     copy = float(kv["copy_bytes_each_way"])
     fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * copy / (float(kv["copy_fetch_kib"]) * 1024)
     write = float(kv["write_kib_per_dispatch"]) * 1024 * copy / (float(kv["copy_write_kib"]) * 1024)
+    kernel = kv.get("kernel", "?")
+    if "`" in kernel:
+        kernel = kernel.split("`")[1]
     return {"bytes": round(fetch + write), "ratio_to_algorithmic": round((fetch + write) / alg_bytes, 4),
-            "note": f"counters of {kv.get('kernel', '?')} over {kv.get('dispatches', '?')} dispatches"}
+            "note": f"counters of {kernel} over {kv.get('dispatches', '?')} dispatches"}
 
 
 def batched_bench(omg, synth, torch):

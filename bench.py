@@ -55,7 +55,8 @@ def profile_traffic(alg_bytes):
     for line in open(PROFILE_RM):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
-            kv[k.strip()] = v.strip().strip("`")
+            v = v.strip()
+            kv[k.strip()] = v.split("`")[1] if v.startswith("`") else v
     sha = rm_kernel_sha()
     if kv.get("source_sha256") != sha:
         return None
@@ -63,8 +64,6 @@ def profile_traffic(alg_bytes):
     fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * copy / (float(kv["copy_fetch_kib"]) * 1024)
     write = float(kv["write_kib_per_dispatch"]) * 1024 * copy / (float(kv["copy_write_kib"]) * 1024)
     kernel = kv.get("kernel", "?")
-    if "`" in kernel:
-        kernel = kernel.split("`")[1]
     return {"bytes": round(fetch + write), "ratio_to_algorithmic": round((fetch + write) / alg_bytes, 4),
             "note": f"counters of {kernel} over {kv.get('dispatches', '?')} dispatches"}
 

@@ -20,7 +20,11 @@
  *   - semi-asynchronous OrthoMG, Algorithm 5 (Sec. 4), in a deterministic form:
  *     the coarse correction is computed from a snapshot of r taken at the start
  *     of the cycle, the smoother side runs a fixed number of smoother+RM steps,
- *     then RM of the coarse correction; executed sequentially here;
+ *     then RM of the coarse correction; executed sequentially here, which is
+ *     also the additive synchronous configuration of Table 1;
+ *   - the hybrid configuration of Table 1: Algorithm 2 (pre- and
+ *     post-smoothing, multiplicative) on the finest level and the Algorithm 5
+ *     form on every coarser level;
  *   - coarsest level: direct solve (dense Cholesky);
  *   - discretisation: symmetric interior penalty DG (Sec. 2) on a Cartesian
  *     grid, weighted (harmonic-mean) face coefficient, Nitsche Dirichlet
@@ -57,8 +61,11 @@
 /* Options and report (mirrored by the ctypes wrapper)                        */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    int variant;       /* 0: multiplicative synchronous (Alg. 2); 1: deterministic semi-async (Alg. 5) */
-    int coarse_sync;   /* variant 1 only: 1 = levels >= 1 use Alg. 2 instead of the Alg. 5 form */
+    int variant;       /* 0: multiplicative synchronous (Alg. 2); 1: deterministic semi-async (Alg. 5);
+                          2: hybrid (Alg. 2 on the finest level, Alg. 5 below; Table 1);
+                          3: additive synchronous (Table 1; the Alg. 5 order, which this
+                          sequential code runs for variant 1 as well) */
+    int coarse_sync;   /* variants 1, 3: 1 = levels >= 1 use Alg. 2 instead of the Alg. 5 form */
     int s_pre;         /* block-Jacobi iterations of the pre-smoother call */
     int s_post;        /* block-Jacobi iterations of the post-smoother call */
     int n_s;           /* variant 1: smoother+RM steps per cycle on the smoother side */
@@ -716,6 +723,7 @@ int oracle_setup(const int *row_ptr, const int *col, const double *val, int64_t 
                  int p, int nlev, const or_opts *opt, void **out) {
     *out = NULL;
     if (nlev < 1 || nlev > MAXLEV || p < 0 || p > 5) return OR_EINVAL;
+    if (opt && (opt->variant < 0 || opt->variant > 3)) return OR_EINVAL;
     int bs = oracle_nbasis(p), n = nx * ny * nz;
     int rc = validate_bsr(n, bs, row_ptr, col, nnzb);
     if (rc) return rc;
@@ -745,6 +753,7 @@ int oracle_setup_sip(int nx, int ny, int nz, int p, double h, double penalty_c, 
                      const or_opts *opt, void **out) {
     *out = NULL;
     if (nlev < 1 || nlev > MAXLEV || p < 0 || p > 5 || !(h > 0)) return OR_EINVAL;
+    if (opt && (opt->variant < 0 || opt->variant > 3)) return OR_EINVAL;
     int n = nx * ny * nz;
     for (int c = 0; c < n; ++c)
         if (!(nu[c] > 0.0) || !isfinite(nu[c])) return OR_EINVAL;
@@ -971,9 +980,10 @@ static int stop_level(const oracle_t *o, int l, double rn, double r0n, double bn
     return it >= mx;
 }
 
-/* (x, r) = MG_l(b, 0): Algorithm 2 (variant 0) or the deterministic Algorithm 5
- * (variant 1) on level l with the level-local stopping rule; the coarsest level
- * is the Cholesky solve. Result in xout (N_l). */
+/* (x, r) = MG_l(b, 0): Algorithm 2 (variants 0 and 2) or the deterministic
+ * Algorithm 5 (variants 1 and 3) on level l with the level-local stopping rule;
+ * the coarsest level is the Cholesky solve. Variant 2 (hybrid) hands the
+ * Algorithm 5 form to the coarser levels. Result in xout (N_l). */
 static int mg(oracle_t *o, int l, const double *b, double *xout, double tol, int variant) {
     level_t *L = &o->lev[l];
     size_t N = L->N;
@@ -992,9 +1002,12 @@ static int mg(oracle_t *o, int l, const double *b, double *xout, double tol, int
     if (l == 0) log_trace(o, r0n, 0);
     int it = 0, status = OR_OK;
     double rn = r0n;
-    int sub_variant = (variant == 1 && o->opt.coarse_sync) ? 0 : variant;
+    int sub_variant = variant;
+    if (variant == 2) sub_variant = 1;
+    else if ((variant == 1 || variant == 3) && o->opt.coarse_sync) sub_variant = 0;
+    const int multiplicative = (variant == 0 || variant == 2);
     while (!stop_level(o, l, rn, r0n, bn, it, tol)) {
-        if (variant == 0) {
+        if (multiplicative) {
             smoother(o, l, L->r, o->opt.s_pre, L->z);
             rm(o, l, L->z);
             if (l == 0) { o->step++; log_trace(o, nrm2(L->r, N), 1); }

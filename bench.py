@@ -158,15 +158,15 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="cells per side")
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision solves and the other Table 1 configurations")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the library's plain copy kernel on one finest-level vector "
                          "(reference for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the solve is not sharded across GPUs in this build "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the solve is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -287,23 +287,30 @@ def main():
             log(f"{mode}: {mixed[mode]}")
             sm.close()
 
-    # the deterministic Algorithm 5 schedule: the coarse-grid correction runs
-    # on a second stream while the smoother steps run on the caller's stream
-    overlap = None
+    # the other configurations of Table 1 on the same workload (FP64):
+    # additive task-parallel (deterministic Algorithm 5: the coarse-grid
+    # correction on a second stream while the smoother steps run on the
+    # caller's stream), hybrid (Algorithm 2 on the finest level, the
+    # Algorithm 5 form below, level 1 forking) and additive synchronous (the
+    # Algorithm 5 order on one stream)
+    variants = None
     if not args.no_mixed:
-        so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), variant="overlap", **opts)
-        so.solve(b, tol=1e-10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xo = so.solve(b, tol=1e-10)
-        torch.cuda.synchronize()
-        to = time.perf_counter() - t0
-        r = so.last_report
-        overlap = {"value": prob.n_dofs / to, "unit": "DOF/s", "ms_per_step": round(to * 1e3, 2),
-                   "iters_fine": r["iters_fine"], "rel_res_true": r["rel_res_true"],
-                   "rel_diff_to_sync": float(torch.linalg.norm(xo - x) / torch.linalg.norm(x))}
-        log(f"overlap (Algorithm 5, deterministic): {overlap}")
-        so.close()
+        variants = {"sync_mult": {"value": value, "unit": "DOF/s", "ms_per_step": round(ms_per_step, 2),
+                                  "iters_fine": rep["iters_fine"], "rel_res_true": rep["rel_res_true"]}}
+        for name, v in (("overlap_det", "overlap"), ("hybrid", "hybrid"), ("add_sync", "add_sync")):
+            so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), variant=v, **opts)
+            so.solve(b, tol=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xo = so.solve(b, tol=1e-10)
+            torch.cuda.synchronize()
+            to = time.perf_counter() - t0
+            r = so.last_report
+            variants[name] = {"value": prob.n_dofs / to, "unit": "DOF/s", "ms_per_step": round(to * 1e3, 2),
+                              "iters_fine": r["iters_fine"], "rel_res_true": r["rel_res_true"],
+                              "rel_diff_to_sync": float(torch.linalg.norm(xo - x) / torch.linalg.norm(x))}
+            log(f"{name}: {variants[name]}")
+            so.close()
 
     batched = None if args.no_batched else batched_bench(omg, synth, torch)
 
@@ -333,7 +340,7 @@ def main():
                    "wall_s": round(wall, 3)},
         "hbm_kernels": hbm_kernels,
         "mixed": mixed,
-        "overlap_alg5": overlap,
+        "table1_variants": variants,
         "batched": batched,
         "roofline": roof,
         "kernel_ms_per_solve": breakdown,

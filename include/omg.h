@@ -46,7 +46,14 @@ typedef enum {
     OMG_EUNSUPPORTED = -7  /* operation not available for this solver */
 } omg_status;
 
-enum { OMG_SYNC_MULT = 0, OMG_OVERLAP_DET = 1 };               /* cycle variant */
+/* cycle variant (the configurations of Table 1): multiplicative synchronous
+ * (Algorithm 2, pre- and post-smoothing); additive task-parallel in the
+ * deterministic form of Algorithm 5 (coarse correction from the residual at
+ * the start of the cycle, computed on a second stream, n_s smoother+RM steps,
+ * then RM of the correction); hybrid (Algorithm 2 on the finest level, the
+ * Algorithm 5 form on every coarser level, the first coarse level forking);
+ * additive synchronous (the Algorithm 5 order on one stream). */
+enum { OMG_SYNC_MULT = 0, OMG_OVERLAP_DET = 1, OMG_HYBRID = 2, OMG_ADD_SYNC = 3 };
 enum { OMG_FP64 = 0, OMG_MIXED_IR = 1, OMG_MIXED_FLEX = 2 };    /* precision */
 enum { OMG_MAX_LEVELS = 16 };
 
@@ -74,15 +81,17 @@ typedef struct {
 } omg_bsr;
 
 typedef struct {
-    int32_t variant;      /* OMG_SYNC_MULT (Algorithm 2) or OMG_OVERLAP_DET (Algorithm 5, deterministic) */
-    int32_t coarse_sync;  /* OVERLAP_DET: 1 = levels >= 1 run the multiplicative cycle */
+    int32_t variant;      /* OMG_SYNC_MULT, OMG_OVERLAP_DET, OMG_HYBRID or OMG_ADD_SYNC (above);
+                             another value: OMG_EINVAL at setup */
+    int32_t coarse_sync;  /* OVERLAP_DET, ADD_SYNC: 1 = levels >= 1 run the multiplicative cycle */
     int32_t s_pre;        /* block-Jacobi iterations per pre-smoother call */
     int32_t s_post;       /* block-Jacobi iterations per post-smoother call */
-    int32_t n_s;          /* OVERLAP_DET: smoother+RM steps per cycle */
+    int32_t n_s;          /* additive levels: smoother+RM steps per cycle (>= 1) */
     int32_t max_iter;     /* finest-level cycles before OMG_ENOCONV */
     int32_t precision;    /* OMG_FP64, OMG_MIXED_IR (FP32 inner + FP64 refinement), OMG_MIXED_FLEX */
     int32_t max_outer;    /* OMG_MIXED_IR: refinement steps */
-    int32_t overlap_streams; /* OVERLAP_DET: 1 = coarse path on a second stream, 0 = one stream */
+    int32_t overlap_streams; /* OVERLAP_DET, HYBRID: 1 = coarse path of the forking level on a
+                                second stream, 0 = one stream (same results bit for bit) */
     int32_t trace;        /* 1 = record the finest-level residual after every RM (extra syncs) */
     double omega;         /* block-Jacobi damping */
     double inner_tol;     /* OMG_MIXED_IR: relative tolerance of each inner solve */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libomg.so")
 MAX_LEVELS = 16
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-SYNC_MULT, OVERLAP_DET = 0, 1
+SYNC_MULT, OVERLAP_DET, HYBRID, ADD_SYNC = 0, 1, 2, 3
 FP64, MIXED_IR, MIXED_FLEX = 0, 1, 2
 
 
@@ -124,11 +124,12 @@ def _check(st, what):
 
 def options(**kw) -> Options:
     """omg_options with defaults; keyword names as in the struct. ``variant``
-    accepts 'sync'/'overlap', ``precision`` 'fp64'/'mixed_ir'/'mixed_flex', and
+    accepts 'sync'/'overlap'/'hybrid'/'add_sync', ``precision``
+    'fp64'/'mixed_ir'/'mixed_flex', and
     ``crit`` a list of (rel, max) pairs for levels 1, 2, ..."""
     o = Options()
     lib().omg_default_options(ctypes.byref(o))
-    names = {"sync": SYNC_MULT, "overlap": OVERLAP_DET, "fp64": FP64, "mixed_ir": MIXED_IR,
+    names = {"sync": SYNC_MULT, "overlap": OVERLAP_DET, "hybrid": HYBRID, "add_sync": ADD_SYNC, "fp64": FP64, "mixed_ir": MIXED_IR,
              "mixed_flex": MIXED_FLEX}
     crit = kw.pop("crit", None)
     for k, v in kw.items():

@@ -418,7 +418,7 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
     OMG_TRY(read_norms(g, act, l, r0));
     std::vector<double> rn = r0;
     std::vector<int> its(m, 0), live(m, 1);
-    const int sub_variant = (variant == OMG_OVERLAP_DET && P->opt.coarse_sync) ? OMG_SYNC_MULT : variant;
+    const int sub_variant = cycle_sub_variant(variant, P->opt.coarse_sync);
     for (;;) {
         std::vector<int> cur, pos;
         for (int i = 0; i < m; ++i) {
@@ -433,7 +433,7 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
             pos.push_back(i);
         }
         if (cur.empty()) break;
-        if (variant == OMG_SYNC_MULT) {
+        if (cycle_multiplicative(variant)) {
             OMG_TRY(smoother_b(g, cur, l, P->opt.s_pre, false));
             OMG_TRY(rm_b(g, cur, l, false));
             OMG_TRY(coarse_path(g, cur, l, sub_variant, false));

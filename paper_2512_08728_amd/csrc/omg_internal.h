@@ -69,6 +69,23 @@ struct RmConfig {
 // directions: one per MGS block of B directions, then one for the norm of
 // the orthogonalised vector, its dot product with r and its Gram entries.
 inline unsigned long long rm_phases(int k, int B) { return (unsigned long long)((k + B - 1) / B) + 1; }
+
+// Cycle schedule per level under the configurations of Table 1. A level runs
+// the multiplicative cycle of Algorithm 2 or the additive (deterministic
+// Algorithm 5) cycle; the variant handed to the next coarser level follows.
+inline bool cycle_multiplicative(int variant) { return variant == OMG_SYNC_MULT || variant == OMG_HYBRID; }
+inline int cycle_sub_variant(int variant, int coarse_sync) {
+    if (variant == OMG_HYBRID) return OMG_OVERLAP_DET;
+    if ((variant == OMG_OVERLAP_DET || variant == OMG_ADD_SYNC) && coarse_sync) return OMG_SYNC_MULT;
+    return variant;
+}
+// The level whose coarse path runs on the second stream (levels below it
+// stay there); -1 if every level runs on the caller's stream.
+inline int cycle_fork_level(const omg_options& o) {
+    if (o.variant == OMG_OVERLAP_DET) return 0;
+    if (o.variant == OMG_HYBRID) return 1;
+    return -1;
+}
 // exchange words: two sets of [kMaxRedBlocks][kRmBlock + 1] block words, then
 // two sets of kRmBlock + 1 total words (leader form)
 constexpr size_t kRmSlotWords = 2 * (size_t)kMaxRedBlocks * (kRmBlock + 1) + 2 * (kRmBlock + 1);

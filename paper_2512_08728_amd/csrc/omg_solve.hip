@@ -182,8 +182,17 @@ static omg_status check_grid(const omg_grid* g) {
     return OMG_OK;
 }
 
+static omg_status check_options(const omg_options* o) {
+    if (!o) return OMG_OK;
+    if (o->variant < OMG_SYNC_MULT || o->variant > OMG_ADD_SYNC || o->precision < OMG_FP64 ||
+        o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->s_pre < 0 || o->s_post < 0)
+        return OMG_EINVAL;
+    return OMG_OK;
+}
+
 static omg_status create(const omg_grid* g, const omg_options* opt, void* stream, omg_solver** out) {
     OMG_TRY(check_grid(g));
+    OMG_TRY(check_options(opt));
     omg_solver* s = new omg_solver();
     s->grid = *g;
     if (opt) s->opt = *opt;
@@ -379,10 +388,10 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
         if (!L.coarsest) {
             OMG_TRY(omg_block_inverses(s, L));
             OMG_TRY(omg_fp32_copies(s, L));
-            // the persistent RM runs on the caller's stream only: in the overlap
-            // variant the coarse levels (second stream) keep the per-step kernels
-            const bool eligible = !std::getenv("OMG_NO_PERSISTENT_RM") &&
-                                  !(s->opt.variant == OMG_OVERLAP_DET && l > 0);
+            // the persistent RM runs on the caller's stream only: levels below
+            // the forking level (second stream) keep the per-step kernels
+            const int fl = cycle_fork_level(s->opt);
+            const bool eligible = !std::getenv("OMG_NO_PERSISTENT_RM") && !(fl >= 0 && l > fl);
             if (eligible) L.persist = rm_persistent_config(L.N, &L.rmc);
             if (L.persist) {
                 OMG_TRY(alloc_rm_state(s, L, l));
@@ -728,12 +737,12 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     int replay_count = -1;
     if (g_replay && l < (int)g_replay->q.size() && g_replay->pos[l] < g_replay->q[l].size())
         replay_count = g_replay->q[l][g_replay->pos[l]++];
-    const int sub_variant = (variant == OMG_OVERLAP_DET && s->opt.coarse_sync) ? OMG_SYNC_MULT : variant;
+    const int sub_variant = cycle_sub_variant(variant, s->opt.coarse_sync);
     int it = 0;
     double rn = r0n;
     omg_status status = OMG_OK;
     while (!stop_level(s, l, rn, r0n, bn, it, tol, replay_count)) {
-        if (variant == OMG_SYNC_MULT) {
+        if (cycle_multiplicative(variant)) {
             OMG_TRY(smoother(s, l, L.r, s->opt.s_pre, L.z, st));
             OMG_TRY(rm(s, l, L.z, st));
             OMG_TRY(trace_rm(s, l, st, 1));
@@ -747,7 +756,7 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
         } else {
             // coarse group: restriction of the residual at the start of the cycle
             HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
-            const bool fork = (l == 0) && s->opt.overlap_streams && !s->opt.trace;
+            const bool fork = (l == cycle_fork_level(s->opt)) && s->opt.overlap_streams && !s->opt.trace;
             if (fork) {
                 HIP_OK(hipEventRecord(s->ev_fork, st));
                 // smoother group: queue the fine work first (asynchronous)

@@ -132,6 +132,25 @@ def test_solve_overlap_matches_oracle_and_serial(n, p, lv):
     assert np.linalg.norm(x_2 - x_o) <= 1e-9 * np.linalg.norm(x_o)
 
 
+@pytest.mark.parametrize("n,p,lv", [(8, 1, 3), (16, 1, 4), (8, 2, 3)])
+@pytest.mark.parametrize("variant", ["hybrid", "add_sync"])
+def test_table1_variants_match_oracle(n, p, lv, variant):
+    """Hybrid and additive synchronous configurations (Table 1) against the
+    oracle: the same visit log (levels and iteration counts) and the solution
+    within 1e-9. The hybrid run with the coarse path of level 1 on a second
+    stream equals its one-stream run bit for bit."""
+    prob, nu, o, g = pair(n, p, lv, variant=variant, s_post=2, n_s=1)
+    b = synth.rhs(prob.n_dofs, 0)
+    x_o = o.solve(b)
+    x_g = host(g.solve(cuda(b)))
+    assert np.array_equal(o.visits(), g.visits())
+    assert g.last_report["rel_res_true"] <= 1.0001e-10
+    assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    if variant == "hybrid":
+        g1 = omg().Solver.from_sip(grid_of(prob), cuda(nu), variant="hybrid", s_post=2, n_s=1, overlap_streams=0)
+        assert np.array_equal(host(g1.solve(cuda(b))), x_g)
+
+
 def test_orthonormal_directions_and_residual_on_gpu():
     prob, nu, o, g = pair(8, 1, 2)
     b = synth.rhs(prob.n_dofs, 0)
@@ -245,6 +264,10 @@ def test_error_paths():
     with pytest.raises(m.OmgError) as e:
         m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(-nu))
     assert e.value.status == m.EINVAL
+    for bad_opt in (dict(variant=4), dict(variant=-1), dict(n_s=0), dict(precision=3)):
+        with pytest.raises(m.OmgError) as e:
+            m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(nu), **bad_opt)
+        assert e.value.status == m.EINVAL, bad_opt
 
 
 @pytest.mark.parametrize("dims,p,lv", [((8, 4, 6), 1, 2), ((12, 8, 8), 2, 3), ((4, 4, 4), 3, 2)])

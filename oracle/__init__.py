@@ -76,6 +76,7 @@ def lib():
         L.oracle_get_dirs.argtypes = [P, i, P, P]
         L.oracle_get_residual.argtypes = [P, i, P]
         L.oracle_get_visits.argtypes = [P, P]
+        L.oracle_set_step_schedule.argtypes = [P, P, i]
         L.oracle_get_trace.argtypes = [P, P]
         L.oracle_spmv.argtypes = [P, i, P, P, P]
         L.oracle_smoother.argtypes = [P, i, P, i, P]
@@ -231,6 +232,14 @@ class Oracle:
         out = np.zeros(2 * max(cnt, 1), dtype=np.int32)
         m = lib().oracle_get_visits(self._h, _p(out))
         return out[: 2 * m].reshape(m, 2)
+
+    def set_step_schedule(self, counts):
+        """Smoother-step counts per cycle of the forking level for the next
+        solves (replay of a timing-adaptive run); empty clears."""
+        c = np.ascontiguousarray(counts, dtype=np.int32)
+        st = lib().oracle_set_step_schedule(self._h, _p(c) if len(c) else None, len(c))
+        if st != OK:
+            raise OracleError(st)
 
     def trace(self):
         cnt = self.last_report["n_trace"]

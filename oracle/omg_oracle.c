@@ -25,6 +25,11 @@
  *   - the hybrid configuration of Table 1: Algorithm 2 (pre- and
  *     post-smoothing, multiplicative) on the finest level and the Algorithm 5
  *     form on every coarser level;
+ *   - the adaptive loops of Sec. 4.3 choose the number of smoother steps per
+ *     cycle by timing; the oracle takes such counts as an input (a schedule
+ *     for the cycles of the level whose coarse path runs concurrently: the
+ *     finest level for variant 1, level 1 for variant 2) and otherwise runs
+ *     n_s steps;
  *   - coarsest level: direct solve (dense Cholesky);
  *   - discretisation: symmetric interior penalty DG (Sec. 2) on a Cartesian
  *     grid, weighted (harmonic-mean) face coefficient, Nitsche Dirichlet
@@ -522,6 +527,8 @@ typedef struct {
     int n_trace, cap_trace, step;
     int n_breakdowns;
     double bnorm_fine;
+    int *sched;        /* smoother steps per cycle of the forking level (NULL: n_s) */
+    int sched_n, sched_pos;
 } oracle_t;
 
 static void level_free(level_t *L) {
@@ -546,7 +553,34 @@ void oracle_destroy(void *h) {
     free(o->nu);
     free(o->visits);
     free(o->trace);
+    free(o->sched);
     free(o);
+}
+
+/* Smoother-step counts for the cycles of the forking level, consumed in
+ * order by the following solves (n = 0 clears; cycles beyond the schedule
+ * take n_s). Each count must be >= 1. */
+int oracle_set_step_schedule(void *h, const int *counts, int n) {
+    oracle_t *o = h;
+    if (!o || n < 0 || (n > 0 && !counts)) return OR_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (counts[i] < 1) return OR_EINVAL;
+    free(o->sched);
+    o->sched = NULL;
+    o->sched_n = o->sched_pos = 0;
+    if (n == 0) return OR_OK;
+    o->sched = malloc(sizeof(int) * n);
+    if (!o->sched) return OR_ENOMEM;
+    memcpy(o->sched, counts, sizeof(int) * n);
+    o->sched_n = n;
+    return OR_OK;
+}
+
+/* the level whose cycles have a concurrent coarse path (-1: none) */
+static int fork_level(const oracle_t *o) {
+    if (o->opt.variant == 1) return 0;
+    if (o->opt.variant == 2) return 1;
+    return -1;
 }
 
 static void log_visit(oracle_t *o, int l, int it) {
@@ -1020,7 +1054,9 @@ static int mg(oracle_t *o, int l, const double *b, double *xout, double tol, int
         } else {
             memcpy(L->rsnap, L->r, sizeof(double) * N);
             coarse_correction(o, l, L->rsnap, L->zcor, tol, sub_variant);
-            for (int t = 0; t < o->opt.n_s; ++t) {
+            int ns = o->opt.n_s;
+            if (o->sched && l == fork_level(o) && o->sched_pos < o->sched_n) ns = o->sched[o->sched_pos++];
+            for (int t = 0; t < ns; ++t) {
                 smoother(o, l, L->r, o->opt.s_post, L->z);
                 rm(o, l, L->z);
                 if (l == 0) { o->step++; log_trace(o, nrm2(L->r, N), 1); }
@@ -1049,6 +1085,7 @@ int oracle_solve(void *h, const double *b, double *x, double tol, or_report *rep
     o->n_trace = 0;
     o->step = 0;
     o->n_breakdowns = 0;
+    o->sched_pos = 0;
     or_report R;
     memset(&R, 0, sizeof(R));
     for (size_t e = 0; e < N; ++e)

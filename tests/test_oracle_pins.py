@@ -445,6 +445,64 @@ def test_first_hybrid_cycle_structure():
     assert np.linalg.norm(x - cycle(additive=False)) > 1e-6 * np.linalg.norm(xr)
 
 
+def test_step_schedule_first_overlap_cycle():
+    """Adaptive loops (Sec. 4.3) replayed with two smoother steps in the
+    first cycle (2 levels): the coarse correction comes from the residual at
+    the start of the cycle, the smoother steps are multiplicative (the second
+    one smooths the residual left by the first RM), and x minimises the
+    residual over span{z1, z2, z_cor}."""
+    prob, nu, o = sip(4, 1, n_levels=2, variant="overlap", max_iter=1, s_post=1, n_s=1)
+    o.set_step_schedule([2])
+    b = synth.rhs(prob.n_dofs, 10)
+    x = o.solve(b, check=False)
+    A, Dinv, P, Ac = _dense_parts(o, prob)
+    zc = P @ np.linalg.solve(Ac, P.T @ b)
+    z1 = 0.7 * Dinv @ b
+    _, r1 = _lsq_update(A, [z1], b)
+    z2 = 0.7 * Dinv @ r1
+    xr, _ = _lsq_update(A, [z1, z2, zc], b)
+    assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
+
+
+def test_step_schedule_hybrid_level1_and_default():
+    """The schedule of the hybrid configuration applies to the cycles of
+    level 1: with counts [2] the first level-1 iteration takes two smoother
+    steps (dense least squares over its three directions); a schedule of n_s
+    everywhere equals running without one, bit for bit."""
+    prob, nu, o = sip(8, 1, n_levels=3, variant="hybrid", max_iter=1, s_pre=1, s_post=1, n_s=1,
+                      crit=[(-1.0, 1)])
+    o.set_step_schedule([2])
+    b = synth.rhs(prob.n_dofs, 9)
+    x = o.solve(b, check=False)
+    A0 = o.scipy_matrix().toarray()
+    E = o.embedding()
+    P0 = P_matrix(E, 8, 8, 8).toarray()
+    P1 = P_matrix(E, 4, 4, 4).toarray()
+    A1 = P0.T @ A0 @ P0
+    A2 = P1.T @ A1 @ P1
+    D0, D1 = _block_inv(A0, prob.bs), _block_inv(A1, prob.bs)
+    z1 = 0.7 * D0 @ b
+    _, r1 = _lsq_update(A0, [z1], b)
+    rc = P0.T @ r1
+    za = 0.7 * D1 @ rc
+    _, rca = _lsq_update(A1, [za], rc)
+    zb = 0.7 * D1 @ rca
+    zcor = P1 @ np.linalg.solve(A2, P1.T @ rc)
+    y, _ = _lsq_update(A1, [za, zb, zcor], rc)
+    z2 = P0 @ y
+    _, r2 = _lsq_update(A0, [z1, z2], b)
+    z3 = 0.7 * D0 @ r2
+    xr, _ = _lsq_update(A0, [z1, z2, z3], b)
+    assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
+    prob, nu, o1 = sip(8, 1, n_levels=3, variant="hybrid", s_post=2, n_s=1)
+    b = synth.rhs(prob.n_dofs, 0)
+    x1 = o1.solve(b)
+    o1.set_step_schedule([1] * 500)
+    assert np.array_equal(o1.solve(b), x1)
+    with pytest.raises(oracle.OracleError):
+        o1.set_step_schedule([1, 0])
+
+
 def test_hybrid_two_levels_is_sync():
     """With two levels no level runs the Algorithm 5 form, so the hybrid
     configuration is Algorithm 2 exactly (bit for bit)."""

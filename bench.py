@@ -297,8 +297,11 @@ def main():
     if not args.no_mixed:
         variants = {"sync_mult": {"value": value, "unit": "DOF/s", "ms_per_step": round(ms_per_step, 2),
                                   "iters_fine": rep["iters_fine"], "rel_res_true": rep["rel_res_true"]}}
-        for name, v in (("overlap_det", "overlap"), ("hybrid", "hybrid"), ("add_sync", "add_sync")):
-            so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), variant=v, **opts)
+        # the last two: timing-adaptive loops (Sec. 4.3), the smoother side
+        # stepping while the coarse path runs (at most 8 steps per cycle)
+        for name, v, nsm in (("overlap_det", "overlap", 0), ("hybrid", "hybrid", 0), ("add_sync", "add_sync", 0),
+                             ("overlap_adaptive", "overlap", 8), ("hybrid_adaptive", "hybrid", 8)):
+            so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), variant=v, n_s_max=nsm, **opts)
             so.solve(b, tol=1e-10)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -309,6 +312,9 @@ def main():
             variants[name] = {"value": prob.n_dofs / to, "unit": "DOF/s", "ms_per_step": round(to * 1e3, 2),
                               "iters_fine": r["iters_fine"], "rel_res_true": r["rel_res_true"],
                               "rel_diff_to_sync": float(torch.linalg.norm(xo - x) / torch.linalg.norm(x))}
+            if nsm:
+                sc = so.step_counts()
+                variants[name]["steps_per_cycle_mean"] = round(float(sc.mean()), 2) if len(sc) else None
             log(f"{name}: {variants[name]}")
             so.close()
 

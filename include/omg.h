@@ -93,6 +93,12 @@ typedef struct {
     int32_t overlap_streams; /* OVERLAP_DET, HYBRID: 1 = coarse path of the forking level on a
                                 second stream, 0 = one stream (same results bit for bit) */
     int32_t trace;        /* 1 = record the finest-level residual after every RM (extra syncs) */
+    int32_t n_s_max;      /* > n_s: timing-adaptive cycle (Sec. 4.3) on the forking level of
+                             OVERLAP_DET / HYBRID with two streams: the smoother side keeps
+                             taking smoother+RM steps until the coarse path has finished, at
+                             least n_s and at most n_s_max (counts: omg_get_step_counts);
+                             results then depend on timing. <= n_s: deterministic */
+    int32_t pad0;
     double omega;         /* block-Jacobi damping */
     double inner_tol;     /* OMG_MIXED_IR: relative tolerance of each inner solve */
     double breakdown;     /* RM drops a direction when ||w_out|| <= breakdown * ||w_in|| */
@@ -234,6 +240,11 @@ omg_status omg_get_visits(const omg_solver *s, int32_t *out, int32_t cap, int32_
 /* Residual trace of the last solve (needs opt.trace): triples
  * (step, ||r||, type: 0 initial, 1 smoother, 2 coarse, 3 final), host. */
 omg_status omg_get_trace(const omg_solver *s, double *out, int32_t cap, int32_t *n);
+/* Smoother+RM steps taken in each cycle of the forking level during the
+ * last solve (OVERLAP_DET: the finest level; HYBRID: level 1), in execution
+ * order, into host out[cap]; count in *n (out nullable). n_s each unless the
+ * cycle was timing-adaptive. */
+omg_status omg_get_step_counts(const omg_solver *s, int32_t *out, int32_t cap, int32_t *n);
 /* Replay: make the next solve(s) use these per-visit iteration counts
  * (host pairs (level, iterations), n entries) instead of the level tests;
  * n = 0 switches replay off. */

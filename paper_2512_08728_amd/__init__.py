@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
                 ("s_post", ctypes.c_int32), ("n_s", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("overlap_streams", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("n_s_max", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("inner_tol", ctypes.c_double), ("breakdown", ctypes.c_double),
                 ("crit_rel", ctypes.c_double * MAX_LEVELS), ("crit_max", ctypes.c_int32 * MAX_LEVELS)]
 
@@ -62,7 +63,7 @@ _lib = None
 EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "omg_solve_batched",
            "omg_solve_backward", "omg_destroy", "omg_strerror", "omg_level_info", "omg_level_matrix",
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
-           "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_set_replay", "omg_bench_kernel",
+           "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_get_step_counts", "omg_set_replay", "omg_bench_kernel",
            "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result", "omg_level_multi",
            "omg_level_tuning", "omg_level_rm_step", "omg_level_rm_configs"]
 MR_SPMV, MR_SMOOTHER, MR_COARSE = 0, 1, 2
@@ -101,6 +102,7 @@ def lib():
         L.omg_get_dirs.argtypes = [P, i32, P, P]
         L.omg_get_visits.argtypes = [P, P, i32, P]
         L.omg_get_trace.argtypes = [P, P, i32, P]
+        L.omg_get_step_counts.argtypes = [P, P, i32, P]
         L.omg_set_replay.argtypes = [P, P, i32]
         L.omg_bench_kernel.argtypes = [P, i32, i32, i32, P, P]
         L.omg_get_kernel_counts.argtypes = [P, P]
@@ -334,6 +336,14 @@ class Solver:
         out = np.zeros(2 * max(n.value, 1), dtype=np.int32)
         lib().omg_get_visits(self._h, out.ctypes.data, n.value, ctypes.byref(n))
         return out[: 2 * n.value].reshape(-1, 2)
+
+    def step_counts(self):
+        """Smoother+RM steps per cycle of the forking level in the last solve."""
+        n = ctypes.c_int32()
+        lib().omg_get_step_counts(self._h, None, 0, ctypes.byref(n))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        lib().omg_get_step_counts(self._h, out.ctypes.data, n.value, ctypes.byref(n))
+        return out[: n.value]
 
     def trace(self):
         n = ctypes.c_int32()

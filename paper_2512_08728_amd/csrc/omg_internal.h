@@ -193,6 +193,7 @@ struct omg_solver {
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cstream = nullptr;     // coarse-path stream (OVERLAP_DET)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_step[2] = {nullptr, nullptr}; // smoother steps of a timing-adaptive cycle
     std::vector<omg::Level> lev;
     double* E = nullptr;               // [8][bs][bs] embedding blocks (device)
     float* E32 = nullptr;
@@ -208,6 +209,7 @@ struct omg_solver {
     int* err_flag = nullptr;           // device error flag (setup kernels)
     // logs of the last solve
     std::vector<int> visits;
+    std::vector<int> steps;            // smoother+RM steps per cycle of the forking level
     std::vector<omg::Trace> trace;
     std::vector<int> replay;
     size_t replay_pos = 0;

@@ -21,8 +21,10 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <atomic>
 #include <map>
 #include <mutex>
+#include <thread>
 
 #include "omg_internal.h"
 
@@ -58,6 +60,7 @@ extern "C" void omg_default_options(omg_options* o) {
     o->max_outer = 50;
     o->overlap_streams = 1;
     o->trace = 0;
+    o->n_s_max = 0;
     o->omega = 0.7;
     o->inner_tol = 1e-5;
     o->breakdown = 1e-14;
@@ -144,6 +147,8 @@ extern "C" void omg_destroy(omg_solver* s) {
     }
     if (s->ev_fork) hipEventDestroy(s->ev_fork);
     if (s->ev_join) hipEventDestroy(s->ev_join);
+    for (hipEvent_t e : s->ev_step)
+        if (e) hipEventDestroy(e);
     for (auto& L : s->lev) free_level(L);
     hipFree(s->E);
     hipFree(s->E32);
@@ -185,7 +190,7 @@ static omg_status check_grid(const omg_grid* g) {
 static omg_status check_options(const omg_options* o) {
     if (!o) return OMG_OK;
     if (o->variant < OMG_SYNC_MULT || o->variant > OMG_ADD_SYNC || o->precision < OMG_FP64 ||
-        o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->s_pre < 0 || o->s_post < 0)
+        o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->n_s_max < 0 || o->s_pre < 0 || o->s_post < 0)
         return OMG_EINVAL;
     return OMG_OK;
 }
@@ -233,13 +238,15 @@ static omg_status create(const omg_grid* g, const omg_options* opt, void* stream
     HIP_OK(hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&s->ev_step[0], hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&s->ev_step[1], hipEventDisableTiming));
     return OMG_OK;
 }
 
 // Storage of the persistent RM kernel on one level: exchange words, abort
 // flag, MGS coefficient history (sized for the level's iteration cap).
 static omg_status alloc_rm_state(omg_solver* s, Level& L, int l) {
-    const int per_it = std::max(3, s->opt.n_s + 1);
+    const int per_it = std::max(3, std::max(s->opt.n_s, s->opt.n_s_max) + 1); // RMs per level iteration
     const int its = (l == 0) ? s->opt.max_iter : s->opt.crit_max[l - 1];
     L.ucap = per_it * std::max(its, 1) + 4;
     if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
@@ -719,6 +726,59 @@ static omg_status coarse_path(omg_solver* s, int l, int variant, hipStream_t st,
     return OMG_OK;
 }
 
+// Timing-adaptive cycle of the forking level (adaptive loops, Sec. 4.3;
+// Algorithm 5). The coarse group (coarse recursion on the restricted
+// residual, prolongation into zcor; second stream) is driven by a host thread
+// of its own, because the coarse recursion waits for one residual norm per
+// coarse iteration. Meanwhile the smoother group keeps issuing smoothing +
+// RM steps on the caller's stream until the coarse group has signalled that
+// its correction is complete on the device: at least n_s steps, at most
+// n_s_max. One step is kept queued ahead of the GPU, and the decision to stop
+// is taken when the step before it has finished, so at most one step is
+// issued after the signal. The count is returned in *steps.
+static omg_status adaptive_cycle(omg_solver* s, int l, int sub_variant, hipStream_t st, int* steps) {
+    Level& L = s->lev[l];
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipStreamWaitEvent(s->cstream, s->ev_fork, 0));
+    std::atomic<int> done_c{0};
+    omg_status cst = OMG_OK;
+    std::thread coarse;
+    try {
+        coarse = std::thread([&]() {
+            if (hipSetDevice(dev) != hipSuccess) cst = OMG_EHIP;
+            if (cst == OMG_OK) cst = coarse_path(s, l, sub_variant, s->cstream, L.zcor);
+            if (cst == OMG_OK && hipEventRecord(s->ev_join, s->cstream) != hipSuccess) cst = OMG_EHIP;
+            if (cst == OMG_OK && hipEventSynchronize(s->ev_join) != hipSuccess) cst = OMG_EHIP;
+            done_c.store(1, std::memory_order_release);
+        });
+    } catch (...) {
+        return OMG_EHIP; // no thread: nothing was queued on the coarse stream but the wait
+    }
+    omg_status sst = OMG_OK;
+    int t = 0;
+    for (;;) {
+        sst = smoother(s, l, L.r, s->opt.s_post, L.z, st);
+        if (sst == OMG_OK) sst = rm(s, l, L.z, st);
+        if (sst == OMG_OK && hipEventRecord(s->ev_step[t & 1], st) != hipSuccess) sst = OMG_EHIP;
+        if (sst != OMG_OK) break;
+        ++t;
+        if (t >= s->opt.n_s_max) break;
+        // step t is queued; wait for step t - 1 before deciding on step t + 1
+        if (t >= 2 && hipEventSynchronize(s->ev_step[t & 1]) != hipSuccess) {
+            sst = OMG_EHIP;
+            break;
+        }
+        if (t >= s->opt.n_s && done_c.load(std::memory_order_acquire)) break;
+    }
+    coarse.join();
+    *steps = t;
+    OMG_TRY(sst);
+    OMG_TRY(cst);
+    HIP_OK(hipStreamWaitEvent(st, s->ev_join, 0));
+    return OMG_OK;
+}
+
 static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double tol, int variant, hipStream_t st) {
     Level& L = s->lev[l];
     if (L.coarsest) {
@@ -756,8 +816,15 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
         } else {
             // coarse group: restriction of the residual at the start of the cycle
             HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
-            const bool fork = (l == cycle_fork_level(s->opt)) && s->opt.overlap_streams && !s->opt.trace;
-            if (fork) {
+            const bool forking = (l == cycle_fork_level(s->opt));
+            const bool fork = forking && s->opt.overlap_streams && !s->opt.trace;
+            if (fork && s->opt.n_s_max > s->opt.n_s) {
+                HIP_OK(hipEventRecord(s->ev_fork, st));
+                int steps = 0;
+                OMG_TRY(adaptive_cycle(s, l, sub_variant, st, &steps));
+                s->steps.push_back(steps);
+            } else if (fork) {
+                s->steps.push_back(s->opt.n_s);
                 HIP_OK(hipEventRecord(s->ev_fork, st));
                 // smoother group: queue the fine work first (asynchronous)
                 for (int t = 0; t < s->opt.n_s; ++t) {
@@ -769,6 +836,7 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
                 HIP_OK(hipEventRecord(s->ev_join, s->cstream));
                 HIP_OK(hipStreamWaitEvent(st, s->ev_join, 0));
             } else {
+                if (forking) s->steps.push_back(s->opt.n_s);
                 OMG_TRY(coarse_path(s, l, sub_variant, st, L.zcor));
                 for (int t = 0; t < s->opt.n_s; ++t) {
                     OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
@@ -901,6 +969,7 @@ static omg_status finish_report(omg_solver* s, const double* b, const double* x,
 
 static void reset_logs(omg_solver* s) {
     s->visits.clear();
+    s->steps.clear();
     s->trace.clear();
     s->step = 0;
     for (auto& L : s->lev)
@@ -1299,6 +1368,15 @@ extern "C" omg_status omg_get_visits(const omg_solver* s, int32_t* out, int32_t 
             out[2 * i] = s->visits[2 * i];
             out[2 * i + 1] = s->visits[2 * i + 1];
         }
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_get_step_counts(const omg_solver* s, int32_t* out, int32_t cap, int32_t* n) {
+    if (!s || !n) return OMG_EINVAL;
+    const int cnt = (int)s->steps.size();
+    *n = cnt;
+    if (out)
+        for (int i = 0; i < cnt && i < cap; ++i) out[i] = s->steps[i];
     return OMG_OK;
 }
 

@@ -151,6 +151,33 @@ def test_table1_variants_match_oracle(n, p, lv, variant):
         assert np.array_equal(host(g1.solve(cuda(b))), x_g)
 
 
+@pytest.mark.parametrize("variant,n,p,lv", [("overlap", 8, 1, 2), ("overlap", 16, 1, 4), ("hybrid", 16, 1, 4),
+                                             ("hybrid", 8, 2, 3)])
+def test_adaptive_loop_replayed_by_oracle(variant, n, p, lv):
+    """Timing-adaptive cycles (adaptive loops, Sec. 4.3): the smoother side
+    keeps stepping while the coarse path runs on the second stream. The
+    counts the GPU chose lie in [n_s, n_s_max]; the oracle, replaying them,
+    reproduces the visit log and the solution within 1e-9, and the true
+    residual reaches 1e-10. With n_s_max <= n_s the run is the deterministic
+    one, bit for bit."""
+    prob, nu, o, g0 = pair(n, p, lv, variant=variant, s_post=2, n_s=1)
+    g = omg().Solver.from_sip(grid_of(prob), cuda(nu), variant=variant, s_post=2, n_s=1, n_s_max=6)
+    b = synth.rhs(prob.n_dofs, 0)
+    x_g = host(g.solve(cuda(b)))
+    counts = g.step_counts()
+    print(f"{variant} {n}^3 P{p}: {len(counts)} cycles, steps per cycle {np.bincount(counts).tolist()}")
+    assert len(counts) > 0 and counts.min() >= 1 and counts.max() <= 6
+    assert g.last_report["rel_res_true"] <= 1.0001e-10
+    o.set_step_schedule(counts)
+    x_o = o.solve(b)
+    assert np.array_equal(o.visits(), g.visits())
+    assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    gd = omg().Solver.from_sip(grid_of(prob), cuda(nu), variant=variant, s_post=2, n_s=1, n_s_max=1)
+    x_d = host(gd.solve(cuda(b)))
+    assert np.all(gd.step_counts() == 1)
+    assert np.array_equal(x_d, host(g0.solve(cuda(b))))
+
+
 def test_orthonormal_directions_and_residual_on_gpu():
     prob, nu, o, g = pair(8, 1, 2)
     b = synth.rhs(prob.n_dofs, 0)
@@ -264,7 +291,7 @@ def test_error_paths():
     with pytest.raises(m.OmgError) as e:
         m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(-nu))
     assert e.value.status == m.EINVAL
-    for bad_opt in (dict(variant=4), dict(variant=-1), dict(n_s=0), dict(precision=3)):
+    for bad_opt in (dict(variant=4), dict(variant=-1), dict(n_s=0), dict(precision=3), dict(n_s_max=-1)):
         with pytest.raises(m.OmgError) as e:
             m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(nu), **bad_opt)
         assert e.value.status == m.EINVAL, bad_opt

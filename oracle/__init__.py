@@ -35,6 +35,7 @@ class Opts(ctypes.Structure):
         ("s_post", ctypes.c_int), ("n_s", ctypes.c_int), ("max_iter", ctypes.c_int),
         ("precision", ctypes.c_int), ("gs", ctypes.c_int), ("alpha_mode", ctypes.c_int),
         ("m_max", ctypes.c_int), ("max_outer", ctypes.c_int), ("n_crit", ctypes.c_int),
+        ("smoother", ctypes.c_int), ("pad_smoother", ctypes.c_int),
         ("omega", ctypes.c_double), ("inner_tol", ctypes.c_double), ("breakdown", ctypes.c_double),
         ("crit_rel", ctypes.c_double * MAXLEV), ("crit_max", ctypes.c_int * MAXLEV),
     ]
@@ -98,13 +99,14 @@ def _p(a: np.ndarray):
 
 
 def make_opts(**kw) -> Opts:
-    """Options: variant ('sync'|'overlap'|'hybrid'|'add_sync' or 0|1|2|3), s_pre, s_post, n_s, omega,
+    """Options: variant ('sync'|'overlap'|'hybrid'|'add_sync' or 0|1|2|3), smoother ('bj'|'schwarz'),
+    s_pre, s_post, n_s, omega,
     max_iter, precision ('fp64'|'mixed_ir'|'mixed_flex' or 0|1|2), gs
     ('mgs'|'mgs2'), alpha_mode, m_max, inner_tol, max_outer, breakdown,
     coarse_sync, crit (list of (rel, max) for levels 1, 2, ...)."""
     o = Opts()
     lib().oracle_default_opts(ctypes.byref(o))
-    names = {"sync": 0, "overlap": 1, "hybrid": 2, "add_sync": 3, "fp64": 0, "mixed_ir": 1, "mixed_flex": 2, "mgs": 0, "mgs2": 1}
+    names = {"sync": 0, "overlap": 1, "hybrid": 2, "add_sync": 3, "bj": 0, "schwarz": 1, "fp64": 0, "mixed_ir": 1, "mixed_flex": 2, "mgs": 0, "mgs2": 1}
     crit = kw.pop("crit", None)
     for k, v in kw.items():
         if isinstance(v, str):

@@ -17,6 +17,10 @@
  *     level-local stopping rules of Sec. 4.2;
  *   - block-Jacobi smoother: Algorithm 4 (Sec. 3.3) with precomputed block
  *     inverses, started from zero, a fixed number of sweeps;
+ *   - additive Schwarz smoother: Algorithm 3 (Sec. 3.2) with one subdomain
+ *     per cell and an overlap of one cell (the cells its matrix row couples
+ *     to), local problems solved with stored Cholesky factors, corrections
+ *     summed, damped by omega like the block-Jacobi sweeps;
  *   - semi-asynchronous OrthoMG, Algorithm 5 (Sec. 4), in a deterministic form:
  *     the coarse correction is computed from a snapshot of r taken at the start
  *     of the cycle, the smoother side runs a fixed number of smoother+RM steps,
@@ -81,6 +85,8 @@ typedef struct {
     int m_max;         /* 0 unbounded; else restart the level's W,Z when they hold m_max columns */
     int max_outer;     /* precision 1: maximum refinement steps */
     int n_crit;        /* number of entries used in crit_rel/crit_max (levels 1..n_crit) */
+    int smoother;      /* 0 block-Jacobi (Alg. 4); 1 additive Schwarz (Alg. 3, FP64 only) */
+    int pad_smoother;
     double omega;      /* block-Jacobi damping */
     double inner_tol;  /* precision 1: relative tolerance of each inner solve */
     double breakdown;  /* RM discards a direction when ||w_out|| <= breakdown * ||w_in|| */
@@ -498,6 +504,9 @@ typedef struct {
     bsr_t A;
     float *A32;        /* FP32 copy of A.val (mixed forms) */
     double *Dinv;      /* [n][bs][bs] block inverses (non-coarsest levels) */
+    int as_w;          /* additive Schwarz: cells per patch (row length of A) */
+    int *as_cells;     /* [n][as_w] patch of cell c: c, then its row's other columns (-1: none) */
+    double *as_L;      /* [n][(as_w bs)^2] Cholesky factors of the patch matrices */
     float *Dinv32;
     double *Lc;        /* coarsest: dense Cholesky factor */
     /* residual minimisation storage */
@@ -543,6 +552,8 @@ static void level_free(level_t *L) {
     free(L->rsnap); free(L->zcor); free(L->r0); free(L->x0);
     free(L->parent);
     free(L->slot);
+    free(L->as_cells);
+    free(L->as_L);
 }
 
 void oracle_destroy(void *h) {
@@ -672,6 +683,8 @@ static void default_opts(or_opts *o) {
 void oracle_default_opts(or_opts *o) { default_opts(o); }
 
 /* Setup from a caller-supplied fine BSR matrix (copied) on an nx*ny*nz grid. */
+static int as_setup(oracle_t *o, int l);
+
 static int setup_common(oracle_t *o, int nx, int ny, int nz, int p, int nlev) {
     int bs = o->bs;
     embedding(p, o->E);
@@ -718,6 +731,10 @@ static int setup_common(oracle_t *o, int nx, int ny, int nz, int p, int nlev) {
             }
             if (bad) return OR_ENOTSPD;
             for (size_t t = 0; t < (size_t)L->n * bs * bs; ++t) L->Dinv32[t] = (float)L->Dinv[t];
+            if (o->opt.smoother == 1) {
+                int rc = as_setup(o, l);
+                if (rc) return rc;
+            }
         } else {
             /* coarsest: densify and factor */
             size_t n = L->N;
@@ -757,7 +774,8 @@ int oracle_setup(const int *row_ptr, const int *col, const double *val, int64_t 
                  int p, int nlev, const or_opts *opt, void **out) {
     *out = NULL;
     if (nlev < 1 || nlev > MAXLEV || p < 0 || p > 5) return OR_EINVAL;
-    if (opt && (opt->variant < 0 || opt->variant > 3)) return OR_EINVAL;
+    if (opt && (opt->variant < 0 || opt->variant > 3 || opt->smoother < 0 || opt->smoother > 1)) return OR_EINVAL;
+    if (opt && opt->smoother == 1 && opt->precision != 0) return OR_EUNSUPPORTED;
     int bs = oracle_nbasis(p), n = nx * ny * nz;
     int rc = validate_bsr(n, bs, row_ptr, col, nnzb);
     if (rc) return rc;
@@ -787,7 +805,8 @@ int oracle_setup_sip(int nx, int ny, int nz, int p, double h, double penalty_c, 
                      const or_opts *opt, void **out) {
     *out = NULL;
     if (nlev < 1 || nlev > MAXLEV || p < 0 || p > 5 || !(h > 0)) return OR_EINVAL;
-    if (opt && (opt->variant < 0 || opt->variant > 3)) return OR_EINVAL;
+    if (opt && (opt->variant < 0 || opt->variant > 3 || opt->smoother < 0 || opt->smoother > 1)) return OR_EINVAL;
+    if (opt && opt->smoother == 1 && opt->precision != 0) return OR_EUNSUPPORTED;
     int n = nx * ny * nz;
     for (int c = 0; c < n; ++c)
         if (!(nu[c] > 0.0) || !isfinite(nu[c])) return OR_EINVAL;
@@ -848,11 +867,81 @@ static void apply_dinv(const oracle_t *o, int l, const double *v, double scale, 
     }
 }
 
+/* Additive Schwarz subdomains (Algorithm 3): subdomain i is cell i, its
+ * overlap of one cell is every cell its matrix row couples to; the local
+ * matrix A_i = R_i A P_i is the dense restriction of A to those cells, stored
+ * as its Cholesky factor. */
+static int as_setup(oracle_t *o, int l) {
+    level_t *L = &o->lev[l];
+    const bsr_t *A = &L->A;
+    int bs = o->bs, w = 1;
+    for (int c = 0; c < L->n; ++c) {
+        int len = A->row_ptr[c + 1] - A->row_ptr[c];
+        if (len > w) w = len;
+    }
+    int m = w * bs;
+    if (m > 64 * 8) return OR_EUNSUPPORTED;
+    L->as_w = w;
+    L->as_cells = malloc(sizeof(int) * (size_t)L->n * w);
+    L->as_L = dalloc((size_t)L->n * m * m);
+    if (!L->as_cells || !L->as_L) return OR_ENOMEM;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int c = 0; c < L->n; ++c) {
+        int *cells = L->as_cells + (size_t)c * w, np = 1;
+        cells[0] = c;
+        for (int q = A->row_ptr[c]; q < A->row_ptr[c + 1]; ++q)
+            if (A->col[q] != c) cells[np++] = A->col[q];
+        for (int a = np; a < w; ++a) cells[a] = -1;
+        int mc = np * bs;
+        double *Lf = L->as_L + (size_t)c * m * m; /* leading mc x mc block, row-major, stride mc */
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < np; ++b) {
+                int64_t q = bsr_find(A, cells[a], cells[b]);
+                for (int r = 0; r < bs; ++r)
+                    for (int cc = 0; cc < bs; ++cc)
+                        Lf[(size_t)(a * bs + r) * mc + b * bs + cc] =
+                            q < 0 ? 0.0 : A->val[(size_t)q * bs * bs + r * bs + cc];
+            }
+        if (chol_factor(Lf, mc, 0)) bad = 1;
+    }
+    return bad ? OR_ENOTSPD : OR_OK;
+}
+
+/* y = sum_i P_i A_i^-1 R_i v (one additive Schwarz correction); subdomains
+ * in index order, so the sums are deterministic. */
+static void as_apply(const oracle_t *o, int l, const double *v, double *y) {
+    const level_t *L = &o->lev[l];
+    int bs = o->bs, w = L->as_w, m = w * bs;
+    double rl[64 * 8], zl[64 * 8];
+    memset(y, 0, sizeof(double) * L->N);
+    for (int c = 0; c < L->n; ++c) {
+        const int *cells = L->as_cells + (size_t)c * w;
+        int np = 0;
+        while (np < w && cells[np] >= 0) ++np;
+        for (int a = 0; a < np; ++a)
+            for (int r = 0; r < bs; ++r) rl[a * bs + r] = v[(size_t)cells[a] * bs + r];
+        chol_solve(L->as_L + (size_t)c * m * m, np * bs, rl, zl);
+        for (int a = 0; a < np; ++a)
+            for (int r = 0; r < bs; ++r) y[(size_t)cells[a] * bs + r] += zl[a * bs + r];
+    }
+}
+
 /* Block-Jacobi (Algorithm 4) from x0 = 0 with s iterations:
  * x = omega D^-1 r, then x <- x + omega D^-1 (r - A x). Result in out. */
 static void smoother(oracle_t *o, int l, const double *r, int s, double *out) {
     level_t *L = &o->lev[l];
     double om = o->opt.omega;
+    if (o->opt.smoother == 1) { /* additive Schwarz: x = omega M r, then x <- x + omega M (r - A x) */
+        as_apply(o, l, r, out);
+        for (size_t e = 0; e < L->N; ++e) out[e] *= om;
+        for (int it = 1; it < s; ++it) {
+            level_spmv(o, l, out, r, L->t2, 0);
+            as_apply(o, l, L->t2, L->t);
+            for (size_t e = 0; e < L->N; ++e) out[e] += om * L->t[e];
+        }
+        return;
+    }
     apply_dinv(o, l, r, om, out, NULL);
     for (int it = 1; it < s; ++it) {
         level_spmv(o, l, out, r, L->t2, 0);     /* t2 = r - A x */

@@ -19,6 +19,7 @@ MAX_LEVELS = 16
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 SYNC_MULT, OVERLAP_DET, HYBRID, ADD_SYNC = 0, 1, 2, 3
 FP64, MIXED_IR, MIXED_FLEX = 0, 1, 2
+SMOOTH_BJ, SMOOTH_AS = 0, 1
 
 
 class OmgError(RuntimeError):
@@ -44,7 +45,7 @@ class Options(ctypes.Structure):
                 ("s_post", ctypes.c_int32), ("n_s", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("overlap_streams", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("n_s_max", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("n_s_max", ctypes.c_int32), ("smoother", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("inner_tol", ctypes.c_double), ("breakdown", ctypes.c_double),
                 ("crit_rel", ctypes.c_double * MAX_LEVELS), ("crit_max", ctypes.c_int32 * MAX_LEVELS)]
 
@@ -126,12 +127,13 @@ def _check(st, what):
 
 def options(**kw) -> Options:
     """omg_options with defaults; keyword names as in the struct. ``variant``
-    accepts 'sync'/'overlap'/'hybrid'/'add_sync', ``precision``
+    accepts 'sync'/'overlap'/'hybrid'/'add_sync', ``smoother`` 'bj'/'schwarz', ``precision``
     'fp64'/'mixed_ir'/'mixed_flex', and
     ``crit`` a list of (rel, max) pairs for levels 1, 2, ..."""
     o = Options()
     lib().omg_default_options(ctypes.byref(o))
-    names = {"sync": SYNC_MULT, "overlap": OVERLAP_DET, "hybrid": HYBRID, "add_sync": ADD_SYNC, "fp64": FP64, "mixed_ir": MIXED_IR,
+    names = {"sync": SYNC_MULT, "overlap": OVERLAP_DET, "hybrid": HYBRID, "add_sync": ADD_SYNC,
+             "bj": SMOOTH_BJ, "schwarz": SMOOTH_AS, "fp64": FP64, "mixed_ir": MIXED_IR,
              "mixed_flex": MIXED_FLEX}
     crit = kw.pop("crit", None)
     for k, v in kw.items():

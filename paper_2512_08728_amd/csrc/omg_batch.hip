@@ -652,7 +652,11 @@ omg_status prepare_columns(omg_solver* s, int m) {
     return OMG_OK;
 }
 
-bool lockstep_supported(const omg_solver* s) { return s->bs <= 16 && !s->owner; }
+// (the lockstep engines run the block-Jacobi smoother and fixed smoother
+// step counts; other solvers are solved column by column)
+bool lockstep_supported(const omg_solver* s) {
+    return s->bs <= 16 && !s->owner && s->opt.smoother == OMG_SMOOTH_BJ && s->opt.n_s_max <= s->opt.n_s;
+}
 
 // nrhs columns of one solver, in lockstep groups of up to kMaxCols.
 omg_status solve_columns(omg_solver* s, const double* b, double* x, int nrhs, double tol, omg_report* rep,
@@ -713,7 +717,9 @@ bool same_cycle(const omg_solver* a, const omg_solver* b) {
            a->opt.s_pre == b->opt.s_pre && a->opt.s_post == b->opt.s_post && a->opt.n_s == b->opt.n_s &&
            a->opt.omega == b->opt.omega && a->opt.precision == b->opt.precision &&
            a->opt.coarse_sync == b->opt.coarse_sync && a->opt.max_outer == b->opt.max_outer &&
-           a->opt.inner_tol == b->opt.inner_tol && !a->owner && !b->owner;
+           a->opt.inner_tol == b->opt.inner_tol && a->opt.smoother == OMG_SMOOTH_BJ &&
+           b->opt.smoother == OMG_SMOOTH_BJ && a->opt.n_s_max <= a->opt.n_s && b->opt.n_s_max <= b->opt.n_s &&
+           !a->owner && !b->owner;
 }
 
 // Independent solvers with one right-hand side each (b[i], x[i] cell-major),

@@ -142,6 +142,13 @@ struct Level {
     float* ablk32 = nullptr;
     double* dblk = nullptr;
     float* dblk32 = nullptr;
+    // additive Schwarz smoother (built when selected): patch of cell i = i and
+    // the cells its row couples to, as_w cells at most
+    int as_w = 0;
+    int* as_cells = nullptr;           // [as_w][n] cells of each patch (-1: none; present ones first)
+    int* as_rev = nullptr;             // [as_w][n] contributions to cell i: patch * as_w + slot (-1: none)
+    double* as_inv = nullptr;          // [n][m][m] patch inverses, transposed (m = as_w bs)
+    double* as_z = nullptr;            // [n][m] local corrections of one sweep
     int shared_op = 0;                 // operator arrays belong to another solver (column solvers)
     // autotuned launch shape + 1 of the multi-RHS kernels [op: spmv, bj_first,
     // bj_sweep][FP64, FP32][one tile, two tiles]; 0 = not tuned
@@ -247,6 +254,9 @@ hipError_t launch_from_soa(const double* in, double* out, int n, int bs, hipStre
 hipError_t launch_spmv(const Level& L, int bs, bool fp32, const double* x, const double* b, double* y,
                        hipStream_t st);
 hipError_t launch_bj_first(const Level& L, int bs, bool fp32, double omega, const double* r, double* x,
+                           hipStream_t st);
+omg_status as_setup(omg_solver* s, Level& L);
+hipError_t launch_as_sweep(const Level& L, int bs, double omega, const double* v, double* out, bool accumulate,
                            hipStream_t st);
 hipError_t launch_bj_sweep(const Level& L, int bs, bool fp32, double omega, const double* r, const double* xin,
                            double* xout, hipStream_t st);

@@ -61,6 +61,7 @@ extern "C" void omg_default_options(omg_options* o) {
     o->overlap_streams = 1;
     o->trace = 0;
     o->n_s_max = 0;
+    o->smoother = OMG_SMOOTH_BJ;
     o->omega = 0.7;
     o->inner_tol = 1e-5;
     o->breakdown = 1e-14;
@@ -102,6 +103,10 @@ static void free_level(Level& L) {
         hipFree(L.ablk);
         hipFree(L.ablk32);
         hipFree(L.dblk);
+        hipFree(L.as_cells);
+        hipFree(L.as_rev);
+        hipFree(L.as_inv);
+        hipFree(L.as_z);
         hipFree(L.dblk32);
     }
     hipFree(L.b);
@@ -190,8 +195,10 @@ static omg_status check_grid(const omg_grid* g) {
 static omg_status check_options(const omg_options* o) {
     if (!o) return OMG_OK;
     if (o->variant < OMG_SYNC_MULT || o->variant > OMG_ADD_SYNC || o->precision < OMG_FP64 ||
-        o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->n_s_max < 0 || o->s_pre < 0 || o->s_post < 0)
+        o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->n_s_max < 0 || o->s_pre < 0 || o->s_post < 0 ||
+        o->smoother < OMG_SMOOTH_BJ || o->smoother > OMG_SMOOTH_AS)
         return OMG_EINVAL;
+    if (o->smoother == OMG_SMOOTH_AS && o->precision != OMG_FP64) return OMG_EUNSUPPORTED;
     return OMG_OK;
 }
 
@@ -394,6 +401,7 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
         OMG_TRY(omg_alloc_level_vectors(s, L));
         if (!L.coarsest) {
             OMG_TRY(omg_block_inverses(s, L));
+            if (s->opt.smoother == OMG_SMOOTH_AS) OMG_TRY(as_setup(s, L));
             OMG_TRY(omg_fp32_copies(s, L));
             // the persistent RM runs on the caller's stream only: levels below
             // the forking level (second stream) keep the per-step kernels
@@ -666,6 +674,14 @@ static omg_status smoother(omg_solver* s, int l, const double* r, int sweeps, do
     Level& L = s->lev[l];
     const bool f32 = use32(s, l, false);
     if (sweeps < 1) sweeps = 1;
+    if (s->opt.smoother == OMG_SMOOTH_AS) { // additive Schwarz (Algorithm 3), damped sweeps from zero
+        HIP_OK(launch_as_sweep(L, s->bs, s->opt.omega, r, out, false, st));
+        for (int it = 1; it < sweeps; ++it) {
+            HIP_OK(launch_spmv(L, s->bs, false, out, r, L.t, st)); // t = r - A x
+            HIP_OK(launch_as_sweep(L, s->bs, s->opt.omega, L.t, out, true, st));
+        }
+        return OMG_OK;
+    }
     // place the last sweep's output in `out`
     double* bufs[2] = {out, L.t};
     int cur = (sweeps % 2 == 1) ? 0 : 1;

@@ -178,6 +178,40 @@ def test_adaptive_loop_replayed_by_oracle(variant, n, p, lv):
     assert np.array_equal(x_d, host(g0.solve(cuda(b))))
 
 
+@pytest.mark.parametrize("n,p,lv", [(8, 1, 3), (8, 2, 3), (4, 0, 2)])
+def test_schwarz_smoother_matches_oracle(n, p, lv):
+    """Additive Schwarz sweeps (Algorithm 3: patch inverses formed on the
+    GPU, one wavefront per patch, fixed-order gather) against the oracle's
+    Cholesky solves of the same patches, 1 and 2 sweeps, every smoothed
+    level (1e-12 relative)."""
+    prob, nu, o, g = pair(n, p, lv, smoother="schwarz")
+    rng = np.random.default_rng(3)
+    for l in range(lv - 1):
+        nl = (n >> l) ** 3 * prob.bs
+        b = rng.standard_normal(nl)
+        for sw in (1, 2):
+            ref = o.smoother(b, sw, l)
+            got = host(g.level_smoother(l, cuda(b), sw))
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (l, sw)
+
+
+@pytest.mark.parametrize("variant,n,p,lv,s", [("sync", 8, 1, 3, 1), ("sync", 16, 1, 4, 2), ("sync", 8, 2, 3, 1),
+                                              ("overlap", 16, 1, 4, 1)])
+def test_schwarz_solve_matches_oracle(variant, n, p, lv, s):
+    """Whole solves with the additive Schwarz smoother: the oracle's visit log
+    and its solution within 1e-9. The overlapping patch inverses give
+    lambda_max(M A) ~ 11 here, so repeated sweeps need omega below ~0.18; one
+    sweep is scaled by RM anyway."""
+    om = 0.7 if s == 1 else 0.1
+    prob, nu, o, g = pair(n, p, lv, smoother="schwarz", variant=variant, s_pre=s, s_post=s, omega=om)
+    b = synth.rhs(prob.n_dofs, 0)
+    x_o = o.solve(b)
+    x_g = host(g.solve(cuda(b)))
+    assert np.array_equal(o.visits(), g.visits())
+    assert g.last_report["rel_res_true"] <= 1.0001e-10
+    assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o)
+
+
 def test_orthonormal_directions_and_residual_on_gpu():
     prob, nu, o, g = pair(8, 1, 2)
     b = synth.rhs(prob.n_dofs, 0)
@@ -291,10 +325,17 @@ def test_error_paths():
     with pytest.raises(m.OmgError) as e:
         m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(-nu))
     assert e.value.status == m.EINVAL
-    for bad_opt in (dict(variant=4), dict(variant=-1), dict(n_s=0), dict(precision=3), dict(n_s_max=-1)):
+    for bad_opt in (dict(variant=4), dict(variant=-1), dict(n_s=0), dict(precision=3), dict(n_s_max=-1),
+                    dict(smoother=2)):
         with pytest.raises(m.OmgError) as e:
             m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(nu), **bad_opt)
         assert e.value.status == m.EINVAL, bad_opt
+    with pytest.raises(m.OmgError) as e:
+        m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 1, 2), cuda(nu), smoother="schwarz", precision="mixed_ir")
+    assert e.value.status == m.EUNSUPPORTED
+    with pytest.raises(m.OmgError) as e:
+        m.Solver.from_sip(m.Solver.make_grid(4, 4, 4, 3, 2), cuda(nu), smoother="schwarz")
+    assert e.value.status == m.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("dims,p,lv", [((8, 4, 6), 1, 2), ((12, 8, 8), 2, 3), ((4, 4, 4), 3, 2)])

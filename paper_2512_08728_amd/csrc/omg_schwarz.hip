@@ -114,10 +114,20 @@ __global__ __launch_bounds__(256) void k_as_apply(int n, int w, const int* __res
     double acc0 = 0.0, acc1 = 0.0;
     const bool two = lane + 64 < ma;
     if (lane < ma) {
-        for (int j = 0; j < ma; ++j) {
-            const double rj = rl[wid][j];
-            acc0 = fma(T[j * m + lane], rj, acc0);
-            if (two) acc1 = fma(T[j * m + lane + 64], rj, acc1);
+        // ma is a multiple of BS: BS independent column loads in flight per step
+        for (int j0 = 0; j0 < ma; j0 += BS) {
+            double t0[BS], t1[BS];
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj) {
+                t0[jj] = T[(j0 + jj) * m + lane];
+                t1[jj] = two ? T[(j0 + jj) * m + lane + 64] : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj) {
+                const double rj = rl[wid][j0 + jj];
+                acc0 = fma(t0[jj], rj, acc0);
+                acc1 = fma(t1[jj], rj, acc1);
+            }
         }
         z[(int64_t)P * m + lane] = acc0;
         if (two) z[(int64_t)P * m + lane + 64] = acc1;

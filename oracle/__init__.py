@@ -81,6 +81,7 @@ def lib():
         L.oracle_get_trace.argtypes = [P, P]
         L.oracle_spmv.argtypes = [P, i, P, P, P]
         L.oracle_smoother.argtypes = [P, i, P, i, P]
+        L.oracle_smoother32.argtypes = [P, i, P, i, P]
         L.oracle_restrict.argtypes = [P, i, P, P]
         L.oracle_prolong.argtypes = [P, i, P, P]
         L.oracle_coarse_solve.argtypes = [P, P, P]
@@ -256,10 +257,10 @@ class Oracle:
         lib().oracle_spmv(self._h, l, _p(x), None if bb is None else _p(bb), _p(y))
         return y
 
-    def smoother(self, r, s, l=0):
+    def smoother(self, r, s, l=0, fp32=False):
         r = np.ascontiguousarray(r, dtype=np.float64)
         out = np.zeros_like(r)
-        st = lib().oracle_smoother(self._h, l, _p(r), s, _p(out))
+        st = (lib().oracle_smoother32 if fp32 else lib().oracle_smoother)(self._h, l, _p(r), s, _p(out))
         if st != OK:
             raise OracleError(st)
         return out

@@ -20,7 +20,10 @@
  *   - additive Schwarz smoother: Algorithm 3 (Sec. 3.2) with one subdomain
  *     per cell and an overlap of one cell (the cells its matrix row couples
  *     to), local problems solved with stored Cholesky factors, corrections
- *     summed, damped by omega like the block-Jacobi sweeps;
+ *     summed, damped by omega like the block-Jacobi sweeps; in the mixed
+ *     forms the local solves are single precision (the patch inverse formed
+ *     in FP64 and rounded, the local residual rounded, products summed in
+ *     float), as the paper does;
  *   - semi-asynchronous OrthoMG, Algorithm 5 (Sec. 4), in a deterministic form:
  *     the coarse correction is computed from a snapshot of r taken at the start
  *     of the cycle, the smoother side runs a fixed number of smoother+RM steps,
@@ -85,7 +88,7 @@ typedef struct {
     int m_max;         /* 0 unbounded; else restart the level's W,Z when they hold m_max columns */
     int max_outer;     /* precision 1: maximum refinement steps */
     int n_crit;        /* number of entries used in crit_rel/crit_max (levels 1..n_crit) */
-    int smoother;      /* 0 block-Jacobi (Alg. 4); 1 additive Schwarz (Alg. 3, FP64 only) */
+    int smoother;      /* 0 block-Jacobi (Alg. 4); 1 additive Schwarz (Alg. 3) */
     int pad_smoother;
     double omega;      /* block-Jacobi damping */
     double inner_tol;  /* precision 1: relative tolerance of each inner solve */
@@ -507,6 +510,7 @@ typedef struct {
     int as_w;          /* additive Schwarz: cells per patch (row length of A) */
     int *as_cells;     /* [n][as_w] patch of cell c: c, then its row's other columns (-1: none) */
     double *as_L;      /* [n][(as_w bs)^2] Cholesky factors of the patch matrices */
+    float *as_inv32;   /* mixed forms: [n][m][m] patch inverses rounded to float, row-major */
     float *Dinv32;
     double *Lc;        /* coarsest: dense Cholesky factor */
     /* residual minimisation storage */
@@ -554,6 +558,7 @@ static void level_free(level_t *L) {
     free(L->slot);
     free(L->as_cells);
     free(L->as_L);
+    free(L->as_inv32);
 }
 
 void oracle_destroy(void *h) {
@@ -775,7 +780,6 @@ int oracle_setup(const int *row_ptr, const int *col, const double *val, int64_t 
     *out = NULL;
     if (nlev < 1 || nlev > MAXLEV || p < 0 || p > 5) return OR_EINVAL;
     if (opt && (opt->variant < 0 || opt->variant > 3 || opt->smoother < 0 || opt->smoother > 1)) return OR_EINVAL;
-    if (opt && opt->smoother == 1 && opt->precision != 0) return OR_EUNSUPPORTED;
     int bs = oracle_nbasis(p), n = nx * ny * nz;
     int rc = validate_bsr(n, bs, row_ptr, col, nnzb);
     if (rc) return rc;
@@ -806,7 +810,6 @@ int oracle_setup_sip(int nx, int ny, int nz, int p, double h, double penalty_c, 
     *out = NULL;
     if (nlev < 1 || nlev > MAXLEV || p < 0 || p > 5 || !(h > 0)) return OR_EINVAL;
     if (opt && (opt->variant < 0 || opt->variant > 3 || opt->smoother < 0 || opt->smoother > 1)) return OR_EINVAL;
-    if (opt && opt->smoother == 1 && opt->precision != 0) return OR_EUNSUPPORTED;
     int n = nx * ny * nz;
     for (int c = 0; c < n; ++c)
         if (!(nu[c] > 0.0) || !isfinite(nu[c])) return OR_EINVAL;
@@ -905,15 +908,38 @@ static int as_setup(oracle_t *o, int l) {
             }
         if (chol_factor(Lf, mc, 0)) bad = 1;
     }
-    return bad ? OR_ENOTSPD : OR_OK;
+    if (bad) return OR_ENOTSPD;
+    if (o->opt.precision != 0) { /* single-precision local solves: inverse columns by Cholesky solves */
+        L->as_inv32 = malloc(sizeof(float) * (size_t)L->n * m * m);
+        if (!L->as_inv32) return OR_ENOMEM;
+#pragma omp parallel for schedule(static)
+        for (int c = 0; c < L->n; ++c) {
+            const int *cells = L->as_cells + (size_t)c * w;
+            int np = 0;
+            while (np < w && cells[np] >= 0) ++np;
+            int mc = np * bs;
+            double e[64 * 8], x[64 * 8];
+            float *I32 = L->as_inv32 + (size_t)c * m * m;
+            for (int j = 0; j < mc; ++j) {
+                for (int i = 0; i < mc; ++i) e[i] = (i == j) ? 1.0 : 0.0;
+                chol_solve(L->as_L + (size_t)c * m * m, mc, e, x);
+                for (int i = 0; i < mc; ++i) I32[(size_t)i * mc + j] = (float)x[i];
+            }
+        }
+    }
+    return OR_OK;
 }
 
+static int use32(const oracle_t *o, int l, int is_rm);
+
 /* y = sum_i P_i A_i^-1 R_i v (one additive Schwarz correction); subdomains
- * in index order, so the sums are deterministic. */
+ * in index order, so the sums are deterministic. Single-precision local
+ * solves where the level's smoother runs in FP32. */
 static void as_apply(const oracle_t *o, int l, const double *v, double *y) {
     const level_t *L = &o->lev[l];
-    int bs = o->bs, w = L->as_w, m = w * bs;
+    int bs = o->bs, w = L->as_w, m = w * bs, f32 = use32(o, l, 0);
     double rl[64 * 8], zl[64 * 8];
+    float r32[64 * 8];
     memset(y, 0, sizeof(double) * L->N);
     for (int c = 0; c < L->n; ++c) {
         const int *cells = L->as_cells + (size_t)c * w;
@@ -921,7 +947,18 @@ static void as_apply(const oracle_t *o, int l, const double *v, double *y) {
         while (np < w && cells[np] >= 0) ++np;
         for (int a = 0; a < np; ++a)
             for (int r = 0; r < bs; ++r) rl[a * bs + r] = v[(size_t)cells[a] * bs + r];
-        chol_solve(L->as_L + (size_t)c * m * m, np * bs, rl, zl);
+        if (f32) {
+            int mc = np * bs;
+            const float *I32 = L->as_inv32 + (size_t)c * m * m;
+            for (int i = 0; i < mc; ++i) r32[i] = (float)rl[i];
+            for (int i = 0; i < mc; ++i) {
+                float s = 0.0f;
+                for (int j = 0; j < mc; ++j) s += I32[(size_t)i * mc + j] * r32[j];
+                zl[i] = (double)s;
+            }
+        } else {
+            chol_solve(L->as_L + (size_t)c * m * m, np * bs, rl, zl);
+        }
         for (int a = 0; a < np; ++a)
             for (int r = 0; r < bs; ++r) y[(size_t)cells[a] * bs + r] += zl[a * bs + r];
     }
@@ -1354,6 +1391,18 @@ int oracle_smoother(void *h, int l, const double *r, int s, double *out) {
     oracle_t *o = h;
     if (l >= o->nlev - 1) return OR_EINVAL;
     smoother(o, l, r, s, out);
+    return OR_OK;
+}
+
+/* The smoother in the single-precision form of the mixed solves (FP32
+ * matrices and local solves); needs a solver set up with a mixed precision. */
+int oracle_smoother32(void *h, int l, const double *r, int s, double *out) {
+    oracle_t *o = h;
+    if (l >= o->nlev - 1 || o->opt.precision == 0) return OR_EINVAL;
+    int saved = o->mode32;
+    o->mode32 = 1;
+    smoother(o, l, r, s, out);
+    o->mode32 = saved;
     return OR_OK;
 }
 

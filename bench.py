@@ -321,9 +321,10 @@ def main():
         # one-cell overlap, patch inverses formed at setup) in Algorithm 2:
         # one sweep (omega cancels in RM) and two sweeps damped to 0.1 (the
         # overlapping patch inverses give lambda_max(M A) ~ 11, so repeated
-        # sweeps need omega below ~0.18)
-        for sw, om in ((1, 0.7), (2, 0.1)):
-            o2 = dict(opts, s_pre=sw, s_post=sw, omega=om)
+        # sweeps need omega below ~0.18); the last with single-precision local
+        # solves inside the mixed form
+        for sw, om, prec in ((1, 0.7, "fp64"), (2, 0.1, "fp64"), (2, 0.1, "mixed_flex")):
+            o2 = dict(opts, s_pre=sw, s_post=sw, omega=om, precision=prec)
             t0 = time.perf_counter()
             so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), smoother="schwarz", **o2)
             torch.cuda.synchronize()
@@ -335,7 +336,7 @@ def main():
             torch.cuda.synchronize()
             to = time.perf_counter() - t0
             r = so.last_report
-            name = f"schwarz_{sw}+{sw}"
+            name = f"schwarz_{sw}+{sw}" + ("" if prec == "fp64" else f"_{prec}")
             variants[name] = {"value": prob.n_dofs / to, "unit": "DOF/s", "ms_per_step": round(to * 1e3, 2),
                               "iters_fine": r["iters_fine"], "rel_res_true": r["rel_res_true"],
                               "setup_s": round(ts, 3),

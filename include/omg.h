@@ -58,7 +58,8 @@ enum { OMG_FP64 = 0, OMG_MIXED_IR = 1, OMG_MIXED_FLEX = 2 };    /* precision */
 /* smoother: damped block-Jacobi (Algorithm 4), or additive Schwarz
  * (Algorithm 3) with one subdomain per cell and an overlap of one cell (the
  * cells its matrix row couples to), local problems solved with inverses
- * formed at setup, FP64 only, P <= 2; the same omega damps its sweeps */
+ * formed at setup (single precision in the mixed forms), P <= 2; the same
+ * omega damps its sweeps */
 enum { OMG_SMOOTH_BJ = 0, OMG_SMOOTH_AS = 1 };
 enum { OMG_MAX_LEVELS = 16 };
 
@@ -103,8 +104,8 @@ typedef struct {
                              taking smoother+RM steps until the coarse path has finished, at
                              least n_s and at most n_s_max (counts: omg_get_step_counts);
                              results then depend on timing. <= n_s: deterministic */
-    int32_t smoother;     /* OMG_SMOOTH_BJ or OMG_SMOOTH_AS (OMG_EUNSUPPORTED with mixed precision
-                             or P3); batched solves of such solvers go column by column */
+    int32_t smoother;     /* OMG_SMOOTH_BJ or OMG_SMOOTH_AS (OMG_EUNSUPPORTED for P3); batched
+                             solves of such solvers go column by column */
     double omega;         /* block-Jacobi damping */
     double inner_tol;     /* OMG_MIXED_IR: relative tolerance of each inner solve */
     double breakdown;     /* RM drops a direction when ||w_out|| <= breakdown * ||w_in|| */

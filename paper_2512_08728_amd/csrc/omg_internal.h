@@ -148,6 +148,7 @@ struct Level {
     int* as_cells = nullptr;           // [as_w][n] cells of each patch (-1: none; present ones first)
     int* as_rev = nullptr;             // [as_w][n] contributions to cell i: patch * as_w + slot (-1: none)
     double* as_inv = nullptr;          // [n][m][m] patch inverses, transposed (m = as_w bs)
+    float* as_inv32 = nullptr;         // the same rounded to float (mixed forms)
     double* as_z = nullptr;            // [n][m] local corrections of one sweep
     int shared_op = 0;                 // operator arrays belong to another solver (column solvers)
     // autotuned launch shape + 1 of the multi-RHS kernels [op: spmv, bj_first,
@@ -256,8 +257,8 @@ hipError_t launch_spmv(const Level& L, int bs, bool fp32, const double* x, const
 hipError_t launch_bj_first(const Level& L, int bs, bool fp32, double omega, const double* r, double* x,
                            hipStream_t st);
 omg_status as_setup(omg_solver* s, Level& L);
-hipError_t launch_as_sweep(const Level& L, int bs, double omega, const double* v, double* out, bool accumulate,
-                           hipStream_t st);
+hipError_t launch_as_sweep(const Level& L, int bs, bool fp32, double omega, const double* v, double* out,
+                           bool accumulate, hipStream_t st);
 hipError_t launch_bj_sweep(const Level& L, int bs, bool fp32, double omega, const double* r, const double* xin,
                            double* xout, hipStream_t st);
 hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,

@@ -20,6 +20,9 @@
 //               cell's own patch list, and update x (no atomics, so results
 //               are deterministic).
 // Further sweeps add omega M (v - A x) with the level's residual SpMV.
+// In the mixed forms the local solves are single precision, as in the paper:
+// the inverse (formed in FP64) is stored rounded to float, the local residual
+// is rounded and the products are summed in float; the gather stays FP64.
 // Algorithmic bytes per sweep: the stored inverses (n m^2 8), v gathered
 // (w N 8), z written and read back (2 n m 8), x written.
 #include <vector>
@@ -92,12 +95,13 @@ __global__ __launch_bounds__(256) void k_as_build(int n, int width, int w, const
     }
 }
 
-// z_i = A_i^-1 R_i v for four patches per block, one wavefront each.
-template <int BS>
+// z_i = A_i^-1 R_i v for four patches per block, one wavefront each; T is
+// the precision of the stored inverse and of the local solve.
+template <int BS, typename T>
 __global__ __launch_bounds__(256) void k_as_apply(int n, int w, const int* __restrict__ cells,
-                                                  const double* __restrict__ inv, const double* __restrict__ v,
+                                                  const T* __restrict__ inv, const double* __restrict__ v,
                                                   double* __restrict__ z) {
-    __shared__ double rl[4][kAsMaxM];
+    __shared__ T rl[4][kAsMaxM];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int P = blockIdx.x * 4 + wid;
     if (P >= n) return; // whole wavefront
@@ -107,30 +111,30 @@ __global__ __launch_bounds__(256) void k_as_apply(int n, int w, const int* __res
     const int ma = np * BS;
     for (int t = lane; t < m; t += 64) {
         const int cell = cells[(int64_t)(t / BS) * n + P];
-        rl[wid][t] = cell >= 0 ? v[(int64_t)(t % BS) * n + cell] : 0.0;
+        rl[wid][t] = cell >= 0 ? (T)v[(int64_t)(t % BS) * n + cell] : (T)0;
     }
     __builtin_amdgcn_wave_barrier();
-    const double* T = inv + (int64_t)P * m * m;
-    double acc0 = 0.0, acc1 = 0.0;
+    const T* Ti = inv + (int64_t)P * m * m;
+    T acc0 = 0, acc1 = 0;
     const bool two = lane + 64 < ma;
     if (lane < ma) {
         // ma is a multiple of BS: BS independent column loads in flight per step
         for (int j0 = 0; j0 < ma; j0 += BS) {
-            double t0[BS], t1[BS];
+            T t0[BS], t1[BS];
 #pragma unroll
             for (int jj = 0; jj < BS; ++jj) {
-                t0[jj] = T[(j0 + jj) * m + lane];
-                t1[jj] = two ? T[(j0 + jj) * m + lane + 64] : 0.0;
+                t0[jj] = Ti[(j0 + jj) * m + lane];
+                t1[jj] = two ? Ti[(j0 + jj) * m + lane + 64] : (T)0;
             }
 #pragma unroll
             for (int jj = 0; jj < BS; ++jj) {
-                const double rj = rl[wid][j0 + jj];
+                const T rj = rl[wid][j0 + jj];
                 acc0 = fma(t0[jj], rj, acc0);
                 acc1 = fma(t1[jj], rj, acc1);
             }
         }
-        z[(int64_t)P * m + lane] = acc0;
-        if (two) z[(int64_t)P * m + lane + 64] = acc1;
+        z[(int64_t)P * m + lane] = (double)acc0;
+        if (two) z[(int64_t)P * m + lane + 64] = (double)acc1;
     }
 }
 
@@ -150,6 +154,11 @@ __global__ __launch_bounds__(256) void k_as_gather(int n, int w, const int* __re
         if (q >= 0) e += z[(int64_t)(q / w) * m + (q % w) * BS + c];
     }
     x[t] = accumulate ? x[t] + omega * e : omega * e;
+}
+
+__global__ void k_as_round(int64_t cnt, const double* __restrict__ in, float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < cnt) out[e] = (float)in[e];
 }
 
 #define OMG_AS_DISPATCH(bs, CALL)                              \
@@ -204,31 +213,41 @@ omg_status as_setup(omg_solver* s, Level& L) {
     OMG_AS_DISPATCH(bs, hipLaunchKernelGGL((k_as_build<BSV>), dim3(n), dim3(256), 0, s->stream, n, L.width, w, L.col,
                                            L.dslot, L.val, L.as_cells, L.as_inv));
     OMG_TRY_HIP(hipGetLastError());
+    if (s->opt.precision != OMG_FP64) { // single-precision local solves of the mixed forms
+        const int64_t cnt = (int64_t)n * m * m;
+        if (hipMalloc((void**)&L.as_inv32, sizeof(float) * cnt) != hipSuccess) {
+            (void)hipGetLastError();
+            return OMG_ENOMEM;
+        }
+        hipLaunchKernelGGL(k_as_round, dim3(cdiv(cnt, 256)), dim3(256), 0, s->stream, cnt, L.as_inv, L.as_inv32);
+        OMG_TRY_HIP(hipGetLastError());
+    }
     return OMG_OK;
 }
 
-// One sweep: out = omega M v (accumulate = 0) or out + omega M v.
-hipError_t launch_as_sweep(const Level& L, int bs, double omega, const double* v, double* out, bool accumulate,
-                           hipStream_t st) {
+template <int BS>
+static void as_sweep(const Level& L, bool fp32, double omega, const double* v, double* out, bool accumulate,
+                     hipStream_t st) {
     const int n = L.n, w = L.as_w;
-    if (!L.as_inv || w * bs > kAsMaxM) return hipErrorInvalidValue;
+    if (fp32)
+        hipLaunchKernelGGL((k_as_apply<BS, float>), dim3(cdiv(n, 4)), dim3(256), 0, st, n, w, L.as_cells, L.as_inv32,
+                           v, L.as_z);
+    else
+        hipLaunchKernelGGL((k_as_apply<BS, double>), dim3(cdiv(n, 4)), dim3(256), 0, st, n, w, L.as_cells, L.as_inv,
+                           v, L.as_z);
+    hipLaunchKernelGGL((k_as_gather<BS>), dim3(cdiv((int64_t)n * BS, 256)), dim3(256), 0, st, n, w, L.as_rev, L.as_z,
+                       omega, (int)accumulate, out);
+}
+
+// One sweep: out = omega M v (accumulate = 0) or out + omega M v; fp32
+// selects the single-precision local solves.
+hipError_t launch_as_sweep(const Level& L, int bs, bool fp32, double omega, const double* v, double* out,
+                           bool accumulate, hipStream_t st) {
+    if (!L.as_inv || L.as_w * bs > kAsMaxM || (fp32 && !L.as_inv32)) return hipErrorInvalidValue;
     switch (bs) {
-    case 1: {
-        hipLaunchKernelGGL((k_as_apply<1>), dim3(cdiv(n, 4)), dim3(256), 0, st, n, w, L.as_cells, L.as_inv, v, L.as_z);
-        hipLaunchKernelGGL((k_as_gather<1>), dim3(cdiv((int64_t)n, 256)), dim3(256), 0, st, n, w, L.as_rev, L.as_z,
-                           omega, (int)accumulate, out);
-    } break;
-    case 4: {
-        hipLaunchKernelGGL((k_as_apply<4>), dim3(cdiv(n, 4)), dim3(256), 0, st, n, w, L.as_cells, L.as_inv, v, L.as_z);
-        hipLaunchKernelGGL((k_as_gather<4>), dim3(cdiv((int64_t)n * 4, 256)), dim3(256), 0, st, n, w, L.as_rev,
-                           L.as_z, omega, (int)accumulate, out);
-    } break;
-    case 10: {
-        hipLaunchKernelGGL((k_as_apply<10>), dim3(cdiv(n, 4)), dim3(256), 0, st, n, w, L.as_cells, L.as_inv, v,
-                           L.as_z);
-        hipLaunchKernelGGL((k_as_gather<10>), dim3(cdiv((int64_t)n * 10, 256)), dim3(256), 0, st, n, w, L.as_rev,
-                           L.as_z, omega, (int)accumulate, out);
-    } break;
+    case 1: as_sweep<1>(L, fp32, omega, v, out, accumulate, st); break;
+    case 4: as_sweep<4>(L, fp32, omega, v, out, accumulate, st); break;
+    case 10: as_sweep<10>(L, fp32, omega, v, out, accumulate, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -106,6 +106,7 @@ static void free_level(Level& L) {
         hipFree(L.as_cells);
         hipFree(L.as_rev);
         hipFree(L.as_inv);
+        hipFree(L.as_inv32);
         hipFree(L.as_z);
         hipFree(L.dblk32);
     }
@@ -198,7 +199,6 @@ static omg_status check_options(const omg_options* o) {
         o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->n_s_max < 0 || o->s_pre < 0 || o->s_post < 0 ||
         o->smoother < OMG_SMOOTH_BJ || o->smoother > OMG_SMOOTH_AS)
         return OMG_EINVAL;
-    if (o->smoother == OMG_SMOOTH_AS && o->precision != OMG_FP64) return OMG_EUNSUPPORTED;
     return OMG_OK;
 }
 
@@ -675,10 +675,10 @@ static omg_status smoother(omg_solver* s, int l, const double* r, int sweeps, do
     const bool f32 = use32(s, l, false);
     if (sweeps < 1) sweeps = 1;
     if (s->opt.smoother == OMG_SMOOTH_AS) { // additive Schwarz (Algorithm 3), damped sweeps from zero
-        HIP_OK(launch_as_sweep(L, s->bs, s->opt.omega, r, out, false, st));
+        HIP_OK(launch_as_sweep(L, s->bs, f32, s->opt.omega, r, out, false, st));
         for (int it = 1; it < sweeps; ++it) {
-            HIP_OK(launch_spmv(L, s->bs, false, out, r, L.t, st)); // t = r - A x
-            HIP_OK(launch_as_sweep(L, s->bs, s->opt.omega, L.t, out, true, st));
+            HIP_OK(launch_spmv(L, s->bs, f32, out, r, L.t, st)); // t = r - A x
+            HIP_OK(launch_as_sweep(L, s->bs, f32, s->opt.omega, L.t, out, true, st));
         }
         return OMG_OK;
     }

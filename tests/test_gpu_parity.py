@@ -232,6 +232,24 @@ def test_schwarz_mixed_precision(mode):
     assert err < 1e-4
 
 
+def test_adaptive_loop_with_mixed_precision():
+    """Timing-adaptive cycles inside the mixed forms (FP32 inner work on both
+    host threads' streams, FP64 refinement): the true FP64 residual reaches
+    1e-10 and the solution is within 1e-4 of the FP64 oracle."""
+    prob, nu, o, _ = pair(16, 1, 4, variant="overlap", s_post=2, n_s=1)
+    b = synth.rhs(prob.n_dofs, 0)
+    x64 = o.solve(b)
+    A = o.scipy_matrix(0)
+    for mode in ("mixed_ir", "mixed_flex"):
+        g = omg().Solver.from_sip(grid_of(prob), cuda(nu), variant="overlap", s_post=2, n_s=1, n_s_max=6,
+                                  precision=mode)
+        x = host(g.solve(cuda(b)))
+        counts = g.step_counts()
+        assert len(counts) > 0 and counts.min() >= 1 and counts.max() <= 6
+        assert np.linalg.norm(b - A @ x) <= 1.0001e-10 * np.linalg.norm(b), mode
+        assert np.linalg.norm(x - x64) <= 1e-4 * np.linalg.norm(x64), mode
+
+
 def test_orthonormal_directions_and_residual_on_gpu():
     prob, nu, o, g = pair(8, 1, 2)
     b = synth.rhs(prob.n_dofs, 0)

@@ -249,8 +249,10 @@ omg_status omg_get_visits(const omg_solver *s, int32_t *out, int32_t cap, int32_
 omg_status omg_get_trace(const omg_solver *s, double *out, int32_t cap, int32_t *n);
 /* Smoother+RM steps taken in each cycle of the forking level during the
  * last solve (OVERLAP_DET: the finest level; HYBRID: level 1), in execution
- * order, into host out[cap]; count in *n (out nullable). n_s each unless the
- * cycle was timing-adaptive. */
+ * order, into host out[cap] (caller-owned; at most cap written); count in *n
+ * (out nullable to query it). n_s each unless the cycle was timing-adaptive
+ * (adaptive loops, Sec. 4.3), where replaying these counts reproduces the
+ * solve. OMG_EINVAL for a NULL solver or n. */
 omg_status omg_get_step_counts(const omg_solver *s, int32_t *out, int32_t cap, int32_t *n);
 /* Replay: make the next solve(s) use these per-visit iteration counts
  * (host pairs (level, iterations), n entries) instead of the level tests;

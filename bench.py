@@ -297,11 +297,15 @@ def main():
     if not args.no_mixed:
         variants = {"sync_mult": {"value": value, "unit": "DOF/s", "ms_per_step": round(ms_per_step, 2),
                                   "iters_fine": rep["iters_fine"], "rel_res_true": rep["rel_res_true"]}}
-        # the last two: timing-adaptive loops (Sec. 4.3), the smoother side
-        # stepping while the coarse path runs (at most 8 steps per cycle)
-        for name, v, nsm in (("overlap_det", "overlap", 0), ("hybrid", "hybrid", 0), ("add_sync", "add_sync", 0),
-                             ("overlap_adaptive", "overlap", 8), ("hybrid_adaptive", "hybrid", 8)):
-            so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), variant=v, n_s_max=nsm, **opts)
+        # the last three: timing-adaptive loops (Sec. 4.3), the smoother side
+        # stepping while the coarse path runs (at most 10 steps per cycle),
+        # the last of them inside the mixed form with FP32 inner work
+        for name, v, nsm, prec in (("overlap_det", "overlap", 0, "fp64"), ("hybrid", "hybrid", 0, "fp64"),
+                                   ("add_sync", "add_sync", 0, "fp64"), ("overlap_adaptive", "overlap", 10, "fp64"),
+                                   ("hybrid_adaptive", "hybrid", 10, "fp64"),
+                                   ("overlap_adaptive_mixed_flex", "overlap", 10, "mixed_flex")):
+            so = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), variant=v, n_s_max=nsm, precision=prec,
+                                     **opts)
             so.solve(b, tol=1e-10)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

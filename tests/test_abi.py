@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads and
-exports every function that include/omg.h declares."""
+exports every function that include/omg.h declares, and the binding's ctypes
+structures have the C layout of the header's structures."""
 import ctypes
 import os
 import re
@@ -50,3 +51,40 @@ def test_strerror_and_defaults_without_gpu():
     assert o.omega == 0.7 and o.crit_rel[0] == 0.1 and o.crit_max[0] == 20
     assert o.crit_rel[1] == 0.5 and o.crit_max[1] == 2 and o.crit_max[2] == 1
     assert omg.lib().omg_strerror(omg.ENOTSPD) == b"matrix not symmetric positive definite"
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Compile a C program against include/omg.h (gcc) that prints the size
+    and every field offset of the option, report, grid and BSR structures;
+    the ctypes mirrors must agree field by field."""
+    import paper_2512_08728_amd as omg
+    mirrors = {"omg_options": omg.Options, "omg_report": omg.Report, "omg_grid": omg.Grid, "omg_bsr": omg.Bsr}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("    return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_option_names_map_to_header_values():
+    import paper_2512_08728_amd as omg
+    if not os.path.exists(LIB):
+        pytest.skip("libomg.so not built")
+    o = omg.options(variant="hybrid", smoother="schwarz", n_s_max=5, precision="mixed_flex")
+    assert (o.variant, o.smoother, o.n_s_max, o.precision) == (omg.HYBRID, omg.SMOOTH_AS, 5, omg.MIXED_FLEX)
+    src = open(HEADER).read()
+    for name, val in (("OMG_SYNC_MULT", omg.SYNC_MULT), ("OMG_OVERLAP_DET", omg.OVERLAP_DET),
+                      ("OMG_HYBRID", omg.HYBRID), ("OMG_ADD_SYNC", omg.ADD_SYNC), ("OMG_SMOOTH_BJ", omg.SMOOTH_BJ),
+                      ("OMG_SMOOTH_AS", omg.SMOOTH_AS), ("OMG_MIXED_FLEX", omg.MIXED_FLEX)):
+        assert re.search(rf"\b{name}\s*=\s*{val}\b", src), name

@@ -992,6 +992,26 @@ static void reset_logs(omg_solver* s) {
         if (L.scal) hipMemsetAsync(L.scal, 0, sizeof(double) * S_COUNT, s->stream);
 }
 
+// A raised abort flag on a persistent level means a bounded wait of one of
+// its RM launches expired (a block was not resident in time): the results of
+// the solve are not trustworthy. The flag is cleared and the level's exchange
+// words are reset before its next launch.
+static omg_status check_rm_abort(omg_solver* s) {
+    HIP_OK(hipStreamSynchronize(s->stream));
+    omg_status st = OMG_OK;
+    for (Level& L : s->lev) {
+        if (!L.persist || !L.bar) continue;
+        unsigned f = 0;
+        HIP_OK(hipMemcpy(&f, L.bar + 1, sizeof(unsigned), hipMemcpyDeviceToHost));
+        if (f) {
+            HIP_OK(hipMemset(L.bar + 1, 0, sizeof(unsigned)));
+            L.slot_G = -1;
+            st = OMG_EHIP;
+        }
+    }
+    return st;
+}
+
 static omg_status solve_internal(omg_solver* s, const double* b_soa, double* x_soa, double tol, omg_report* R) {
     reset_logs(s);
     ReplayState rs;
@@ -1004,7 +1024,8 @@ static omg_status solve_internal(omg_solver* s, const double* b_soa, double* x_s
     }
     omg_status st = solve_soa(s, b_soa, x_soa, tol, R);
     g_replay = nullptr;
-    return st;
+    const omg_status ab = check_rm_abort(s);
+    return ab != OMG_OK ? ab : st;
 }
 
 extern "C" omg_status omg_solve(omg_solver* s, const double* b, double* x, double tol, double* r_out,

@@ -130,7 +130,7 @@ def batched_bench(omg, synth, torch):
     return out
 
 
-def cpu_baseline(prob, nu, b, gpu_cycles, cycles=2):
+def cpu_baseline(prob, nu, b, gpu_cycles, cycles=4):
     """The FP64 oracle on the host cores: the first `cycles` cycles of the
     same solve, scaled to DOF/s of the full solve by the GPU's cycle count."""
     import oracle

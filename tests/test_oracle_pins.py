@@ -607,6 +607,38 @@ def test_schwarz_solve_converges_and_single_precision_local_solves():
     assert om.last_report["rel_res_true"] <= 1.0001e-10
 
 
+def test_restart_after_m_max_directions():
+    """Option m_max (bounded direction storage, reading 9): when a level holds
+    m_max directions, the next RM restarts from x0 = x, r0 = r with W = Z = {}.
+    First cycle of Algorithm 2 on 2 levels with s = 1 and m_max = 2: z1, z2 are
+    combined by least squares from b, then z3 = omega D^-1 r2 alone from r2
+    (dense); without the restart x spans all three directions (differs).
+    Solves with restarts still reach 1e-10 with a monotone residual, and an
+    m_max above the number of directions equals no restart bit for bit."""
+    prob, nu, o = sip(4, 1, n_levels=2, max_iter=1, s_pre=1, s_post=1, m_max=2)
+    b = synth.rhs(prob.n_dofs, 11)
+    x = o.solve(b, check=False)
+    A, Dinv, P, Ac = _dense_parts(o, prob)
+    z1 = 0.7 * Dinv @ b
+    _, r1 = _lsq_update(A, [z1], b)
+    z2 = P @ np.linalg.solve(Ac, P.T @ r1)
+    xa, r2 = _lsq_update(A, [z1, z2], b)
+    z3 = 0.7 * Dinv @ r2
+    xb, _ = _lsq_update(A, [z3], r2)
+    assert np.linalg.norm(x - (xa + xb)) <= 1e-9 * np.linalg.norm(xa + xb)
+    xr, _ = _lsq_update(A, [z1, z2, z3], b)
+    assert np.linalg.norm(x - xr) > 1e-6 * np.linalg.norm(xr)
+    prob, nu, o = sip(8, 1, n_levels=3, m_max=8)
+    b = synth.rhs(prob.n_dofs, 0)
+    o.solve(b)
+    assert o.last_report["rel_res_true"] <= 1.0001e-10
+    rn = o.trace()[:, 1]
+    assert np.all(rn[1:] <= rn[:-1] * (1 + 1e-14))
+    _, _, o1 = sip(8, 1, n_levels=3)
+    _, _, o2 = sip(8, 1, n_levels=3, m_max=100000)
+    assert np.array_equal(o1.solve(b), o2.solve(b))
+
+
 def test_level_criteria_counts():
     """Sec. 4.2: level 1 stops at 0.1 r0 or 20 iterations, level 2 at 0.5 r0
     or 2 iterations, deeper levels after one iteration."""

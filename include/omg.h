@@ -106,6 +106,11 @@ typedef struct {
                              results then depend on timing. <= n_s: deterministic */
     int32_t smoother;     /* OMG_SMOOTH_BJ or OMG_SMOOTH_AS (OMG_EUNSUPPORTED for P3); batched
                              solves of such solvers go column by column */
+    int32_t m_max;        /* 0: directions grow within a level solve (the paper sets no limit);
+                             > 0: a level holding m_max directions restarts before its next RM
+                             from x0 = x, r0 = r with W = Z = {} (bounds their storage);
+                             batched solves of such solvers go column by column */
+    int32_t pad1;
     double omega;         /* block-Jacobi damping */
     double inner_tol;     /* OMG_MIXED_IR: relative tolerance of each inner solve */
     double breakdown;     /* RM drops a direction when ||w_out|| <= breakdown * ||w_in|| */

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("s_post", ctypes.c_int32), ("n_s", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("overlap_streams", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("n_s_max", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("n_s_max", ctypes.c_int32), ("smoother", ctypes.c_int32), ("m_max", ctypes.c_int32),
+                ("pad1", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("inner_tol", ctypes.c_double), ("breakdown", ctypes.c_double),
                 ("crit_rel", ctypes.c_double * MAX_LEVELS), ("crit_max", ctypes.c_int32 * MAX_LEVELS)]
 

@@ -652,10 +652,11 @@ omg_status prepare_columns(omg_solver* s, int m) {
     return OMG_OK;
 }
 
-// (the lockstep engines run the block-Jacobi smoother and fixed smoother
-// step counts; other solvers are solved column by column)
+// (the lockstep engines run the block-Jacobi smoother, fixed smoother step
+// counts and no restarts; other solvers are solved column by column)
 bool lockstep_supported(const omg_solver* s) {
-    return s->bs <= 16 && !s->owner && s->opt.smoother == OMG_SMOOTH_BJ && s->opt.n_s_max <= s->opt.n_s;
+    return s->bs <= 16 && !s->owner && s->opt.smoother == OMG_SMOOTH_BJ && s->opt.n_s_max <= s->opt.n_s &&
+           s->opt.m_max == 0;
 }
 
 // nrhs columns of one solver, in lockstep groups of up to kMaxCols.
@@ -719,6 +720,7 @@ bool same_cycle(const omg_solver* a, const omg_solver* b) {
            a->opt.coarse_sync == b->opt.coarse_sync && a->opt.max_outer == b->opt.max_outer &&
            a->opt.inner_tol == b->opt.inner_tol && a->opt.smoother == OMG_SMOOTH_BJ &&
            b->opt.smoother == OMG_SMOOTH_BJ && a->opt.n_s_max <= a->opt.n_s && b->opt.n_s_max <= b->opt.n_s &&
+           a->opt.m_max == 0 && b->opt.m_max == 0 &&
            !a->owner && !b->owner;
 }
 

@@ -186,6 +186,8 @@ struct Level {
     int ucap = 0;                      // maximum directions of one level solve
     double *alphas = nullptr, *gammas = nullptr, *gram = nullptr, *dvec = nullptr;
     int Grn = 1;                       // number of ||r||^2 partials written by the last update
+    int restarted = 0;                 // the current level solve restarted (m_max): x holds the
+                                       // share of the directions dropped at the restarts
 };
 
 struct Trace {

@@ -197,7 +197,7 @@ static omg_status check_options(const omg_options* o) {
     if (!o) return OMG_OK;
     if (o->variant < OMG_SYNC_MULT || o->variant > OMG_ADD_SYNC || o->precision < OMG_FP64 ||
         o->precision > OMG_MIXED_FLEX || o->n_s < 1 || o->n_s_max < 0 || o->s_pre < 0 || o->s_post < 0 ||
-        o->smoother < OMG_SMOOTH_BJ || o->smoother > OMG_SMOOTH_AS)
+        o->smoother < OMG_SMOOTH_BJ || o->smoother > OMG_SMOOTH_AS || o->m_max < 0)
         return OMG_EINVAL;
     return OMG_OK;
 }
@@ -573,8 +573,26 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k) {
 // normalise, append, alpha = w.r, x += alpha z, r -= alpha w. Leaves the
 // partials of ||r||^2 in part slot 4 (L.Grn of them).
 static omg_status rm_apply(omg_solver* s, int l, double* z, hipStream_t st);
+// Restart of a level solve that holds m_max directions (bounded storage;
+// the paper sets no limit): x0 = x, r0 = r, W = Z = {}. On a level with
+// implicit directions the share of x carried by the dropped directions is
+// formed now and accumulated in L.x (zero since level entry), which the
+// level's result adds at the end; elsewhere x is explicit already.
+static omg_status restart_level(omg_solver* s, int l, hipStream_t st) {
+    Level& L = s->lev[l];
+    if (L.persist && L.k > 0) {
+        HIP_OK(launch_recon(L.k, L.hist, L.gammas, L.alphas, L.dvec, st));
+        HIP_OK(launch_lincomb(L.N, L.k, L.dvec, L.dZp, L.t2, st));
+        HIP_OK(launch_axpy(L.x, 1.0, L.t2, L.N, st));
+        L.restarted = 1;
+    }
+    L.k = 0;
+    return OMG_OK;
+}
+
 static omg_status rm(omg_solver* s, int l, double* z, hipStream_t st) {
     Level& L = s->lev[l];
+    if (s->opt.m_max > 0 && L.k >= s->opt.m_max) OMG_TRY(restart_level(s, l, st));
     const int kspmv = use32(s, l, true) ? OMG_K_SPMV32 : OMG_K_SPMV;
     probe_begin(s, kspmv, l, st);
     HIP_OK(launch_spmv(L, s->bs, use32(s, l, true), z, nullptr, L.w, st));
@@ -804,6 +822,7 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     }
     Level& C = s->lev[l + 1];
     L.k = 0;
+    L.restarted = 0;
     HIP_OK(launch_level_init(L.N, L.G, b, L.x, L.r, L.part + 4 * kMaxRedBlocks, st));
     L.Grn = L.G;
     double r0n;
@@ -876,6 +895,7 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     if (L.persist) { // x = sum_k d_k z~_k: the search directions are implicit
         HIP_OK(launch_recon(L.k, L.hist, L.gammas, L.alphas, L.dvec, st));
         HIP_OK(launch_lincomb(L.N, L.k, L.dvec, L.dZp, xout, st));
+        if (L.restarted) HIP_OK(launch_axpy(xout, 1.0, L.x, L.N, st)); // directions dropped at restarts
     }
     else
         HIP_OK(launch_copy(xout, L.x, L.N, st));

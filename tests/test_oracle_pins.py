@@ -316,6 +316,22 @@ def test_recursive_vs_true_residual(solved_8p1):
     assert np.linalg.norm((b - A @ x) - r) <= 1e-12 * np.linalg.norm(b)
 
 
+def test_mgs2_mode():
+    """Oracle option: MGS with one DGKS re-orthogonalisation pass (repeat
+    the sweep when ||w_out|| < ||w_in|| / sqrt(2)). It keeps W orthonormal to
+    1e-13, reaches the residual 1e-10 and, on this well-converged problem,
+    agrees with plain MGS to 1e-8 relative."""
+    prob, nu, o2 = sip(8, 1, n_levels=2, gs="mgs2")
+    _, _, o1 = sip(8, 1, n_levels=2)
+    b = synth.rhs(prob.n_dofs, 0)
+    x2 = o2.solve(b)
+    x1 = o1.solve(b)
+    assert o2.last_report["rel_res_true"] <= 1.0001e-10
+    W, _ = o2.dirs(0)
+    assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 1e-13
+    assert np.linalg.norm(x2 - x1) <= 1e-8 * np.linalg.norm(x1)
+
+
 def test_literal_alpha_agrees():
     """Ambiguity: alpha from r0 (literal Algorithm 1) vs from the current r."""
     prob, nu, o = sip(4, 1, n_levels=2)

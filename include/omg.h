@@ -132,9 +132,12 @@ typedef struct {
     double t_solve_ms;      /* wall time of the solve (host clock, stream synchronised) */
 } omg_report;
 
-/* Defaults: SYNC_MULT, s_pre = s_post = 1, n_s = 1, omega = 0.7,
- * max_iter = 1000, FP64, level criteria of Sec. 4.2 (level 1: 0.1 or 20
- * iterations; level 2: 0.5 or 2; deeper: 1 iteration), breakdown 1e-14. */
+/* Defaults: SYNC_MULT, coarse_sync = 0, s_pre = s_post = 1, n_s = 1,
+ * n_s_max = 0 (deterministic cycles), omega = 0.7, max_iter = 1000, FP64
+ * (max_outer = 50, inner_tol = 1e-5 for MIXED_IR), overlap_streams = 1,
+ * trace = 0, block-Jacobi smoother, m_max = 0 (no restarts), level criteria
+ * of Sec. 4.2 (level 1: 0.1 or 20 iterations; level 2: 0.5 or 2; deeper: 1
+ * iteration), breakdown 1e-14. */
 void omg_default_options(omg_options *opt);
 
 /* Setup from an assembled fine operator (Algorithm 2's A). Builds the
@@ -143,7 +146,10 @@ void omg_default_options(omg_options *opt);
  * inverses of Algorithm 4 and the dense Cholesky factor of the coarsest level.
  * A->bs must equal the basis size of grid->p; A->n_cells = nx*ny*nz.
  * hip_stream: hipStream_t (NULL = default). Errors: OMG_EINVAL (shape,
- * pattern, non-finite values), OMG_ENOTSPD, OMG_ENOMEM, OMG_EHIP. */
+ * pattern, non-finite values, option values out of range), OMG_EUNSUPPORTED
+ * (an option combination this library does not run, e.g. the Schwarz
+ * smoother at P3), OMG_ENOTSPD, OMG_ENOMEM, OMG_EHIP. *out is set only on
+ * success; the solver owns everything it allocates (omg_destroy). */
 omg_status omg_setup(const omg_bsr *A, const omg_grid *grid, const omg_options *opt, void *hip_stream,
                      omg_solver **out);
 
@@ -152,7 +158,8 @@ omg_status omg_setup(const omg_bsr *A, const omg_grid *grid, const omg_options *
  * -div(nu grad u) = f on the grid (Sec. 2), face terms weighted by the
  * harmonic mean 2 nu- nu+ / (nu- + nu+), penalty penalty_c (p+1)(p+3)/h,
  * Nitsche Dirichlet faces weighted by the cell's nu. Enables
- * omg_solve_backward's g_nu. */
+ * omg_solve_backward's g_nu. Errors as omg_setup, plus OMG_EINVAL for a
+ * non-positive or non-finite nu or h. nu is copied; the caller keeps it. */
 omg_status omg_setup_sip(const omg_grid *grid, const double *nu, const omg_options *opt, void *hip_stream,
                          omg_solver **out);
 
@@ -160,13 +167,21 @@ omg_status omg_setup_sip(const omg_grid *grid, const double *nu, const omg_optio
  * solution with ||b - A x|| <= tol ||b|| (recursive residual; the true
  * residual is reported). b is not written. r_out (nullable) receives the
  * final recursive residual. rep (host, nullable) is filled. OMG_ENOCONV
- * leaves the last iterate in x. b = 0 gives x = 0 at once. */
+ * leaves the last iterate in x. b = 0 gives x = 0 at once. Errors:
+ * OMG_EINVAL (non-finite b or x0, NULL pointers, tol < 0), OMG_ENOCONV,
+ * OMG_ENOMEM (direction storage), OMG_EHIP (a runtime failure, or a bounded
+ * wait of the persistent RM kernel that expired: the results are then not
+ * trustworthy). Calls on one solver must not overlap. */
 omg_status omg_solve(omg_solver *s, const double *b, double *x, double tol, double *r_out, omg_report *rep);
 
 /* Batched solve. n_inst solvers (host array s[n_inst]), each with nrhs
  * right-hand sides: b[i], x[i] are device arrays of shape (N_i, nrhs) with
  * the RHS index fastest. Each column is the same solve as omg_solve on that
- * column alone. rep: host array of n_inst*nrhs reports (nullable). */
+ * column alone. rep: host array of n_inst*nrhs reports (nullable). Solvers
+ * whose options the lockstep engines do not run (Schwarz smoother,
+ * timing-adaptive cycles, m_max restarts) are solved column by column.
+ * Returns the first failure (as omg_solve), OMG_OK if every column
+ * converged. */
 omg_status omg_solve_batched(omg_solver *const *s, int32_t n_inst, int32_t nrhs, const double *const *b,
                              double *const *x, double tol, omg_report *rep);
 
@@ -194,7 +209,8 @@ omg_status omg_level_matrix(const omg_solver *s, int32_t level, int32_t *row_ptr
                             int64_t *nnzb);
 /* y = b - A_l x (b nullable: y = A_l x), FP64, cell-major device vectors. */
 omg_status omg_level_spmv(omg_solver *s, int32_t level, const double *x, const double *b, double *y);
-/* out = Smoother(A_l, r, 0) with `sweeps` block-Jacobi iterations (Algorithm 4). */
+/* out = Smoother(A_l, r, 0) with `sweeps` iterations of the solver's
+ * smoother: block-Jacobi (Algorithm 4) or additive Schwarz (Algorithm 3). */
 omg_status omg_level_smoother(omg_solver *s, int32_t level, const double *r, int32_t sweeps, double *out);
 /* rc = P_l^T r (level l -> l+1) and z = P_l zc (level l+1 -> l). */
 omg_status omg_level_restrict(omg_solver *s, int32_t level, const double *r, double *rc);

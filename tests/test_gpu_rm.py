@@ -88,3 +88,30 @@ def test_rm_step_exchange_wave_is_bitwise_plain(n, p):
             what = f"k={k} config={cw}"
             assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), what
             assert np.array_equal(a[2], b[2]) and a[3] == b[3] and a[4] == b[4], what
+
+
+@pytest.mark.parametrize("n,p", [(8, 1), (16, 2)])
+def test_rm_step_breakdown_drops_direction(n, p):
+    """A new vector already in span(W) (here a stored direction itself):
+    after MGS ||w_out|| <= 1e-14 ||w_in||, so every configuration drops it:
+    gamma = alpha = 0, the new direction is zero and r is unchanged bit for
+    bit; the MGS coefficients are still the sequential ones."""
+    prob = synth.make_problem(n, p, n_levels=2)
+    nu = synth.nu_sphere(n, n, n, prob.h)
+    g = omg().Solver.from_sip(omg().Solver.make_grid(n, n, n, p, 2, prob.h), torch.tensor(nu, device="cuda"))
+    N = prob.n_dofs
+    rng = np.random.default_rng(9)
+    k = 6
+    W = np.linalg.qr(rng.standard_normal((N, k)))[0].T.copy()
+    w = W[2].copy()
+    z = rng.standard_normal(N)
+    r = rng.standard_normal(N)
+    betas, _, _, _, _ = reference(W, w, r)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    for cfg in g.rm_configs(0):
+        Wk, rn_g, b_g, gm_g, al_g = g.rm_step(0, dev(W), dev(w), dev(z), dev(r), cfg)
+        what = f"config={cfg}"
+        assert gm_g == 0.0 and al_g == 0.0, what
+        assert not torch.any(Wk != 0), what
+        assert np.array_equal(rn_g.cpu().numpy(), r), what
+        assert np.abs(b_g - betas).max() <= 1e-12, what

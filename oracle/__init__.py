@@ -45,12 +45,12 @@ class Report(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int), ("iters_fine", ctypes.c_int), ("n_dirs_fine", ctypes.c_int),
         ("n_breakdowns", ctypes.c_int), ("outer_iters", ctypes.c_int), ("n_visits", ctypes.c_int),
-        ("n_trace", ctypes.c_int), ("pad", ctypes.c_int),
+        ("n_trace", ctypes.c_int), ("n_vnorm", ctypes.c_int),
         ("rel_res_rec", ctypes.c_double), ("rel_res_true", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -66,6 +66,7 @@ def lib():
         i, d, i64 = ctypes.c_int, ctypes.c_double, ctypes.c_int64
         L.oracle_setup.argtypes = [P, P, P, i64, i, i, i, i, i, P, ctypes.POINTER(P)]
         L.oracle_setup_sip.argtypes = [i, i, i, i, d, d, P, i, P, ctypes.POINTER(P)]
+        L.oracle_setup_h.argtypes = [P, P, P, i64, i, i, P, P, P, P, P, ctypes.POINTER(P)]
         L.oracle_solve.argtypes = [P, P, P, d, P]
         L.oracle_grad.argtypes = [P, P, P, P, P, d, P]
         L.oracle_destroy.argtypes = [P]
@@ -79,6 +80,10 @@ def lib():
         L.oracle_get_visits.argtypes = [P, P]
         L.oracle_set_step_schedule.argtypes = [P, P, i]
         L.oracle_get_trace.argtypes = [P, P]
+        L.oracle_get_visit_norms.argtypes = [P, P]
+        L.oracle_spmv32.argtypes = [P, i, P, P, P]
+        L.oracle_restrict32.argtypes = [P, i, P, P]
+        L.oracle_prolong32.argtypes = [P, i, P, P]
         L.oracle_spmv.argtypes = [P, i, P, P, P]
         L.oracle_smoother.argtypes = [P, i, P, i, P]
         L.oracle_smoother32.argtypes = [P, i, P, i, P]
@@ -157,6 +162,29 @@ class Oracle:
             raise OracleError(st)
         bs = lib().oracle_nbasis(p)
         return cls(h, nx * ny * nz, bs, n_levels)
+
+    @classmethod
+    def from_bsr_hierarchy(cls, row_ptr, col_idx, val, n_cells, parents, slots, embed, **opts):
+        """Setup with a caller-supplied agglomeration hierarchy: level sizes
+        n_cells[0..L-1], per level l < L-1 the parent (int) and slot (0..7) of
+        every cell, and the embedding blocks embed[8][bs][bs]."""
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        nc = np.ascontiguousarray(n_cells, dtype=np.int32)
+        par = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int32) for p in parents])
+                                   if len(parents) else np.zeros(1, np.int32))
+        sl = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.uint8) for q in slots])
+                                  if len(slots) else np.zeros(1, np.uint8))
+        E = np.ascontiguousarray(embed, dtype=np.float64)
+        bs = val.shape[1]
+        h = ctypes.c_void_p()
+        o = make_opts(**opts)
+        st = lib().oracle_setup_h(_p(row_ptr), _p(col_idx), _p(val), len(col_idx), bs, len(nc), _p(nc), _p(par),
+                                  _p(sl), _p(E), ctypes.byref(o), ctypes.byref(h))
+        if st != OK:
+            raise OracleError(st)
+        return cls(h, int(nc[0]), bs, len(nc))
 
     def close(self):
         if self._h:
@@ -250,11 +278,22 @@ class Oracle:
         m = lib().oracle_get_trace(self._h, _p(out))
         return out[: 3 * m].reshape(m, 3)
 
-    def spmv(self, x, l=0, b=None):
+    def visit_norms(self):
+        """Per-visit residual log of the last solve, in completion order: a list
+        of (level, iterations, ||r0||, array of ||r|| after each iteration)."""
+        cnt = self.last_report["n_vnorm"]
+        out = np.zeros(max(cnt, 1))
+        m = lib().oracle_get_visit_norms(self._h, _p(out))
+        return parse_visit_norms(out[:m])
+
+    def spmv(self, x, l=0, b=None, fp32=False):
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.zeros_like(x)
         bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
-        lib().oracle_spmv(self._h, l, _p(x), None if bb is None else _p(bb), _p(y))
+        f = lib().oracle_spmv32 if fp32 else lib().oracle_spmv
+        st = f(self._h, l, _p(x), None if bb is None else _p(bb), _p(y))
+        if st != OK:
+            raise OracleError(st)
         return y
 
     def smoother(self, r, s, l=0, fp32=False):
@@ -265,18 +304,22 @@ class Oracle:
             raise OracleError(st)
         return out
 
-    def restrict(self, r, l=0):
+    def restrict(self, r, l=0, fp32=False):
         r = np.ascontiguousarray(r, dtype=np.float64)
         nc, _, _ = self.level_info(l + 1)
         rc = np.zeros(nc * self.bs)
-        lib().oracle_restrict(self._h, l, _p(r), _p(rc))
+        st = (lib().oracle_restrict32 if fp32 else lib().oracle_restrict)(self._h, l, _p(r), _p(rc))
+        if st != OK:
+            raise OracleError(st)
         return rc
 
-    def prolong(self, zc, l=0):
+    def prolong(self, zc, l=0, fp32=False):
         zc = np.ascontiguousarray(zc, dtype=np.float64)
         n, _, _ = self.level_info(l)
         z = np.zeros(n * self.bs)
-        lib().oracle_prolong(self._h, l, _p(zc), _p(z))
+        st = (lib().oracle_prolong32 if fp32 else lib().oracle_prolong)(self._h, l, _p(zc), _p(z))
+        if st != OK:
+            raise OracleError(st)
         return z
 
     def coarse_solve(self, b):
@@ -292,6 +335,18 @@ class Oracle:
         if st != OK:
             raise OracleError(st)
         return D
+
+
+def parse_visit_norms(v):
+    """Split a flat per-visit log (level, iterations, ||r0||, ||r||...) into
+    (level, iterations, r0, array of ||r|| per iteration) tuples."""
+    out, i = [], 0
+    v = np.asarray(v, dtype=np.float64)
+    while i < len(v):
+        l, it = int(v[i]), int(v[i + 1])
+        out.append((l, it, float(v[i + 2]), v[i + 3:i + 3 + it].copy()))
+        i += 3 + it
+    return out
 
 
 class OracleError(RuntimeError):

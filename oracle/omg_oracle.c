@@ -45,6 +45,12 @@
  *   - hierarchy: 2x2x2 agglomeration, P = L2 embedding of coarse polynomials
  *     into the children, R = P^T, A_c = P^T A P.
  *
+ * A direction that breaks down in residual minimisation (its orthogonalised
+ * w is at most `breakdown` times the w it started from) is dropped: its slot
+ * is stored as a zero vector, which leaves x and r exactly as discarding it
+ * would and counts it among the level's stored directions (the restart limit
+ * m_max and the reported direction count see it).
+ *
  * Every floating-point operation is FP64 except the optional FP32 emulation of
  * the mixed-precision forms, which rounds operands and results to float.
  * Dot products are plain sequential sums. Row-wise loops (SpMV, smoother,
@@ -105,7 +111,7 @@ typedef struct {
     int outer_iters;    /* refinement steps (precision 1) */
     int n_visits;       /* entries in the visit log */
     int n_trace;        /* entries in the finest-level residual trace */
-    int pad;
+    int n_vnorm;        /* doubles in the per-visit residual log */
     double rel_res_rec; /* ||r|| / ||b|| of the recursive residual (fine level) */
     double rel_res_true;/* ||b - A x|| / ||b|| recomputed in FP64 */
 } or_report;
@@ -521,6 +527,10 @@ typedef struct {
     /* transfers to the next coarser level: parent cell and child slot */
     int *parent;
     unsigned char *slot;
+    /* children of each cell of this level (levels >= 1): kids[kid_ptr[I] ..
+     * kid_ptr[I+1]) are the finer level's cells K with parent(K) = I, in
+     * order of (slot, K) */
+    int *kid_ptr, *kids;
 } level_t;
 
 typedef struct {
@@ -538,6 +548,9 @@ typedef struct {
     int n_visits, cap_visits;
     double *trace;     /* triples (step, ||r||, type) on the finest level */
     int n_trace, cap_trace, step;
+    double *vnorm;     /* per visit, in completion order: level, iterations, ||r0||, then ||r||
+                          after each iteration (the quantities the level tests of Sec. 4.2 read) */
+    int n_vnorm, cap_vnorm;
     int n_breakdowns;
     double bnorm_fine;
     int *sched;        /* smoother steps per cycle of the forking level (NULL: n_s) */
@@ -556,6 +569,8 @@ static void level_free(level_t *L) {
     free(L->rsnap); free(L->zcor); free(L->r0); free(L->x0);
     free(L->parent);
     free(L->slot);
+    free(L->kid_ptr);
+    free(L->kids);
     free(L->as_cells);
     free(L->as_L);
     free(L->as_inv32);
@@ -569,6 +584,7 @@ void oracle_destroy(void *h) {
     free(o->nu);
     free(o->visits);
     free(o->trace);
+    free(o->vnorm);
     free(o->sched);
     free(o);
 }
@@ -609,6 +625,22 @@ static void log_visit(oracle_t *o, int l, int it) {
     o->n_visits++;
 }
 
+static void log_vnorm(oracle_t *o, int l, int it, double r0n, const double *rns) {
+    int need = o->n_vnorm + 3 + it;
+    if (need > o->cap_vnorm) {
+        int cap = o->cap_vnorm ? o->cap_vnorm : 1024;
+        while (cap < need) cap *= 2;
+        o->vnorm = realloc(o->vnorm, sizeof(double) * cap);
+        o->cap_vnorm = cap;
+    }
+    double *v = o->vnorm + o->n_vnorm;
+    v[0] = l;
+    v[1] = it;
+    v[2] = r0n;
+    for (int i = 0; i < it; ++i) v[3 + i] = rns[i];
+    o->n_vnorm = need;
+}
+
 /* type: 0 initial, 1 smoother, 2 coarse, 3 final (the paper's residual-trace kinds) */
 static void log_trace(oracle_t *o, double rn, int type) {
     if (o->n_trace == o->cap_trace) {
@@ -622,8 +654,57 @@ static void log_trace(oracle_t *o, double rn, int type) {
 }
 
 /* Galerkin product A_c = P^T A P, P having block E_{slot(K)} at (K, parent(K)). */
+static int cmp_int(const void *a, const void *b) {
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* Block pattern of P^T A P: coarse cells I and J couple when a child of I
+ * couples with a child of J in A. Sorted columns, zero values. */
+static int coarse_pattern(const bsr_t *Af, const level_t *F, const level_t *C, int bs, bsr_t *Ac) {
+    int n = C->n;
+    Ac->n = n;
+    Ac->bs = bs;
+    Ac->row_ptr = malloc(sizeof(int) * (n + 1));
+    int *tmp = malloc(sizeof(int) * ((size_t)Af->nnzb + 1));
+    if (!Ac->row_ptr || !tmp) { free(tmp); return OR_ENOMEM; }
+    int64_t cnt = 0;
+    Ac->row_ptr[0] = 0;
+    /* pass 1: count unique parents of the children's columns per coarse row */
+    for (int I = 0; I < n; ++I) {
+        int m = 0;
+        for (int q = C->kid_ptr[I]; q < C->kid_ptr[I + 1]; ++q) {
+            int K = C->kids[q];
+            for (int e = Af->row_ptr[K]; e < Af->row_ptr[K + 1]; ++e) tmp[m++] = F->parent[Af->col[e]];
+        }
+        qsort(tmp, m, sizeof(int), cmp_int);
+        int u = 0;
+        for (int a = 0; a < m; ++a)
+            if (a == 0 || tmp[a] != tmp[a - 1]) ++u;
+        cnt += u;
+        Ac->row_ptr[I + 1] = (int)cnt;
+    }
+    Ac->nnzb = cnt;
+    Ac->col = malloc(sizeof(int) * (cnt ? cnt : 1));
+    Ac->val = calloc((size_t)(cnt ? cnt : 1) * bs * bs, sizeof(double));
+    if (!Ac->col || !Ac->val) { free(tmp); return OR_ENOMEM; }
+    for (int I = 0; I < n; ++I) {
+        int m = 0;
+        for (int q = C->kid_ptr[I]; q < C->kid_ptr[I + 1]; ++q) {
+            int K = C->kids[q];
+            for (int e = Af->row_ptr[K]; e < Af->row_ptr[K + 1]; ++e) tmp[m++] = F->parent[Af->col[e]];
+        }
+        qsort(tmp, m, sizeof(int), cmp_int);
+        int o_ = Ac->row_ptr[I];
+        for (int a = 0; a < m; ++a)
+            if (a == 0 || tmp[a] != tmp[a - 1]) Ac->col[o_++] = tmp[a];
+    }
+    free(tmp);
+    return OR_OK;
+}
+
 static int galerkin(const bsr_t *Af, const level_t *F, const level_t *C, const double *E, int bs, bsr_t *Ac) {
-    int rc = stencil_pattern(Ac, C->nx, C->ny, C->nz, bs);
+    int rc = coarse_pattern(Af, F, C, bs, Ac);
     if (rc) return rc;
     double tmp[64 * 64];
     for (int K = 0; K < Af->n; ++K) {
@@ -687,32 +768,88 @@ static void default_opts(or_opts *o) {
 
 void oracle_default_opts(or_opts *o) { default_opts(o); }
 
-/* Setup from a caller-supplied fine BSR matrix (copied) on an nx*ny*nz grid. */
 static int as_setup(oracle_t *o, int l);
 
-static int setup_common(oracle_t *o, int nx, int ny, int nz, int p, int nlev) {
-    int bs = o->bs;
-    embedding(p, o->E);
+/* Agglomeration hierarchy: level l+1's cells are unions of level l's cells;
+ * parent[l][K] is the coarse cell of fine cell K and slot[l][K] in 0..7 picks
+ * the embedding block E_slot (fine x coarse) of P_l, which has block
+ * E_{slot(K)} at (K, parent(K)). Maps of all levels are concatenated. */
+typedef struct {
+    int nlev;
+    const int *n_cells;          /* [nlev] */
+    const int *parent;           /* levels 0..nlev-2, n_cells[l] each */
+    const unsigned char *slot;
+    const double *E;             /* [8][bs][bs], NULL: the Cartesian embedding of degree p */
+} hier_t;
+
+/* The 2x2x2 agglomeration of an nx*ny*nz grid (every halved side even):
+ * parent (i/2, j/2, k/2), slot (i&1) + 2(j&1) + 4(k&1). Caller frees. */
+static int cartesian_maps(int nx, int ny, int nz, int nlev, int **n_cells, int **parent, unsigned char **slot) {
+    *n_cells = malloc(sizeof(int) * nlev);
+    size_t tot = 0;
+    for (int l = 0; l < nlev; ++l) {
+        int ax = nx >> l, ay = ny >> l, az = nz >> l;
+        if ((ax << l) != nx || (ay << l) != ny || (az << l) != nz || ax < 1) return OR_EINVAL;
+        (*n_cells)[l] = ax * ay * az;
+        if (l + 1 < nlev) tot += (size_t)ax * ay * az;
+    }
+    *parent = malloc(sizeof(int) * (tot ? tot : 1));
+    *slot = malloc(tot ? tot : 1);
+    size_t off = 0;
+    for (int l = 0; l + 1 < nlev; ++l) {
+        int ax = nx >> l, ay = ny >> l, cx = ax / 2, cy = ay / 2;
+        for (int c = 0; c < (*n_cells)[l]; ++c) {
+            int i = c % ax, j = (c / ax) % ay, k = c / (ax * ay);
+            (*parent)[off + c] = (i / 2) + cx * ((j / 2) + cy * (k / 2));
+            (*slot)[off + c] = (unsigned char)((i & 1) + 2 * (j & 1) + 4 * (k & 1));
+        }
+        off += (*n_cells)[l];
+    }
+    return OR_OK;
+}
+
+static int setup_common(oracle_t *o, const hier_t *H, int p) {
+    int bs = o->bs, nlev = H->nlev;
+    if (H->E) memcpy(o->E, H->E, sizeof(double) * 8 * bs * bs);
+    else embedding(p, o->E);
     for (int t = 0; t < 8 * bs * bs; ++t) o->E32[t] = (float)o->E[t];
     for (int l = 0; l < nlev; ++l) {
         level_t *L = &o->lev[l];
-        L->nx = nx >> l; L->ny = ny >> l; L->nz = nz >> l;
-        if ((L->nx << l) != nx || (L->ny << l) != ny || (L->nz << l) != nz || L->nx < 1) return OR_EINVAL;
-        L->n = L->nx * L->ny * L->nz;
+        if (H->n_cells[l] < 1) return OR_EINVAL;
+        if (l == 0 && H->n_cells[0] != L->A.n) return OR_EINVAL;
+        L->n = H->n_cells[l];
         L->N = (size_t)L->n * bs;
         int rc = level_alloc_work(L);
         if (rc) return rc;
     }
-    /* parent / slot maps */
+    /* parent / slot maps and, per coarse cell, its children in (slot, index) order */
+    size_t off = 0;
     for (int l = 0; l + 1 < nlev; ++l) {
         level_t *L = &o->lev[l], *C = &o->lev[l + 1];
         L->parent = malloc(sizeof(int) * L->n);
         L->slot = malloc(L->n);
+        C->kid_ptr = calloc((size_t)C->n + 1, sizeof(int));
+        C->kids = malloc(sizeof(int) * L->n);
+        if (!L->parent || !L->slot || !C->kid_ptr || !C->kids) return OR_ENOMEM;
         for (int c = 0; c < L->n; ++c) {
-            int i = c % L->nx, j = (c / L->nx) % L->ny, k = c / (L->nx * L->ny);
-            L->parent[c] = (i / 2) + C->nx * ((j / 2) + C->ny * (k / 2));
-            L->slot[c] = (unsigned char)((i & 1) + 2 * (j & 1) + 4 * (k & 1));
+            int I = H->parent[off + c], sl = H->slot[off + c];
+            if (I < 0 || I >= C->n || sl > 7) return OR_EINVAL;
+            L->parent[c] = I;
+            L->slot[c] = (unsigned char)sl;
+            C->kid_ptr[I + 1]++;
         }
+        for (int I = 0; I < C->n; ++I) {
+            if (C->kid_ptr[I + 1] == 0) return OR_EINVAL; /* a coarse cell without children */
+            C->kid_ptr[I + 1] += C->kid_ptr[I];
+        }
+        int *fill = malloc(sizeof(int) * C->n);
+        if (!fill) return OR_ENOMEM;
+        memcpy(fill, C->kid_ptr, sizeof(int) * C->n);
+        for (int sl = 0; sl < 8; ++sl)
+            for (int c = 0; c < L->n; ++c)
+                if (L->slot[c] == sl) C->kids[fill[L->parent[c]]++] = c;
+        free(fill);
+        off += L->n;
     }
     /* coarse operators */
     for (int l = 0; l + 1 < nlev; ++l) {
@@ -799,7 +936,52 @@ int oracle_setup(const int *row_ptr, const int *col, const double *val, int64_t 
     memcpy(A->val, val, sizeof(double) * (size_t)nnzb * bs * bs);
     for (size_t t = 0; t < (size_t)nnzb * bs * bs; ++t)
         if (!isfinite(A->val[t])) { oracle_destroy(o); return OR_EINVAL; }
-    rc = setup_common(o, nx, ny, nz, p, nlev);
+    int *nc = NULL, *par = NULL;
+    unsigned char *sl = NULL;
+    rc = cartesian_maps(nx, ny, nz, nlev, &nc, &par, &sl);
+    if (!rc) {
+        hier_t H = {nlev, nc, par, sl, NULL};
+        rc = setup_common(o, &H, p);
+    }
+    free(nc); free(par); free(sl);
+    if (rc) { oracle_destroy(o); return rc; }
+    *out = o;
+    return OR_OK;
+}
+
+/* Setup from a caller-supplied fine BSR matrix (copied) with a caller-supplied
+ * agglomeration hierarchy: n_cells[nlev], parent and slot maps of levels
+ * 0..nlev-2 concatenated, embedding blocks E[8][bs][bs]. */
+int oracle_setup_h(const int *row_ptr, const int *col, const double *val, int64_t nnzb, int bs, int nlev,
+                   const int *n_cells, const int *parent, const unsigned char *slot, const double *E,
+                   const or_opts *opt, void **out) {
+    *out = NULL;
+    if (nlev < 1 || nlev > MAXLEV || bs < 1 || bs > 64 || !n_cells || !E) return OR_EINVAL;
+    if (nlev > 1 && (!parent || !slot)) return OR_EINVAL;
+    if (opt && (opt->variant < 0 || opt->variant > 3 || opt->smoother < 0 || opt->smoother > 1)) return OR_EINVAL;
+    int n = n_cells[0];
+    int rc = validate_bsr(n, bs, row_ptr, col, nnzb);
+    if (rc) return rc;
+    oracle_t *o = calloc(1, sizeof(oracle_t));
+    if (!o) return OR_ENOMEM;
+    o->nlev = nlev;
+    o->bs = bs;
+    o->p = -1;
+    if (opt) o->opt = *opt; else default_opts(&o->opt);
+    bsr_t *A = &o->lev[0].A;
+    A->n = n; A->bs = bs; A->nnzb = nnzb;
+    A->row_ptr = malloc(sizeof(int) * (n + 1));
+    A->col = malloc(sizeof(int) * (nnzb ? nnzb : 1));
+    A->val = malloc(sizeof(double) * (size_t)(nnzb ? nnzb : 1) * bs * bs);
+    memcpy(A->row_ptr, row_ptr, sizeof(int) * (n + 1));
+    memcpy(A->col, col, sizeof(int) * nnzb);
+    memcpy(A->val, val, sizeof(double) * (size_t)nnzb * bs * bs);
+    for (size_t t = 0; t < (size_t)nnzb * bs * bs; ++t)
+        if (!isfinite(A->val[t])) { oracle_destroy(o); return OR_EINVAL; }
+    for (int t = 0; t < 8 * bs * bs; ++t)
+        if (!isfinite(E[t])) { oracle_destroy(o); return OR_EINVAL; }
+    hier_t H = {nlev, n_cells, parent, slot, E};
+    rc = setup_common(o, &H, -1);
     if (rc) { oracle_destroy(o); return rc; }
     *out = o;
     return OR_OK;
@@ -824,7 +1006,15 @@ int oracle_setup_sip(int nx, int ny, int nz, int p, double h, double penalty_c, 
     o->nu = dalloc(n);
     memcpy(o->nu, nu, sizeof(double) * n);
     if (!rc) rc = assemble(&o->lev[0].A, &o->elem, nx, ny, nz, nu);
-    if (!rc) rc = setup_common(o, nx, ny, nz, p, nlev);
+    o->lev[0].nx = nx; o->lev[0].ny = ny; o->lev[0].nz = nz;
+    int *nc = NULL, *par = NULL;
+    unsigned char *sl = NULL;
+    if (!rc) rc = cartesian_maps(nx, ny, nz, nlev, &nc, &par, &sl);
+    if (!rc) {
+        hier_t H = {nlev, nc, par, sl, NULL};
+        rc = setup_common(o, &H, p);
+    }
+    free(nc); free(par); free(sl);
     if (rc) { oracle_destroy(o); return rc; }
     *out = o;
     return OR_OK;
@@ -1030,13 +1220,21 @@ static int rm(oracle_t *o, int l, double *z) {
         }
     }
     double n_out = nrm2(w, N);
+    if (L->k == L->cap && grow_dirs(L)) return 0;
+    double *Wk = L->W + (size_t)L->k * N, *Zk = L->Z + (size_t)L->k * N;
     if (!(n_out > o->opt.breakdown * n_in)) {   /* also catches n_out == 0 and NaN */
+        /* breakdown: w lies in span(W) to working precision, so the direction
+         * carries nothing new and is dropped. Its slot is kept as a zero
+         * vector (W_k = Z_k = 0): every later coefficient against it is zero,
+         * so x and r are those of discarding it, and it still counts as one
+         * of the level's stored directions (toward m_max and n_dirs). */
         o->n_breakdowns++;
+        memset(Wk, 0, sizeof(double) * N);
+        memset(Zk, 0, sizeof(double) * N);
+        L->k++;
         return 0;
     }
-    if (L->k == L->cap && grow_dirs(L)) return 0;
     double gamma = 1.0 / n_out;
-    double *Wk = L->W + (size_t)L->k * N, *Zk = L->Z + (size_t)L->k * N;
 #pragma omp parallel for schedule(static)
     for (size_t e = 0; e < N; ++e) {
         Wk[e] = gamma * w[e];
@@ -1073,12 +1271,11 @@ static void restrict_(oracle_t *o, int l, const double *r, double *rc) {
     level_t *L = &o->lev[l], *C = &o->lev[l + 1];
     int bs = o->bs, f32 = use32(o, l, 0);
     memset(rc, 0, sizeof(double) * C->N);
-    /* loop over coarse cells so each output is written by one thread, children in slot order */
+    /* loop over coarse cells so each output is written by one thread, children in (slot, index) order */
 #pragma omp parallel for schedule(static)
     for (int I = 0; I < C->n; ++I) {
-        int ci = I % C->nx, cj = (I / C->nx) % C->ny, ck = I / (C->nx * C->ny);
-        for (int s = 0; s < 8; ++s) {
-            int K = (2 * ci + (s & 1)) + L->nx * ((2 * cj + ((s >> 1) & 1)) + L->ny * (2 * ck + ((s >> 2) & 1)));
+        for (int q = C->kid_ptr[I]; q < C->kid_ptr[I + 1]; ++q) {
+            int K = C->kids[q], s = L->slot[K];
             for (int c = 0; c < bs; ++c) {
                 if (f32) {
                     const float *E = o->E32 + (size_t)s * bs * bs;
@@ -1166,6 +1363,8 @@ static int mg(oracle_t *o, int l, const double *b, double *xout, double tol, int
     if (variant == 2) sub_variant = 1;
     else if ((variant == 1 || variant == 3) && o->opt.coarse_sync) sub_variant = 0;
     const int multiplicative = (variant == 0 || variant == 2);
+    double *rns = NULL; /* ||r|| after each iteration of this visit */
+    int cap_rns = 0;
     while (!stop_level(o, l, rn, r0n, bn, it, tol)) {
         if (multiplicative) {
             smoother(o, l, L->r, o->opt.s_pre, L->z);
@@ -1192,10 +1391,17 @@ static int mg(oracle_t *o, int l, const double *b, double *xout, double tol, int
         }
         it++;
         rn = nrm2(L->r, N);
+        if (it > cap_rns) {
+            cap_rns = cap_rns ? 2 * cap_rns : 32;
+            rns = realloc(rns, sizeof(double) * cap_rns);
+        }
+        rns[it - 1] = rn;
         if (!isfinite(rn)) { status = OR_EINVAL; break; }
     }
     if (l == 0 && status == OR_OK && rn > tol * bn) status = OR_ENOCONV;
     log_visit(o, l, it);
+    log_vnorm(o, l, it, r0n, rns);
+    free(rns);
     memcpy(xout, L->x, sizeof(double) * N);
     return status;
 }
@@ -1209,6 +1415,7 @@ int oracle_solve(void *h, const double *b, double *x, double tol, or_report *rep
     size_t N = L->N;
     o->n_visits = 0;
     o->n_trace = 0;
+    o->n_vnorm = 0;
     o->step = 0;
     o->n_breakdowns = 0;
     o->sched_pos = 0;
@@ -1263,6 +1470,7 @@ int oracle_solve(void *h, const double *b, double *x, double tol, or_report *rep
     R.n_breakdowns = o->n_breakdowns;
     R.n_visits = o->n_visits;
     R.n_trace = o->n_trace;
+    R.n_vnorm = o->n_vnorm;
     free(rr);
     free(e);
     if (rep) *rep = R;
@@ -1386,6 +1594,45 @@ int oracle_spmv(void *h, int l, const double *x, const double *b, double *y) {
     return OR_OK;
 }
 
+/* The per-visit residual log of the last solve (out sized from the report's
+ * n_vnorm); returns its length. */
+int oracle_get_visit_norms(void *h, double *out) {
+    oracle_t *o = h;
+    memcpy(out, o->vnorm, sizeof(double) * o->n_vnorm);
+    return o->n_vnorm;
+}
+
+/* Single-precision forms of the level operations, as the mixed solves run
+ * them (Sec. 3.2 precedent): y = A_l x (or b - A_l x) with the operator and
+ * x rounded to float and float sums; r_c = P^T r and z = P z_c with the
+ * embedding blocks and inputs rounded to float. */
+int oracle_spmv32(void *h, int l, const double *x, const double *b, double *y) {
+    oracle_t *o = h;
+    if (l < 0 || l >= o->nlev) return OR_EINVAL;
+    spmv32(&o->lev[l].A, o->lev[l].A32, x, b, y);
+    return OR_OK;
+}
+
+int oracle_restrict32(void *h, int l, const double *r, double *rc) {
+    oracle_t *o = h;
+    if (l < 0 || l >= o->nlev - 1) return OR_EINVAL;
+    int saved = o->mode32;
+    o->mode32 = 1;
+    restrict_(o, l, r, rc);
+    o->mode32 = saved;
+    return OR_OK;
+}
+
+int oracle_prolong32(void *h, int l, const double *zc, double *z) {
+    oracle_t *o = h;
+    if (l < 0 || l >= o->nlev - 1) return OR_EINVAL;
+    int saved = o->mode32;
+    o->mode32 = 1;
+    prolong(o, l, zc, z);
+    o->mode32 = saved;
+    return OR_OK;
+}
+
 /* coarsest-level direct solve and single smoother call, for unit pins */
 int oracle_smoother(void *h, int l, const double *r, int s, double *out) {
     oracle_t *o = h;
@@ -1398,7 +1645,8 @@ int oracle_smoother(void *h, int l, const double *r, int s, double *out) {
  * matrices and local solves); needs a solver set up with a mixed precision. */
 int oracle_smoother32(void *h, int l, const double *r, int s, double *out) {
     oracle_t *o = h;
-    if (l >= o->nlev - 1 || o->opt.precision == 0) return OR_EINVAL;
+    /* the single-precision Schwarz inverses exist only in the mixed forms */
+    if (l >= o->nlev - 1 || (o->opt.smoother == 1 && o->opt.precision == 0)) return OR_EINVAL;
     int saved = o->mode32;
     o->mode32 = 1;
     smoother(o, l, r, s, out);

@@ -2,12 +2,12 @@
  * omg.h -- C ABI of the MI355X orthonormalization-multigrid (OrthoMG) library.
  *
  * The library solves A x = b for a symmetric positive definite block-sparse
- * A (one dense bs x bs block per cell of a Cartesian grid) with the K-cycle
+ * A (one dense bs x bs block per pair of coupled cells) with the K-cycle
  * orthonormalization multigrid of the paper: residual minimisation by modified
  * Gram-Schmidt (Algorithm 1, Sec. 3.1) inside the multiplicative cycle
  * (Algorithm 2, Sec. 3.1) or the semi-asynchronous cycle (Algorithm 5, Sec. 4,
  * in a deterministic form), damped block-Jacobi smoothing (Algorithm 4,
- * Sec. 3.3), 2x2x2 agglomeration transfers with Galerkin coarse operators,
+ * Sec. 3.3), agglomeration transfers with Galerkin coarse operators,
  * level-local stopping rules (Sec. 4.2) and a dense Cholesky solve on the
  * coarsest level.
  *
@@ -15,7 +15,8 @@
  *   - Pointers are DEVICE pointers (hipMalloc'd, or torch CUDA tensors) unless
  *     a comment says "host".
  *   - Vectors are FP64 in cell-major DOF order: entry k of cell c is at
- *     c*bs + k. Cells are numbered i + nx*(j + ny*k), x fastest.
+ *     c*bs + k. On a Cartesian grid cells are numbered i + nx*(j + ny*k),
+ *     x fastest.
  *   - Basis per cell (used by omg_setup_sip and by the transfers): orthonormal
  *     total-degree-p Legendre products h^{-3/2} psi_a psi_b psi_c,
  *     psi_m(t) = sqrt(2m+1) P_m(2t-1), ordered by total degree then (a,b,c)
@@ -25,6 +26,8 @@
  *     stream). The host blocks only to read residual norms for stopping tests.
  *   - Every function returns a status and never throws across the ABI.
  *   - One host thread per solver. Solvers are independent.
+ *   - Inspection and timing calls used by tests and benchmarks are declared
+ *     in omg_inspect.h.
  */
 #ifndef OMG_H
 #define OMG_H
@@ -65,15 +68,36 @@ enum { OMG_MAX_LEVELS = 16 };
 
 typedef struct omg_solver omg_solver; /* opaque, library-owned */
 
-/* Cartesian grid and hierarchy: nx*ny*nz cubes of side h, polynomial degree
- * p, n_levels agglomeration levels (level l has nx>>l cells per side; every
- * coarsened side must be even). penalty_c scales the SIP penalty
- * penalty_c (p+1)(p+3)/h (omg_setup_sip only). */
+/* Cartesian grid: nx*ny*nz cubes of side h, polynomial degree p; n_levels
+ * levels of its 2x2x2 agglomeration (level l has nx>>l cells per side; every
+ * coarsened side must be even) when no hierarchy is given. penalty_c scales
+ * the SIP penalty penalty_c (p+1)(p+3)/h (omg_setup_sip only). */
 typedef struct {
     int32_t nx, ny, nz, p, n_levels;
     int32_t pad;
     double h, penalty_c;
 } omg_grid;
+
+/* Agglomeration hierarchy (the restriction R and prolongation P of
+ * Algorithm 2, Sec. 3.1), HOST pointers, copied at setup. Level l+1's cells
+ * are unions of level l's cells: parent[l][K] (0 <= parent < n_cells[l+1])
+ * is the coarse cell containing cell K of level l, and slot[l][K] (0..7)
+ * selects the embedding block E_slot, a bs x bs row-major block of
+ * embed[8][bs][bs] that maps a coarse cell's basis coefficients to those of
+ * its finer cell K. P_l has block E_{slot(K)} at (K, parent(K)), R_l = P_l^T,
+ * and the coarse operators are A_{l+1} = P_l^T A_l P_l (Galerkin). Every
+ * coarse cell needs at least one finer cell; it may have fewer than eight
+ * (sides of odd length). n_levels = 1: the direct solve on the operator.
+ * For the 2x2x2 agglomeration of a Cartesian grid, omg_grid_hierarchy and
+ * omg_embedding fill these arrays. */
+typedef struct {
+    int32_t n_levels;
+    int32_t pad;
+    const int32_t *n_cells;        /* host [n_levels] */
+    const int32_t *const *parent;  /* host [n_levels-1] arrays of n_cells[l] entries */
+    const uint8_t *const *slot;    /* host [n_levels-1] arrays of n_cells[l] entries */
+    const double *embed;           /* host [8][bs][bs] */
+} omg_hierarchy;
 
 /* Block sparse matrix, HOST pointers: row_ptr[n_cells+1], col_idx[nnzb]
  * (sorted, in range, diagonal present), val[nnzb][bs][bs] row-major FP64.
@@ -113,7 +137,9 @@ typedef struct {
     int32_t pad1;
     double omega;         /* block-Jacobi damping */
     double inner_tol;     /* OMG_MIXED_IR: relative tolerance of each inner solve */
-    double breakdown;     /* RM drops a direction when ||w_out|| <= breakdown * ||w_in|| */
+    double breakdown;     /* RM drops a direction when ||w_out|| <= breakdown * ||w_in||: its slot
+                             is stored as a zero vector (x, r unchanged) and still counts as a
+                             stored direction (toward m_max and n_dirs_fine) */
     double crit_rel[OMG_MAX_LEVELS]; /* level l>=1: stop when ||r|| <= crit_rel[l-1]*||r0|| (<0: off) */
     int32_t crit_max[OMG_MAX_LEVELS];/* level l>=1: stop after crit_max[l-1] iterations */
 } omg_options;
@@ -140,28 +166,45 @@ typedef struct {
  * iteration), breakdown 1e-14. */
 void omg_default_options(omg_options *opt);
 
-/* Setup from an assembled fine operator (Algorithm 2's A). Builds the
- * hierarchy of the grid (2x2x2 agglomeration, P = L2 embedding of coarse
- * polynomials, R = P^T, Galerkin A_{l+1} = P^T A_l P), the block-diagonal
- * inverses of Algorithm 4 and the dense Cholesky factor of the coarsest level.
- * A->bs must equal the basis size of grid->p; A->n_cells = nx*ny*nz.
- * hip_stream: hipStream_t (NULL = default). Errors: OMG_EINVAL (shape,
- * pattern, non-finite values, option values out of range), OMG_EUNSUPPORTED
- * (an option combination this library does not run, e.g. the Schwarz
- * smoother at P3), OMG_ENOTSPD, OMG_ENOMEM, OMG_EHIP. *out is set only on
- * success; the solver owns everything it allocates (omg_destroy). */
-omg_status omg_setup(const omg_bsr *A, const omg_grid *grid, const omg_options *opt, void *hip_stream,
+/* The 2x2x2 agglomeration of the Cartesian grid g: for level < g->n_levels-1,
+ * parent[K] and slot[K] (host, n_cells(level) = (nx>>level)(ny>>level)(nz>>level)
+ * entries each) of every cell K = i + nx_l (j + ny_l k) of that level: parent
+ * (i/2, j/2, k/2) on level+1, slot (i&1) + 2(j&1) + 4(k&1). Every coarsened
+ * side must be even (else OMG_EINVAL). */
+omg_status omg_grid_hierarchy(const omg_grid *g, int32_t level, int32_t *parent, uint8_t *slot);
+
+/* The eight embedding blocks of the library's orthonormal Legendre basis of
+ * degree p (0..3) on a cube and its 2x2x2 children: E[s][i][j] = L2 inner
+ * product of child basis function i (child s, normalised on the child) with
+ * coarse basis function j (host E[8][bs][bs]). */
+omg_status omg_embedding(int32_t p, double *E);
+
+/* Setup from an assembled fine operator A (Algorithm 2's A) and an
+ * agglomeration hierarchy H (both host memory, copied; the caller may free
+ * them afterwards). Builds the Galerkin coarse operators P^T A P, the
+ * block-diagonal inverses of Algorithm 4 and the dense factor of the
+ * coarsest level. A->bs must be 1, 4, 10 or 20 (the total-degree bases of
+ * P0..P3) and H->n_cells[0] = A->n_cells. hip_stream: hipStream_t (NULL =
+ * default). Errors: OMG_EINVAL (shape, pattern, non-finite values, maps out
+ * of range, a coarse cell with no finer cell, option values out of range),
+ * OMG_EUNSUPPORTED (a block size or option combination this library does not
+ * run, e.g. the Schwarz smoother at P3), OMG_ENOTSPD, OMG_ENOMEM, OMG_EHIP.
+ * *out is set only on success; the solver owns everything it allocates
+ * (omg_destroy). */
+omg_status omg_setup(const omg_bsr *A, const omg_hierarchy *H, const omg_options *opt, void *hip_stream,
                      omg_solver **out);
 
 /* Setup with the operator assembled on the device from a per-cell coefficient
  * nu[n_cells] (DEVICE pointer, FP64, > 0): symmetric interior penalty DG for
  * -div(nu grad u) = f on the grid (Sec. 2), face terms weighted by the
  * harmonic mean 2 nu- nu+ / (nu- + nu+), penalty penalty_c (p+1)(p+3)/h,
- * Nitsche Dirichlet faces weighted by the cell's nu. Enables
+ * Nitsche Dirichlet faces weighted by the cell's nu. H (nullable) is the
+ * hierarchy; NULL takes the grid's 2x2x2 agglomeration with grid->n_levels
+ * levels, and an H with embed = NULL takes omg_embedding(grid->p). Enables
  * omg_solve_backward's g_nu. Errors as omg_setup, plus OMG_EINVAL for a
  * non-positive or non-finite nu or h. nu is copied; the caller keeps it. */
-omg_status omg_setup_sip(const omg_grid *grid, const double *nu, const omg_options *opt, void *hip_stream,
-                         omg_solver **out);
+omg_status omg_setup_sip(const omg_grid *grid, const double *nu, const omg_hierarchy *H, const omg_options *opt,
+                         void *hip_stream, omg_solver **out);
 
 /* (x, r) = MG(A, b, x0) (Algorithm 2 / 5): on entry x holds x0, on exit the
  * solution with ||b - A x|| <= tol ||b|| (recursive residual; the true
@@ -186,132 +229,17 @@ omg_status omg_solve_batched(omg_solver *const *s, int32_t n_inst, int32_t nrhs,
                              double *const *x, double tol, omg_report *rep);
 
 /* Gradient of a scalar loss L(u) with u = A(nu)^-1 f, given u and g_u = dL/du:
- * lambda = A^-1 g_u (adjoint solve on the same hierarchy, A symmetric),
- * g_f = lambda, g_nu[K] = -lambda^T (dA/dnu_K) u (per-cell contraction).
- * g_f, g_nu nullable. g_nu needs a solver from omg_setup_sip
- * (else OMG_EUNSUPPORTED). */
+ * lambda = A^-1 g_u (adjoint solve on the same hierarchy, A symmetric,
+ * tolerance tol), g_f = lambda, g_nu[K] = -lambda^T (dA/dnu_K) u (per-cell
+ * contraction). g_f, g_nu nullable (device, N and n_cells entries). g_nu
+ * needs a solver from omg_setup_sip (else OMG_EUNSUPPORTED). If the adjoint
+ * solve does not converge, OMG_ENOCONV is returned and g_f, g_nu are not
+ * written. Errors otherwise as omg_solve. */
 omg_status omg_solve_backward(omg_solver *s, const double *u, const double *g_u, double *g_f, double *g_nu,
                               double tol, omg_report *rep);
 
 void omg_destroy(omg_solver *s);
 const char *omg_strerror(omg_status st);
-
-/* ---- inspection (for tests and benchmarks) ------------------------------ */
-
-/* Level sizes: cells, stored blocks per row (ELL width), directions stored. */
-omg_status omg_level_info(const omg_solver *s, int32_t level, int32_t *n_cells, int32_t *ell_width,
-                          int32_t *k_dirs);
-/* Copy level l's operator out in BSR form (host arrays sized from
- * omg_level_info: row_ptr[n+1], col_idx[n*width], val[n*width*bs*bs]);
- * returns the number of stored blocks in *nnzb (explicit zero padding
- * blocks are dropped). */
-omg_status omg_level_matrix(const omg_solver *s, int32_t level, int32_t *row_ptr, int32_t *col_idx, double *val,
-                            int64_t *nnzb);
-/* y = b - A_l x (b nullable: y = A_l x), FP64, cell-major device vectors. */
-omg_status omg_level_spmv(omg_solver *s, int32_t level, const double *x, const double *b, double *y);
-/* out = Smoother(A_l, r, 0) with `sweeps` iterations of the solver's
- * smoother: block-Jacobi (Algorithm 4) or additive Schwarz (Algorithm 3). */
-omg_status omg_level_smoother(omg_solver *s, int32_t level, const double *r, int32_t sweeps, double *out);
-/* rc = P_l^T r (level l -> l+1) and z = P_l zc (level l+1 -> l). */
-omg_status omg_level_restrict(omg_solver *s, int32_t level, const double *r, double *rc);
-omg_status omg_level_prolong(omg_solver *s, int32_t level, const double *zc, double *z);
-/* x = A_c^-1 b on the coarsest level. */
-omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
-/* Multi-right-hand-side forms of the level operations, as run inside
- * omg_solve_batched (matrix-core block products): X, B, Y are device arrays
- * of shape (N_l, nrhs), RHS index fastest, cell-major DOFs, 1 <= nrhs <= 32.
- * op OMG_MR_SPMV: Y = A_l X (B null) or Y = B - A_l X; OMG_MR_SMOOTHER:
- * Y = Smoother(A_l, X, 0) with `sweeps` block-Jacobi iterations
- * (Algorithm 4); OMG_MR_COARSE: Y = A_c^-1 X (coarsest level, FP64 only).
- * fp32 = 1 uses the FP32 operator copies (inputs rounded to FP32, FP32
- * arithmetic, results widened to FP64). OMG_EUNSUPPORTED for bs > 16. */
-enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
-/* Launch configurations the autotuners chose on a level, host shapes[17]:
- * [0..11] the multi-right-hand-side kernels (tuned on the first batched
- * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
- * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..5 is
- * (wavefronts per block, 16-column tiles per wavefront) = (4,2), (2,2),
- * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..16] the persistent
- * residual-minimisation kernel (tuned at setup): blocks, vector entries per
- * thread, directions per grid exchange, exchange form (0 all-to-all, 1
- * leader block), compute waves per block of the exchange-wave form (0:
- * plain form); -1 if the level does not use it. */
-omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
-omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
-                           const double *X, const double *B, double *Y);
-/* One residual-minimisation step (Algorithm 1 after w = A z) with level l's
- * persistent kernel on caller data: the vectors are flat device arrays of
- * N_l entries (RM has no cell structure); W holds k orthonormal directions
- * as rows of a k x N_l array; cfg (host, nullable) = (blocks, entries per
- * thread, directions per exchange, leader exchange, compute waves) selects
- * one of the co-resident configurations of omg_level_rm_configs (NULL: the
- * tuned one).
- * Outputs: Wk (the new orthonormal direction), r_new, and host
- * coeff[k + 2] = (beta_0..beta_{k-1}, gamma, alpha). The level's own work
- * storage is overwritten. OMG_EUNSUPPORTED if the level does not use the
- * persistent kernel. */
-omg_status omg_level_rm_step(omg_solver *s, int32_t level, int32_t k, const double *W, const double *w,
-                             const double *z, const double *r, const int32_t *cfg, double *Wk, double *r_new,
-                             double *coeff);
-/* The co-resident launch configurations of level l's persistent RM kernel:
- * host out[5*cap] (blocks, entries per thread, directions per exchange,
- * leader exchange, compute waves: 0 for the plain form, 3 or 4 for the
- * exchange-wave form, where one more wave per block performs the grid
- * exchanges), their count in *n (out nullable to query the count). */
-omg_status omg_level_rm_configs(const omg_solver *s, int32_t level, int32_t *out, int32_t cap, int32_t *n);
-/* Stored directions of level l after the last solve (device, cell-major,
- * [k][N] each); W or Z nullable. */
-omg_status omg_get_dirs(const omg_solver *s, int32_t level, double *W, double *Z);
-/* Visit log of the last solve: pairs (level, iterations) in visit order
- * (host out[2*cap]); returns the count through *n. */
-omg_status omg_get_visits(const omg_solver *s, int32_t *out, int32_t cap, int32_t *n);
-/* Residual trace of the last solve (needs opt.trace): triples
- * (step, ||r||, type: 0 initial, 1 smoother, 2 coarse, 3 final), host. */
-omg_status omg_get_trace(const omg_solver *s, double *out, int32_t cap, int32_t *n);
-/* Smoother+RM steps taken in each cycle of the forking level during the
- * last solve (OVERLAP_DET: the finest level; HYBRID: level 1), in execution
- * order, into host out[cap] (caller-owned; at most cap written); count in *n
- * (out nullable to query it). n_s each unless the cycle was timing-adaptive
- * (adaptive loops, Sec. 4.3), where replaying these counts reproduces the
- * solve. OMG_EINVAL for a NULL solver or n. */
-omg_status omg_get_step_counts(const omg_solver *s, int32_t *out, int32_t cap, int32_t *n);
-/* Replay: make the next solve(s) use these per-visit iteration counts
- * (host pairs (level, iterations), n entries) instead of the level tests;
- * n = 0 switches replay off. */
-omg_status omg_set_replay(omg_solver *s, const int32_t *visits, int32_t n);
-
-/* ---- kernel timing (benchmarks) -------------------------------------- */
-enum {
-    OMG_K_SPMV = 0,      /* w = A z, block SpMV of one level (FP64) */
-    OMG_K_SPMV32 = 1,    /* the same with the FP32 operator */
-    OMG_K_BJ = 2,        /* fused block-Jacobi iteration x' = x + omega D^-1 (r - A x) (FP64) */
-    OMG_K_BJ32 = 3,      /* the same in FP32 */
-    OMG_K_MGS = 4,       /* one modified Gram-Schmidt step of residual minimisation */
-    OMG_K_RESTRICT = 5,  /* r_c = P^T r */
-    OMG_K_PROLONG = 6,   /* z = P z_c */
-    OMG_K_COARSE = 7,    /* coarsest-level solve (dense inverse GEMV) */
-    OMG_K_RMFIN = 8,     /* RM normalisation + update (two kernels) */
-    OMG_K_BJFIRST = 9,   /* first block-Jacobi iteration from zero, x = omega D^-1 r */
-    OMG_K_RMP = 10,      /* persistent residual minimisation (whole MGS loop + update, one launch) */
-    OMG_K_COPY = 11,     /* plain copy of one level vector (reference for traffic counters) */
-    OMG_K_COUNT = 12
-};
-/* Launch kernel `kind` of level `level` `reps` times on the solver's stream
- * between two HIP events (inputs are the level's work buffers, filled with
- * finite data); *avg_ms = mean duration per launch, *alg_bytes = the bytes
- * the operation must move per launch (operator values and column indices of
- * the stored blocks, each vector read or written once). */
-omg_status omg_bench_kernel(omg_solver *s, int32_t kind, int32_t level, int32_t reps, double *avg_ms,
-                            double *alg_bytes);
-/* Arm a probe: during the following solves, every launch of kernel `kind` on
- * `level` (up to max_launches) is bracketed by HIP events on the stream it is
- * launched on. omg_probe_result returns the number of timed launches, their
- * mean duration and the algorithmic bytes per launch, and disarms the probe. */
-omg_status omg_probe_kernel(omg_solver *s, int32_t kind, int32_t level, int32_t max_launches);
-omg_status omg_probe_result(omg_solver *s, int64_t *launches, double *avg_ms, double *alg_bytes);
-/* Launch counts of the last solve(s) since the previous call, per kernel kind
- * and level: host out[OMG_K_COUNT][OMG_MAX_LEVELS]; counters are reset. */
-omg_status omg_get_kernel_counts(omg_solver *s, int64_t *out);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,52 @@ class Bsr(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
+class HierarchyC(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_cells", ctypes.c_void_p),
+                ("parent", ctypes.c_void_p), ("slot", ctypes.c_void_p), ("embed", ctypes.c_void_p)]
+
+
+class Hierarchy:
+    """An agglomeration hierarchy for omg_setup / omg_setup_sip (host arrays):
+    level sizes ``n_cells``, per level l < L-1 the ``parents[l]`` (int32) and
+    ``slots[l]`` (uint8, 0..7) of its cells, and the eight embedding blocks
+    ``embed`` [8][bs][bs] (None: the library's basis, omg_setup_sip only)."""
+
+    def __init__(self, n_cells, parents, slots, embed=None):
+        self.n_cells = np.ascontiguousarray(n_cells, dtype=np.int32)
+        self.parents = [np.ascontiguousarray(p, dtype=np.int32) for p in parents]
+        self.slots = [np.ascontiguousarray(q, dtype=np.uint8) for q in slots]
+        self.embed = None if embed is None else np.ascontiguousarray(embed, dtype=np.float64)
+        self._pp = (ctypes.c_void_p * max(len(self.parents), 1))(*[a.ctypes.data for a in self.parents])
+        self._sp = (ctypes.c_void_p * max(len(self.slots), 1))(*[a.ctypes.data for a in self.slots])
+        self.c = HierarchyC(len(self.n_cells), 0, self.n_cells.ctypes.data,
+                            ctypes.cast(self._pp, ctypes.c_void_p) if self.parents else None,
+                            ctypes.cast(self._sp, ctypes.c_void_p) if self.slots else None,
+                            None if self.embed is None else self.embed.ctypes.data)
+
+    @property
+    def n_levels(self):
+        return len(self.n_cells)
+
+    @classmethod
+    def of_grid(cls, grid: "Grid"):
+        """The 2x2x2 agglomeration of a Cartesian grid (omg_grid_hierarchy) with
+        the library's embedding blocks (omg_embedding)."""
+        L = lib()
+        n_cells = [(grid.nx >> l) * (grid.ny >> l) * (grid.nz >> l) for l in range(grid.n_levels)]
+        parents, slots = [], []
+        for l in range(grid.n_levels - 1):
+            par = np.zeros(n_cells[l], dtype=np.int32)
+            sl = np.zeros(n_cells[l], dtype=np.uint8)
+            _check(L.omg_grid_hierarchy(ctypes.byref(grid), l, par.ctypes.data, sl.ctypes.data), "grid_hierarchy")
+            parents.append(par)
+            slots.append(sl)
+        bs = (grid.p + 1) * (grid.p + 2) * (grid.p + 3) // 6
+        E = np.zeros((8, bs, bs))
+        _check(L.omg_embedding(grid.p, E.ctypes.data), "embedding")
+        return cls(n_cells, parents, slots, E)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("coarse_sync", ctypes.c_int32), ("s_pre", ctypes.c_int32),
                 ("s_post", ctypes.c_int32), ("n_s", ctypes.c_int32), ("max_iter", ctypes.c_int32),
@@ -62,7 +108,8 @@ class Report(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["omg_default_options", "omg_setup", "omg_setup_sip", "omg_solve", "omg_solve_batched",
+EXPORTS = ["omg_default_options", "omg_grid_hierarchy", "omg_embedding", "omg_get_visit_norms",
+           "omg_setup", "omg_setup_sip", "omg_solve", "omg_solve_batched",
            "omg_solve_backward", "omg_destroy", "omg_strerror", "omg_level_info", "omg_level_matrix",
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
            "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_get_step_counts", "omg_set_replay", "omg_bench_kernel",
@@ -85,8 +132,11 @@ def lib():
         P, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         L.omg_default_options.argtypes = [P]
         L.omg_default_options.restype = None
+        L.omg_grid_hierarchy.argtypes = [P, i32, P, P]
+        L.omg_embedding.argtypes = [i32, P]
+        L.omg_get_visit_norms.argtypes = [P, P, i32, P]
         L.omg_setup.argtypes = [P, P, P, P, ctypes.POINTER(P)]
-        L.omg_setup_sip.argtypes = [P, P, P, P, ctypes.POINTER(P)]
+        L.omg_setup_sip.argtypes = [P, P, P, P, P, ctypes.POINTER(P)]
         L.omg_solve.argtypes = [P, P, P, d, P, P]
         L.omg_solve_batched.argtypes = [P, i32, i32, P, P, d, P]
         L.omg_solve_backward.argtypes = [P, P, P, P, P, d, P]
@@ -96,10 +146,10 @@ def lib():
         L.omg_strerror.restype = ctypes.c_char_p
         L.omg_level_info.argtypes = [P, i32, P, P, P]
         L.omg_level_matrix.argtypes = [P, i32, P, P, P, P]
-        L.omg_level_spmv.argtypes = [P, i32, P, P, P]
-        L.omg_level_smoother.argtypes = [P, i32, P, i32, P]
-        L.omg_level_restrict.argtypes = [P, i32, P, P]
-        L.omg_level_prolong.argtypes = [P, i32, P, P]
+        L.omg_level_spmv.argtypes = [P, i32, i32, P, P, P]
+        L.omg_level_smoother.argtypes = [P, i32, i32, P, i32, P]
+        L.omg_level_restrict.argtypes = [P, i32, i32, P, P]
+        L.omg_level_prolong.argtypes = [P, i32, i32, P, P]
         L.omg_coarse_solve.argtypes = [P, P, P]
         L.omg_get_dirs.argtypes = [P, i32, P, P]
         L.omg_get_visits.argtypes = [P, P, i32, P]
@@ -163,11 +213,11 @@ def _ptr(t):
 class Solver:
     """Owns one library solver (hierarchy, factors, workspaces) on cuda:0."""
 
-    def __init__(self, handle, grid: Grid, has_sip: bool):
+    def __init__(self, handle, bs: int, n_cells: int, has_sip: bool, grid: Grid = None):
         self._h = handle
         self.grid = grid
-        self.bs = (grid.p + 1) * (grid.p + 2) * (grid.p + 3) // 6
-        self.n_cells = grid.nx * grid.ny * grid.nz
+        self.bs = bs
+        self.n_cells = n_cells
         self.n = self.n_cells * self.bs
         self.has_sip = has_sip
         self.last_report = None
@@ -177,27 +227,31 @@ class Solver:
         return Grid(nx, ny, nz, p, n_levels, 0, 1.0 / nx if h is None else h, penalty_c)
 
     @classmethod
-    def from_bsr(cls, row_ptr, col_idx, val, grid: Grid, **opts):
+    def from_bsr(cls, row_ptr, col_idx, val, hierarchy, **opts):
+        """omg_setup on a host BSR matrix. ``hierarchy`` is a Hierarchy, or a
+        Grid whose 2x2x2 agglomeration is taken."""
         row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
         col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float64)
-        bs = (grid.p + 1) * (grid.p + 2) * (grid.p + 3) // 6
+        H = Hierarchy.of_grid(hierarchy) if isinstance(hierarchy, Grid) else hierarchy
+        bs = val.shape[1]
         A = Bsr(len(row_ptr) - 1, bs, len(col_idx), row_ptr.ctypes.data, col_idx.ctypes.data, val.ctypes.data)
         h = ctypes.c_void_p()
         o = options(**opts)
-        _check(lib().omg_setup(ctypes.byref(A), ctypes.byref(grid), ctypes.byref(o), _stream(), ctypes.byref(h)),
+        _check(lib().omg_setup(ctypes.byref(A), ctypes.byref(H.c), ctypes.byref(o), _stream(), ctypes.byref(h)),
                "omg_setup")
-        return cls(h, grid, False)
+        return cls(h, bs, len(row_ptr) - 1, False, hierarchy if isinstance(hierarchy, Grid) else None)
 
     @classmethod
-    def from_sip(cls, grid: Grid, nu, **opts):
+    def from_sip(cls, grid: Grid, nu, hierarchy: Hierarchy = None, **opts):
         import torch
         nu = torch.as_tensor(nu, dtype=torch.float64, device="cuda").contiguous()
         h = ctypes.c_void_p()
         o = options(**opts)
-        _check(lib().omg_setup_sip(ctypes.byref(grid), _ptr(nu), ctypes.byref(o), _stream(), ctypes.byref(h)),
-               "omg_setup_sip")
-        return cls(h, grid, True)
+        _check(lib().omg_setup_sip(ctypes.byref(grid), _ptr(nu), None if hierarchy is None else ctypes.byref(hierarchy.c),
+                                   ctypes.byref(o), _stream(), ctypes.byref(h)), "omg_setup_sip")
+        bs = (grid.p + 1) * (grid.p + 2) * (grid.p + 3) // 6
+        return cls(h, bs, grid.nx * grid.ny * grid.nz, True, grid)
 
     def close(self):
         if self._h:
@@ -232,7 +286,7 @@ class Solver:
         st = lib().omg_solve_backward(self._h, _ptr(u), _ptr(g_u), _ptr(g_f), None if g_nu is None else _ptr(g_nu),
                                       tol, ctypes.byref(rep))
         self.last_report = rep.as_dict()
-        if st not in (OK, ENOCONV):
+        if st != OK:  # gradients exist only for a converged adjoint solve
             raise OmgError(st, "omg_solve_backward")
         return g_f, g_nu
 
@@ -252,30 +306,31 @@ class Solver:
                "level_matrix")
         return rp, ci[:nnzb.value], v[:nnzb.value]
 
-    def level_spmv(self, l, x, b=None):
+    def level_spmv(self, l, x, b=None, fp32=False):
         import torch
         y = torch.empty_like(x)
-        _check(lib().omg_level_spmv(self._h, l, _ptr(x), None if b is None else _ptr(b), _ptr(y)), "level_spmv")
+        _check(lib().omg_level_spmv(self._h, l, int(fp32), _ptr(x), None if b is None else _ptr(b), _ptr(y)),
+               "level_spmv")
         return y
 
-    def level_smoother(self, l, r, sweeps):
+    def level_smoother(self, l, r, sweeps, fp32=False):
         import torch
         out = torch.empty_like(r)
-        _check(lib().omg_level_smoother(self._h, l, _ptr(r), sweeps, _ptr(out)), "level_smoother")
+        _check(lib().omg_level_smoother(self._h, l, int(fp32), _ptr(r), sweeps, _ptr(out)), "level_smoother")
         return out
 
-    def level_restrict(self, l, r):
+    def level_restrict(self, l, r, fp32=False):
         import torch
         nc, _, _ = self.level_info(l + 1)
         rc = torch.empty(nc * self.bs, dtype=torch.float64, device="cuda")
-        _check(lib().omg_level_restrict(self._h, l, _ptr(r), _ptr(rc)), "level_restrict")
+        _check(lib().omg_level_restrict(self._h, l, int(fp32), _ptr(r), _ptr(rc)), "level_restrict")
         return rc
 
-    def level_prolong(self, l, zc):
+    def level_prolong(self, l, zc, fp32=False):
         import torch
         nf, _, _ = self.level_info(l)
         z = torch.empty(nf * self.bs, dtype=torch.float64, device="cuda")
-        _check(lib().omg_level_prolong(self._h, l, _ptr(zc), _ptr(z)), "level_prolong")
+        _check(lib().omg_level_prolong(self._h, l, int(fp32), _ptr(zc), _ptr(z)), "level_prolong")
         return z
 
     def coarse_solve(self, b):
@@ -339,6 +394,20 @@ class Solver:
         out = np.zeros(2 * max(n.value, 1), dtype=np.int32)
         lib().omg_get_visits(self._h, out.ctypes.data, n.value, ctypes.byref(n))
         return out[: 2 * n.value].reshape(-1, 2)
+
+    def visit_norms(self):
+        """Per-visit residual log of the last solve: (level, iterations, ||r0||,
+        array of ||r|| after each iteration) in completion order."""
+        n = ctypes.c_int32()
+        lib().omg_get_visit_norms(self._h, None, 0, ctypes.byref(n))
+        out = np.zeros(max(n.value, 1))
+        lib().omg_get_visit_norms(self._h, out.ctypes.data, n.value, ctypes.byref(n))
+        res, i = [], 0
+        while i < n.value:
+            l, it = int(out[i]), int(out[i + 1])
+            res.append((l, it, float(out[i + 2]), out[i + 3:i + 3 + it].copy()))
+            i += 3 + it
+        return res
 
     def step_counts(self):
         """Smoother+RM steps per cycle of the forking level in the last solve."""

@@ -353,12 +353,11 @@ XferTable xfer_table(Group& g, const std::vector<int>& act, int l, bool up, bool
     for (size_t i = 0; i < act.size(); ++i) {
         const Level& F = LV(g.col[act[i]], l);
         const Level& C = LV(g.col[act[i]], l + 1);
-        T.fnx[i] = F.nx;
-        T.fny[i] = F.ny;
         T.fn[i] = F.n;
-        T.cnx[i] = C.nx;
-        T.cny[i] = C.ny;
         T.cn[i] = C.n;
+        T.up[i] = F.up;
+        T.dn_ptr[i] = C.dn_ptr;
+        T.dn[i] = C.dn;
         T.in[i] = up ? F.r : C.xout;
         T.out[i] = up ? C.b : (zcor ? F.zcor : F.z);
     }
@@ -418,6 +417,7 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
     OMG_TRY(read_norms(g, act, l, r0));
     std::vector<double> rn = r0;
     std::vector<int> its(m, 0), live(m, 1);
+    std::vector<std::vector<double>> rns(m); // ||r|| after each iteration, per member
     const int sub_variant = cycle_sub_variant(variant, P->opt.coarse_sync);
     for (;;) {
         std::vector<int> cur, pos;
@@ -455,6 +455,7 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
         for (size_t q = 0; q < cur.size(); ++q) {
             its[pos[q]]++;
             rn[pos[q]] = nv[q];
+            rns[pos[q]].push_back(nv[q]);
         }
     }
     RecTable T;
@@ -465,6 +466,10 @@ omg_status mg_b(Group& g, std::vector<int> act, int l, int variant) {
         Level& L = LV(s, l);
         s->visits.push_back(l);
         s->visits.push_back(its[i]);
+        s->vnorm.push_back(l);
+        s->vnorm.push_back(its[i]);
+        s->vnorm.push_back(r0[i]);
+        s->vnorm.insert(s->vnorm.end(), rns[i].begin(), rns[i].end());
         if (l == 0) {
             if (!std::isfinite(rn[i])) g.stat[c] = OMG_EINVAL;
             else if (rn[i] > g.tol[c] * r0[i]) g.stat[c] = OMG_ENOCONV;

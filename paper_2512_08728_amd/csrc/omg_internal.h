@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/omg.h"
+#include "../../include/omg_inspect.h"
 
 namespace omg {
 
@@ -135,6 +136,15 @@ struct Level {
     int ntile = 0;
 
     std::vector<int> hcol;             // host copy of col (Galerkin symbolic phase)
+    // agglomeration maps (R and P of Algorithm 2). On a level with a coarser
+    // one: up[K] = parent(K) << 3 | slot(K) (device) and its host copy hup.
+    // On a level with a finer one: the finer cells of coarse cell I are
+    // dn[dn_ptr[I] .. dn_ptr[I+1]) (device), each K << 3 | slot(K), ordered by
+    // (slot, K) -- the order in which restriction sums them.
+    int* up = nullptr;
+    std::vector<int> hup;
+    int* dn_ptr = nullptr;
+    int* dn = nullptr;
     int* dslot = nullptr;              // [n] slot of the diagonal block of each cell
     // block-contiguous copies for the multi-right-hand-side kernels (built on
     // first use): blocks [n][width][bs][bs], inverses [n][bs][bs]
@@ -198,7 +208,7 @@ struct Trace {
 
 struct omg_solver {
     omg_options opt;
-    omg_grid grid;
+    omg_grid grid;                     // SIP geometry (omg_setup_sip); nx*ny*nz = level 0's cells
     int bs = 0, bsh = 0, p = 0, nlev = 0;
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cstream = nullptr;     // coarse-path stream (OVERLAP_DET)
@@ -221,8 +231,17 @@ struct omg_solver {
     std::vector<int> visits;
     std::vector<int> steps;            // smoother+RM steps per cycle of the forking level
     std::vector<omg::Trace> trace;
-    std::vector<int> replay;
-    size_t replay_pos = 0;
+    std::vector<int> replay;           // (level, iterations) pairs set by omg_set_replay
+    // per-level queues of the replay during a solve (one host thread touches
+    // one level's queue at a time; the outer vectors are sized before it)
+    std::vector<std::vector<int>> replay_q;
+    std::vector<size_t> replay_pos;
+    int replaying = 0;
+    // per-visit residual log of the last solve, in completion order: level,
+    // iterations, ||r0||, then ||r|| after each iteration (what the level
+    // tests of Sec. 4.2 read); appended under vnorm_mu (the adaptive cycle's
+    // coarse thread logs its visits too)
+    std::vector<double> vnorm;
     int mode32 = 0;                    // 0 FP64, 1 FP32 everywhere, 2 FP32 except finest-level RM
     int64_t kcount[OMG_K_COUNT][OMG_MAX_LEVELS] = {};  // launches per kernel kind and level
     int64_t nnzb_level[OMG_MAX_LEVELS] = {};           // stored (non-padding) blocks per level
@@ -371,7 +390,10 @@ hipError_t tune_mr(Level& L, int bs, int nr, const ColPtrs& X, const ColPtrs& Y,
 struct XferTable {
     int count;
     int blk0[kMaxCols + 1];
-    int fnx[kMaxCols], fny[kMaxCols], fn[kMaxCols], cnx[kMaxCols], cny[kMaxCols], cn[kMaxCols];
+    int fn[kMaxCols], cn[kMaxCols];
+    const int* up[kMaxCols];           // the fine level's maps (Level::up)
+    const int* dn_ptr[kMaxCols];       // the coarse level's child lists
+    const int* dn[kMaxCols];
     const double* in[kMaxCols];
     double* out[kMaxCols];
 };

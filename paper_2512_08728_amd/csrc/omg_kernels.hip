@@ -333,19 +333,20 @@ __global__ __launch_bounds__(64 * BS) void k_bj_sweep_rows(int n, int width, con
 }
 
 // ----------------------------------------------------------------- transfers
-// Restriction r_c = P^T r: each coarse cell sums E_s^T r_child over its 8
-// children in slot order s = sx + 2 sy + 4 sz. E is [8][BS][BS] (fine row,
-// coarse column).
+// Restriction r_c = P^T r: each coarse cell sums E_s^T r_K over its finer
+// cells K (slot s), taken from its child list in (slot, K) order. E is
+// [8][BS][BS] (fine row, coarse column).
 template <int BS, typename MT>
-__device__ __forceinline__ void restrict_cell(int I, int fnx, int fny, int fn, int cnx, int cny, int cn,
-                                              const MT* __restrict__ E, const double* __restrict__ r,
-                                              double* __restrict__ rc) {
-    const int ci = I % cnx, cj = (I / cnx) % cny, ck = I / (cnx * cny);
+__device__ __forceinline__ void restrict_cell(int I, int fn, int cn, const int* __restrict__ dn_ptr,
+                                              const int* __restrict__ dn, const MT* __restrict__ E,
+                                              const double* __restrict__ r, double* __restrict__ rc) {
     MT out[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) out[c] = MT(0);
-    for (int s = 0; s < 8; ++s) {
-        const int K = (2 * ci + (s & 1)) + fnx * ((2 * cj + ((s >> 1) & 1)) + fny * (2 * ck + ((s >> 2) & 1)));
+    const int q1 = dn_ptr[I + 1];
+    for (int q = dn_ptr[I]; q < q1; ++q) {
+        const int e = dn[q];
+        const int K = e >> 3, s = e & 7;
         MT rv[BS];
 #pragma unroll
         for (int m = 0; m < BS; ++m) rv[m] = (MT)r[(int64_t)m * fn + K];
@@ -363,22 +364,21 @@ __device__ __forceinline__ void restrict_cell(int I, int fnx, int fny, int fn, i
 }
 
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_restrict(int fnx, int fny, int fn, int cnx, int cny, int cn,
-                                                       const MT* __restrict__ E, const double* __restrict__ r,
-                                                       double* __restrict__ rc) {
+__global__ __launch_bounds__(kThreads) void k_restrict(int fn, int cn, const int* __restrict__ dn_ptr,
+                                                       const int* __restrict__ dn, const MT* __restrict__ E,
+                                                       const double* __restrict__ r, double* __restrict__ rc) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= cn) return;
-    restrict_cell<BS, MT>(I, fnx, fny, fn, cnx, cny, cn, E, r, rc);
+    restrict_cell<BS, MT>(I, fn, cn, dn_ptr, dn, E, r, rc);
 }
 
 // Prolongation z = P z_c: z_K = E_{slot(K)} z_{parent(K)}.
 template <int BS, typename MT>
-__device__ __forceinline__ void prolong_cell(int K, int fnx, int fny, int fn, int cnx, int cny, int cn,
+__device__ __forceinline__ void prolong_cell(int K, int fn, int cn, const int* __restrict__ up,
                                              const MT* __restrict__ E, const double* __restrict__ zc,
                                              double* __restrict__ z) {
-    const int i = K % fnx, j = (K / fnx) % fny, k = K / (fnx * fny);
-    const int I = (i >> 1) + cnx * ((j >> 1) + cny * (k >> 1));
-    const int s = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    const int e = up[K];
+    const int I = e >> 3, s = e & 7;
     MT zv[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) zv[c] = (MT)zc[(int64_t)c * cn + I];
@@ -393,12 +393,12 @@ __device__ __forceinline__ void prolong_cell(int K, int fnx, int fny, int fn, in
 }
 
 template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_prolong(int fnx, int fny, int fn, int cnx, int cny, int cn,
+__global__ __launch_bounds__(kThreads) void k_prolong(int fn, int cn, const int* __restrict__ up,
                                                       const MT* __restrict__ E, const double* __restrict__ zc,
                                                       double* __restrict__ z) {
     const int K = blockIdx.x * blockDim.x + threadIdx.x;
     if (K >= fn) return;
-    prolong_cell<BS, MT>(K, fnx, fny, fn, cnx, cny, cn, E, zc, z);
+    prolong_cell<BS, MT>(K, fn, cn, up, E, zc, z);
 }
 
 // Grouped transfers over several members (segment q: blocks [blk0[q], blk0[q+1])).
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_grouped(XferTable T, cons
     const int q = seg_of(T, blockIdx.x);
     const int I = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
     if (I >= T.cn[q]) return;
-    restrict_cell<BS, MT>(I, T.fnx[q], T.fny[q], T.fn[q], T.cnx[q], T.cny[q], T.cn[q], E, T.in[q], T.out[q]);
+    restrict_cell<BS, MT>(I, T.fn[q], T.cn[q], T.dn_ptr[q], T.dn[q], E, T.in[q], T.out[q]);
 }
 
 template <int BS, typename MT>
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong_grouped(XferTable T, const
     const int q = seg_of(T, blockIdx.x);
     const int K = (blockIdx.x - T.blk0[q]) * blockDim.x + threadIdx.x;
     if (K >= T.fn[q]) return;
-    prolong_cell<BS, MT>(K, T.fnx[q], T.fny[q], T.fn[q], T.cnx[q], T.cny[q], T.cn[q], E, T.in[q], T.out[q]);
+    prolong_cell<BS, MT>(K, T.fn[q], T.cn[q], T.up[q], E, T.in[q], T.out[q]);
 }
 
 // Level entry for several members: segment q runs k_level_init's loop on its
@@ -897,11 +897,11 @@ hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, co
                            const double* r, double* rc, hipStream_t st) {
     dim3 grid(cdiv(C.n, kThreads)), block(kThreads);
     if (fp32) {
-        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, float>), grid, block, 0, st, F.nx, F.ny, F.n, C.nx,
-                                               C.ny, C.n, E32, r, rc));
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, float>), grid, block, 0, st, F.n, C.n, C.dn_ptr,
+                                               C.dn, E32, r, rc));
     } else {
-        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, double>), grid, block, 0, st, F.nx, F.ny, F.n,
-                                               C.nx, C.ny, C.n, E, r, rc));
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, double>), grid, block, 0, st, F.n, C.n, C.dn_ptr,
+                                               C.dn, E, r, rc));
     }
     return hipGetLastError();
 }
@@ -910,11 +910,11 @@ hipError_t launch_prolong(const Level& F, const Level& C, int bs, bool fp32, con
                           const double* zc, double* z, hipStream_t st) {
     dim3 grid(cdiv(F.n, kThreads)), block(kThreads);
     if (fp32) {
-        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong<BSV, float>), grid, block, 0, st, F.nx, F.ny, F.n, C.nx,
-                                               C.ny, C.n, E32, zc, z));
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong<BSV, float>), grid, block, 0, st, F.n, C.n, F.up, E32,
+                                               zc, z));
     } else {
-        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong<BSV, double>), grid, block, 0, st, F.nx, F.ny, F.n, C.nx,
-                                               C.ny, C.n, E, zc, z));
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_prolong<BSV, double>), grid, block, 0, st, F.n, C.n, F.up, E,
+                                               zc, z));
     }
     return hipGetLastError();
 }

@@ -219,7 +219,7 @@ __global__ void k_assemble_sip(int nx, int ny, int nz, int bs, int bsh, const do
 // list of E_{s(K)}^T A_{K, jf} E_{s(K')}, K' = col(K, jf). One block of
 // threads per coarse block; contributions summed in list order (fine cell
 // ascending, slot ascending).
-__global__ void k_galerkin(int bs, int bsh, int fnx, int fny, int fn, const int* __restrict__ fcol,
+__global__ void k_galerkin(int bs, int bsh, const int* __restrict__ fup, int fn, const int* __restrict__ fcol,
                            const double* __restrict__ fval, int cn, const int64_t* __restrict__ cptr,
                            const int* __restrict__ cK, const int* __restrict__ cj, const double* __restrict__ E,
                            double* __restrict__ cval, int cwidth) {
@@ -237,8 +237,8 @@ __global__ void k_galerkin(int bs, int bsh, int fnx, int fny, int fn, const int*
     for (int64_t q = cptr[blk]; q < cptr[blk + 1]; ++q) {
         const int K = cK[q], jf = cj[q];
         const int Kp = fcol[(int64_t)jf * fn + K];
-        const int sK = (K % fnx & 1) + 2 * ((K / fnx) % fny & 1) + 4 * ((K / (fnx * fny)) & 1);
-        const int sKp = (Kp % fnx & 1) + 2 * ((Kp / fnx) % fny & 1) + 4 * ((Kp / (fnx * fny)) & 1);
+        const int sK = fup[K] & 7;
+        const int sKp = fup[Kp] & 7;
         for (int e = threadIdx.x; e < bb; e += blockDim.x) {
             const int r = e / bs, c = e % bs;
             const double2 v = fv[((int64_t)(jf * bs + r) * bsh + (c >> 1)) * fn + K];
@@ -676,6 +676,41 @@ omg_status omg_assemble_sip(omg_solver* s, const double* nu_dev, std::vector<uns
     return OMG_OK;
 }
 
+// Agglomeration maps between level l and l+1 (host parent/slot of every cell
+// of level l): validated (parents in range, slots 0..7, every coarse cell
+// with at least one finer cell) and uploaded as Level::up of level l and the
+// child lists Level::dn_ptr / dn of level l+1, children in (slot, index)
+// order.
+omg_status omg_upload_maps(omg_solver* s, int l, const int32_t* parent, const uint8_t* slot) {
+    Level& F = s->lev[l];
+    Level& C = s->lev[l + 1];
+    const int fn = F.n, cn = C.n;
+    if (fn >= (1 << 28) || cn >= (1 << 28)) return OMG_EUNSUPPORTED; // packed with the slot in 3 bits
+    F.hup.assign(fn, 0);
+    std::vector<int> ptr(cn + 1, 0);
+    for (int K = 0; K < fn; ++K) {
+        const int I = parent[K], sl = slot[K];
+        if (I < 0 || I >= cn || sl > 7) return OMG_EINVAL;
+        F.hup[K] = I << 3 | sl;
+        ptr[I + 1]++;
+    }
+    for (int I = 0; I < cn; ++I) {
+        if (ptr[I + 1] == 0) return OMG_EINVAL; // a coarse cell with no finer cell
+        ptr[I + 1] += ptr[I];
+    }
+    std::vector<int> dn(fn), fill(ptr.begin(), ptr.end() - 1);
+    for (int sl = 0; sl < 8; ++sl)
+        for (int K = 0; K < fn; ++K)
+            if ((F.hup[K] & 7) == sl) dn[fill[F.hup[K] >> 3]++] = K << 3 | sl;
+    OMG_TRY(dmalloc((void**)&F.up, sizeof(int) * fn));
+    OMG_TRY(dmalloc((void**)&C.dn_ptr, sizeof(int) * (cn + 1)));
+    OMG_TRY(dmalloc((void**)&C.dn, sizeof(int) * fn));
+    OMG_TRY_HIP(hipMemcpy(F.up, F.hup.data(), sizeof(int) * fn, hipMemcpyHostToDevice));
+    OMG_TRY_HIP(hipMemcpy(C.dn_ptr, ptr.data(), sizeof(int) * (cn + 1), hipMemcpyHostToDevice));
+    OMG_TRY_HIP(hipMemcpy(C.dn, dn.data(), sizeof(int) * fn, hipMemcpyHostToDevice));
+    return OMG_OK;
+}
+
 // Galerkin A_{l+1} = P^T A_l P: symbolic pattern and contribution lists on the
 // host, numeric triple products on the device.
 omg_status omg_galerkin(omg_solver* s, int l, const std::vector<unsigned char>& fvalid,
@@ -683,10 +718,7 @@ omg_status omg_galerkin(omg_solver* s, int l, const std::vector<unsigned char>& 
     Level& F = s->lev[l];
     Level& C = s->lev[l + 1];
     const int fn = F.n, cn = C.n, bs = s->bs, bsh = s->bsh;
-    auto parent = [&](int K) {
-        const int i = K % F.nx, j = (K / F.nx) % F.ny, k = K / (F.nx * F.ny);
-        return (i >> 1) + C.nx * ((j >> 1) + C.ny * (k >> 1));
-    };
+    auto parent = [&](int K) { return F.hup[K] >> 3; };
     // coarse rows: sorted unique parents of the children's columns
     std::vector<std::vector<int>> rows(cn);
     for (int K = 0; K < fn; ++K) {
@@ -751,7 +783,7 @@ omg_status omg_galerkin(omg_solver* s, int l, const std::vector<unsigned char>& 
         hipMemcpyAsync(C.col, C.hcol.data(), sizeof(int) * C.hcol.size(), hipMemcpyHostToDevice, s->stream);
         hipMemsetAsync(C.val, 0, sizeof(double) * 2 * nblk * bs * bsh, s->stream);
         const size_t shm = sizeof(double) * (size_t)bs * bs * 10;
-        hipLaunchKernelGGL(k_galerkin, dim3((unsigned)nblk), dim3(256), shm, s->stream, bs, bsh, F.nx, F.ny, fn,
+        hipLaunchKernelGGL(k_galerkin, dim3((unsigned)nblk), dim3(256), shm, s->stream, bs, bsh, F.up, fn,
                            F.col, F.val, cn, dptr, dK, dj, s->E, C.val, width);
         if (hipGetLastError() != hipSuccess) st = OMG_EHIP;
         if (hipStreamSynchronize(s->stream) != hipSuccess) st = OMG_EHIP;

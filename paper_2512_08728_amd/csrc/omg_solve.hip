@@ -109,6 +109,9 @@ static void free_level(Level& L) {
         hipFree(L.as_inv32);
         hipFree(L.as_z);
         hipFree(L.dblk32);
+        hipFree(L.up);
+        hipFree(L.dn_ptr);
+        hipFree(L.dn);
     }
     hipFree(L.b);
     hipFree(L.r);
@@ -202,43 +205,60 @@ static omg_status check_options(const omg_options* o) {
     return OMG_OK;
 }
 
-static omg_status create(const omg_grid* g, const omg_options* opt, void* stream, omg_solver** out) {
-    OMG_TRY(check_grid(g));
+// Degree of the total-degree basis with bs functions (the block sizes the
+// kernels are built for), -1 otherwise.
+static int degree_of(int bs) {
+    switch (bs) {
+    case 1: return 0;
+    case 4: return 1;
+    case 10: return 2;
+    case 20: return 3;
+    }
+    return -1;
+}
+
+static omg_status check_hierarchy(const omg_hierarchy* H, int n0) {
+    if (!H || H->n_levels < 1 || H->n_levels > OMG_MAX_LEVELS || !H->n_cells || H->n_cells[0] != n0)
+        return OMG_EINVAL;
+    for (int l = 0; l < H->n_levels; ++l)
+        if (H->n_cells[l] < 1) return OMG_EINVAL;
+    if (H->n_levels > 1 && (!H->parent || !H->slot)) return OMG_EINVAL;
+    for (int l = 0; l + 1 < H->n_levels; ++l)
+        if (!H->parent[l] || !H->slot[l]) return OMG_EINVAL;
+    return OMG_OK;
+}
+
+// Solver shell: level sizes from the hierarchy, streams, events, host
+// scalars, layout buffers. The maps and the embedding come next.
+static omg_status create(int nlev, const int32_t* n_cells, int bs, const omg_options* opt, void* stream,
+                         omg_solver** out) {
+    *out = nullptr;
     OMG_TRY(check_options(opt));
+    const int p = degree_of(bs);
+    if (p < 0) return OMG_EUNSUPPORTED;
     omg_solver* s = new omg_solver();
-    s->grid = *g;
+    *out = s;
     if (opt) s->opt = *opt;
     else omg_default_options(&s->opt);
-    s->p = g->p;
-    s->bs = (g->p + 1) * (g->p + 2) * (g->p + 3) / 6;
+    std::memset(&s->grid, 0, sizeof(s->grid));
+    s->p = p;
+    s->bs = bs;
     s->bsh = (s->bs + 1) / 2;
-    s->nlev = g->n_levels;
+    s->nlev = nlev;
     s->stream = (hipStream_t)stream;
     s->lev.resize(s->nlev);
+    const char* rs = std::getenv("OMG_ROWSPLIT_MAX_CELLS");
     for (int l = 0; l < s->nlev; ++l) {
         Level& L = s->lev[l];
-        L.nx = g->nx >> l;
-        L.ny = g->ny >> l;
-        L.nz = g->nz >> l;
-        L.n = L.nx * L.ny * L.nz;
+        L.n = n_cells[l];
         L.N = (int64_t)L.n * s->bs;
         L.coarsest = (l == s->nlev - 1);
         L.G = reduction_blocks(L.N);
         // few cells: split block rows over threads so the launch covers the GPU
-        const char* rs = std::getenv("OMG_ROWSPLIT_MAX_CELLS");
         L.rowsplit = s->bs <= 16 && L.n <= (rs ? std::atoi(rs) : 65536); // 64*bs threads per smoother block
     }
-    *out = s;
     if (hipMalloc((void**)&s->err_flag, sizeof(int)) != hipSuccess) return OMG_ENOMEM;
     OMG_TRY(alloc_host_scalars(s));
-    std::vector<double> E;
-    embedding_blocks(s->p, E);
-    s->hE = E;
-    std::vector<float> E32(E.begin(), E.end());
-    if (hipMalloc((void**)&s->E, sizeof(double) * E.size()) != hipSuccess) return OMG_ENOMEM;
-    if (hipMalloc((void**)&s->E32, sizeof(float) * E.size()) != hipSuccess) return OMG_ENOMEM;
-    HIP_OK(hipMemcpy(s->E, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->E32, E32.data(), sizeof(float) * E.size(), hipMemcpyHostToDevice));
     const size_t vb = sizeof(double) * (size_t)s->lev[0].N;
     if (hipMalloc((void**)&s->bufA, vb) != hipSuccess) return OMG_ENOMEM;
     if (hipMalloc((void**)&s->bufB, vb) != hipSuccess) return OMG_ENOMEM;
@@ -247,6 +267,85 @@ static omg_status create(const omg_grid* g, const omg_options* opt, void* stream
     HIP_OK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&s->ev_step[0], hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&s->ev_step[1], hipEventDisableTiming));
+    return OMG_OK;
+}
+
+omg_status omg_upload_maps(omg_solver* s, int l, const int32_t* parent, const uint8_t* slot);
+
+// Embedding blocks (host [8][bs][bs]) and the agglomeration maps of every level.
+static omg_status set_hierarchy(omg_solver* s, const omg_hierarchy* H, const double* E) {
+    const size_t ne = (size_t)8 * s->bs * s->bs;
+    for (size_t t = 0; t < ne; ++t)
+        if (!std::isfinite(E[t])) return OMG_EINVAL;
+    s->hE.assign(E, E + ne);
+    std::vector<float> E32(E, E + ne);
+    if (hipMalloc((void**)&s->E, sizeof(double) * ne) != hipSuccess) return OMG_ENOMEM;
+    if (hipMalloc((void**)&s->E32, sizeof(float) * ne) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipMemcpy(s->E, E, sizeof(double) * ne, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->E32, E32.data(), sizeof(float) * ne, hipMemcpyHostToDevice));
+    for (int l = 0; l + 1 < s->nlev; ++l) OMG_TRY(omg_upload_maps(s, l, H->parent[l], H->slot[l]));
+    return OMG_OK;
+}
+
+// The 2x2x2 agglomeration of a Cartesian grid, as host arrays owned here.
+struct GridHierarchy {
+    std::vector<int32_t> n_cells;
+    std::vector<std::vector<int32_t>> parent;
+    std::vector<std::vector<uint8_t>> slot;
+    std::vector<const int32_t*> pp;
+    std::vector<const uint8_t*> sp;
+    std::vector<double> E;
+    omg_hierarchy H;
+};
+
+static omg_status grid_maps(const omg_grid* g, int level, int32_t* parent, uint8_t* slot) {
+    const int nx = g->nx >> level, ny = g->ny >> level, nz = g->nz >> level;
+    const int cx = nx / 2, cy = ny / 2;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int K = i + nx * (j + ny * k);
+                parent[K] = (i >> 1) + cx * ((j >> 1) + cy * (k >> 1));
+                slot[K] = (uint8_t)((i & 1) + 2 * (j & 1) + 4 * (k & 1));
+            }
+    return OMG_OK;
+}
+
+static omg_status make_grid_hierarchy(const omg_grid* g, GridHierarchy& G) {
+    OMG_TRY(check_grid(g));
+    const int nl = g->n_levels;
+    G.n_cells.resize(nl);
+    G.parent.resize(nl > 1 ? nl - 1 : 0);
+    G.slot.resize(nl > 1 ? nl - 1 : 0);
+    for (int l = 0; l < nl; ++l) G.n_cells[l] = (g->nx >> l) * (g->ny >> l) * (g->nz >> l);
+    for (int l = 0; l + 1 < nl; ++l) {
+        G.parent[l].resize(G.n_cells[l]);
+        G.slot[l].resize(G.n_cells[l]);
+        OMG_TRY(grid_maps(g, l, G.parent[l].data(), G.slot[l].data()));
+        G.pp.push_back(G.parent[l].data());
+        G.sp.push_back(G.slot[l].data());
+    }
+    embedding_blocks(g->p, G.E);
+    G.H.n_levels = nl;
+    G.H.pad = 0;
+    G.H.n_cells = G.n_cells.data();
+    G.H.parent = G.pp.empty() ? nullptr : G.pp.data();
+    G.H.slot = G.sp.empty() ? nullptr : G.sp.data();
+    G.H.embed = G.E.data();
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_grid_hierarchy(const omg_grid* g, int32_t level, int32_t* parent, uint8_t* slot) {
+    OMG_TRY(check_grid(g));
+    if (level < 0 || level >= g->n_levels - 1 || !parent || !slot) return OMG_EINVAL;
+    return grid_maps(g, level, parent, slot);
+}
+
+extern "C" omg_status omg_embedding(int32_t p, double* E) {
+    if (p < 0 || p > 3 || !E) return OMG_EINVAL;
+    std::vector<double> v;
+    embedding_blocks(p, v);
+    std::memcpy(E, v.data(), sizeof(double) * v.size());
     return OMG_OK;
 }
 
@@ -420,14 +519,15 @@ static omg_status build_hierarchy(omg_solver* s, std::vector<unsigned char>& val
     return OMG_OK;
 }
 
-extern "C" omg_status omg_setup(const omg_bsr* A, const omg_grid* grid, const omg_options* opt, void* hip_stream,
-                                omg_solver** out) {
+extern "C" omg_status omg_setup(const omg_bsr* A, const omg_hierarchy* H, const omg_options* opt,
+                                void* hip_stream, omg_solver** out) {
     if (!out) return OMG_EINVAL;
     *out = nullptr;
-    if (!A || !grid || !A->row_ptr || !A->col_idx || !A->val) return OMG_EINVAL;
-    const int n = grid->nx * grid->ny * grid->nz;
-    const int bs = (grid->p + 1) * (grid->p + 2) * (grid->p + 3) / 6;
-    if (A->n_cells != n || A->bs != bs || A->row_ptr[0] != 0 || A->row_ptr[n] != A->nnzb) return OMG_EINVAL;
+    if (!A || !A->row_ptr || !A->col_idx || !A->val || !H || !H->embed) return OMG_EINVAL;
+    const int n = A->n_cells, bs = A->bs;
+    if (n < 1 || bs < 1) return OMG_EINVAL;
+    OMG_TRY(check_hierarchy(H, n));
+    if (A->row_ptr[0] != 0 || A->row_ptr[n] != A->nnzb) return OMG_EINVAL;
     for (int i = 0; i < n; ++i) {
         if (A->row_ptr[i + 1] < A->row_ptr[i]) return OMG_EINVAL;
         bool diag = false;
@@ -442,7 +542,8 @@ extern "C" omg_status omg_setup(const omg_bsr* A, const omg_grid* grid, const om
     for (int64_t t = 0; t < A->nnzb * bs * bs; ++t)
         if (!std::isfinite(A->val[t])) return OMG_EINVAL;
     omg_solver* s = nullptr;
-    omg_status st = create(grid, opt, hip_stream, &s);
+    omg_status st = create(H->n_levels, H->n_cells, bs, opt, hip_stream, &s);
+    if (st == OMG_OK) st = set_hierarchy(s, H, H->embed);
     std::vector<unsigned char> valid;
     if (st == OMG_OK) st = omg_ingest_bsr(s, A, valid);
     if (st == OMG_OK) st = build_hierarchy(s, valid);
@@ -454,16 +555,41 @@ extern "C" omg_status omg_setup(const omg_bsr* A, const omg_grid* grid, const om
     return OMG_OK;
 }
 
-extern "C" omg_status omg_setup_sip(const omg_grid* grid, const double* nu, const omg_options* opt,
-                                    void* hip_stream, omg_solver** out) {
+extern "C" omg_status omg_setup_sip(const omg_grid* grid, const double* nu, const omg_hierarchy* H,
+                                    const omg_options* opt, void* hip_stream, omg_solver** out) {
     if (!out) return OMG_EINVAL;
     *out = nullptr;
-    if (!grid || !nu || !(grid->h > 0) || !std::isfinite(grid->penalty_c)) return OMG_EINVAL;
+    if (!grid || !nu || !(grid->h > 0) || !std::isfinite(grid->penalty_c) || grid->nx < 1 || grid->ny < 1 ||
+        grid->nz < 1 || grid->p < 0 || grid->p > 3)
+        return OMG_EINVAL;
+    const int n = grid->nx * grid->ny * grid->nz;
+    GridHierarchy GH;
+    std::vector<double> E;
+    if (!H) {
+        OMG_TRY(make_grid_hierarchy(grid, GH));
+        H = &GH.H;
+    } else {
+        OMG_TRY(check_hierarchy(H, n));
+    }
+    const double* Eh = H->embed;
+    if (!Eh) {
+        embedding_blocks(grid->p, E);
+        Eh = E.data();
+    }
+    const int bs = (grid->p + 1) * (grid->p + 2) * (grid->p + 3) / 6;
     omg_solver* s = nullptr;
-    omg_status st = create(grid, opt, hip_stream, &s);
+    omg_status st = create(H->n_levels, H->n_cells, bs, opt, hip_stream, &s);
+    if (st == OMG_OK) {
+        s->grid = *grid;
+        s->grid.n_levels = H->n_levels;
+        Level& L0 = s->lev[0];
+        L0.nx = grid->nx;
+        L0.ny = grid->ny;
+        L0.nz = grid->nz;
+        st = set_hierarchy(s, H, Eh);
+    }
     if (st == OMG_OK) {
         // nu must be positive and finite
-        const int n = s->lev[0].n;
         std::vector<double> hnu(n);
         if (hipMemcpy(hnu.data(), nu, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess) st = OMG_EHIP;
         for (int i = 0; st == OMG_OK && i < n; ++i)
@@ -476,7 +602,7 @@ extern "C" omg_status omg_setup_sip(const omg_grid* grid, const double* nu, cons
         st = build_hierarchy(s, valid);
     }
     if (st != OMG_OK) {
-        omg_destroy(s);
+        if (s) omg_destroy(s);
         return st;
     }
     *out = s;
@@ -729,12 +855,6 @@ static omg_status trace_rm(omg_solver* s, int l, hipStream_t st, int type) {
     return OMG_OK;
 }
 
-// per-level replay queues built from a visit log
-struct ReplayState {
-    std::vector<std::vector<int>> q;
-    std::vector<size_t> pos;
-};
-static thread_local ReplayState* g_replay = nullptr;
 
 static bool stop_level(const omg_solver* s, int l, double rn, double r0n, double bn, int it, double tol,
                        int replay_count) {
@@ -829,13 +949,14 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     OMG_TRY(read_rnorm(s, l, st, &r0n));
     const double bn = r0n;
     if (l == 0) log_trace(s, r0n, 0);
-    int replay_count = -1;
-    if (g_replay && l < (int)g_replay->q.size() && g_replay->pos[l] < g_replay->q[l].size())
-        replay_count = g_replay->q[l][g_replay->pos[l]++];
+    int replay_count = -1; // replayed iteration count of this visit (omg_set_replay)
+    if (s->replaying && l < (int)s->replay_q.size() && s->replay_pos[l] < s->replay_q[l].size())
+        replay_count = s->replay_q[l][s->replay_pos[l]++];
     const int sub_variant = cycle_sub_variant(variant, s->opt.coarse_sync);
     int it = 0;
     double rn = r0n;
     omg_status status = OMG_OK;
+    std::vector<double> rns; // ||r|| after each iteration of this visit
     while (!stop_level(s, l, rn, r0n, bn, it, tol, replay_count)) {
         if (cycle_multiplicative(variant)) {
             OMG_TRY(smoother(s, l, L.r, s->opt.s_pre, L.z, st));
@@ -884,6 +1005,7 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
         }
         it++;
         OMG_TRY(read_rnorm(s, l, st, &rn));
+        rns.push_back(rn);
         if (!std::isfinite(rn)) {
             status = OMG_EINVAL;
             break;
@@ -892,6 +1014,10 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
     if (l == 0 && status == OMG_OK && rn > tol * bn && replay_count < 0) status = OMG_ENOCONV;
     s->visits.push_back(l);
     s->visits.push_back(it);
+    s->vnorm.push_back(l);
+    s->vnorm.push_back(it);
+    s->vnorm.push_back(r0n);
+    s->vnorm.insert(s->vnorm.end(), rns.begin(), rns.end());
     if (L.persist) { // x = sum_k d_k z~_k: the search directions are implicit
         HIP_OK(launch_recon(L.k, L.hist, L.gammas, L.alphas, L.dvec, st));
         HIP_OK(launch_lincomb(L.N, L.k, L.dvec, L.dZp, xout, st));
@@ -1005,6 +1131,7 @@ static omg_status finish_report(omg_solver* s, const double* b, const double* x,
 
 static void reset_logs(omg_solver* s) {
     s->visits.clear();
+    s->vnorm.clear();
     s->steps.clear();
     s->trace.clear();
     s->step = 0;
@@ -1034,16 +1161,13 @@ static omg_status check_rm_abort(omg_solver* s) {
 
 static omg_status solve_internal(omg_solver* s, const double* b_soa, double* x_soa, double tol, omg_report* R) {
     reset_logs(s);
-    ReplayState rs;
-    if (!s->replay.empty()) {
-        rs.q.assign(s->nlev, {});
-        rs.pos.assign(s->nlev, 0);
-        for (size_t i = 0; i + 1 < s->replay.size(); i += 2)
-            if (s->replay[i] >= 0 && s->replay[i] < s->nlev) rs.q[s->replay[i]].push_back(s->replay[i + 1]);
-        g_replay = &rs;
-    }
+    s->replay_q.assign(s->nlev, {});
+    s->replay_pos.assign(s->nlev, 0);
+    s->replaying = !s->replay.empty();
+    for (size_t i = 0; i + 1 < s->replay.size(); i += 2)
+        if (s->replay[i] >= 0 && s->replay[i] < s->nlev) s->replay_q[s->replay[i]].push_back(s->replay[i + 1]);
     omg_status st = solve_soa(s, b_soa, x_soa, tol, R);
-    g_replay = nullptr;
+    s->replaying = 0;
     const omg_status ab = check_rm_abort(s);
     return ab != OMG_OK ? ab : st;
 }
@@ -1132,6 +1256,9 @@ omg_status engine_make_column(omg_solver* o, omg_solver** out) {
         if (L.atile && hipMalloc((void**)&L.spart, sizeof(double) * (size_t)L.ntile * L.ntile * 64) != hipSuccess)
             return OMG_ENOMEM;
         L.dslot = P.dslot;
+        L.up = P.up;
+        L.dn_ptr = P.dn_ptr;
+        L.dn = P.dn;
         L.ablk = P.ablk;
         L.ablk32 = P.ablk32;
         L.dblk = P.dblk;
@@ -1159,13 +1286,15 @@ extern "C" omg_status omg_solve_backward(omg_solver* s, const double* u, const d
     Level& L = s->lev[0];
     double* lam = nullptr;
     if (hipMalloc((void**)&lam, sizeof(double) * L.N) != hipSuccess) return OMG_ENOMEM;
-    HIP_OK(hipMemsetAsync(lam, 0, sizeof(double) * L.N, s->stream));
-    omg_status st = omg_solve(s, g_u, lam, tol, nullptr, rep); // adjoint: A symmetric
-    if (st == OMG_OK || st == OMG_ENOCONV) {
-        if (g_f) HIP_OK(hipMemcpyAsync(g_f, lam, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s->stream));
-        if (g_nu) HIP_OK(omg_launch_contract(s, lam, u, g_nu, s->stream));
-        HIP_OK(hipStreamSynchronize(s->stream));
-    }
+    omg_status st = OMG_OK;
+    if (launch_fill(lam, 0.0, L.N, s->stream) != hipSuccess) st = OMG_EHIP;
+    if (st == OMG_OK) st = omg_solve(s, g_u, lam, tol, nullptr, rep); // adjoint: A symmetric
+    // gradients only from a converged adjoint
+    if (st == OMG_OK && g_f &&
+        hipMemcpyAsync(g_f, lam, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+        st = OMG_EHIP;
+    if (st == OMG_OK && g_nu && omg_launch_contract(s, lam, u, g_nu, s->stream) != hipSuccess) st = OMG_EHIP;
+    if (hipStreamSynchronize(s->stream) != hipSuccess && st == OMG_OK) st = OMG_EHIP;
     hipFree(lam);
     return st;
 }
@@ -1314,10 +1443,12 @@ extern "C" omg_status omg_level_matrix(const omg_solver* s, int32_t level, int32
 }
 
 // level operations on cell-major vectors (converted through bufA/bufB and t/t2)
-extern "C" omg_status omg_level_spmv(omg_solver* s, int32_t level, const double* x, const double* b, double* y) {
+extern "C" omg_status omg_level_spmv(omg_solver* s, int32_t level, int32_t fp32, const double* x, const double* b,
+                                     double* y) {
     if (!s || level < 0 || level >= s->nlev || !x || !y) return OMG_EINVAL;
     Level& L = s->lev[level];
     if (L.coarsest && level > 0) return OMG_EUNSUPPORTED;
+    if (fp32 && !L.val32) return OMG_EUNSUPPORTED;
     hipStream_t st = s->stream;
     double *xs = s->bufA, *bs_ = nullptr, *ys = s->bufB;
     HIP_OK(launch_to_soa(x, xs, L.n, s->bs, st));
@@ -1326,43 +1457,50 @@ extern "C" omg_status omg_level_spmv(omg_solver* s, int32_t level, const double*
         if (!bs_) return OMG_EUNSUPPORTED;
         HIP_OK(launch_to_soa(b, bs_, L.n, s->bs, st));
     }
-    HIP_OK(launch_spmv(L, s->bs, false, xs, bs_, ys, st));
+    HIP_OK(launch_spmv(L, s->bs, fp32 != 0, xs, bs_, ys, st));
     HIP_OK(launch_from_soa(ys, y, L.n, s->bs, st));
     HIP_OK(hipStreamSynchronize(st));
     return OMG_OK;
 }
 
-extern "C" omg_status omg_level_smoother(omg_solver* s, int32_t level, const double* r, int32_t sweeps,
-                                         double* out) {
+extern "C" omg_status omg_level_smoother(omg_solver* s, int32_t level, int32_t fp32, const double* r,
+                                         int32_t sweeps, double* out) {
     if (!s || level < 0 || level >= s->nlev - 1 || !r || !out || sweeps < 1) return OMG_EINVAL;
     Level& L = s->lev[level];
+    if (fp32 && (!L.val32 || !L.dinv32 || (s->opt.smoother == OMG_SMOOTH_AS && !L.as_inv32)))
+        return OMG_EUNSUPPORTED;
     hipStream_t st = s->stream;
     HIP_OK(launch_to_soa(r, s->bufA, L.n, s->bs, st));
-    OMG_TRY(smoother(s, level, s->bufA, sweeps, s->bufB, st));
+    const int saved = s->mode32;
+    s->mode32 = fp32 ? 1 : 0;
+    const omg_status res = smoother(s, level, s->bufA, sweeps, s->bufB, st);
+    s->mode32 = saved;
+    OMG_TRY(res);
     HIP_OK(launch_from_soa(s->bufB, out, L.n, s->bs, st));
     HIP_OK(hipStreamSynchronize(st));
     return OMG_OK;
 }
 
-extern "C" omg_status omg_level_restrict(omg_solver* s, int32_t level, const double* r, double* rc) {
+extern "C" omg_status omg_level_restrict(omg_solver* s, int32_t level, int32_t fp32, const double* r,
+                                         double* rc) {
     if (!s || level < 0 || level >= s->nlev - 1 || !r || !rc) return OMG_EINVAL;
     Level& F = s->lev[level];
     Level& C = s->lev[level + 1];
     hipStream_t st = s->stream;
     HIP_OK(launch_to_soa(r, s->bufA, F.n, s->bs, st));
-    HIP_OK(launch_restrict(F, C, s->bs, false, s->E, s->E32, s->bufA, s->bufB, st));
+    HIP_OK(launch_restrict(F, C, s->bs, fp32 != 0, s->E, s->E32, s->bufA, s->bufB, st));
     HIP_OK(launch_from_soa(s->bufB, rc, C.n, s->bs, st));
     HIP_OK(hipStreamSynchronize(st));
     return OMG_OK;
 }
 
-extern "C" omg_status omg_level_prolong(omg_solver* s, int32_t level, const double* zc, double* z) {
+extern "C" omg_status omg_level_prolong(omg_solver* s, int32_t level, int32_t fp32, const double* zc, double* z) {
     if (!s || level < 0 || level >= s->nlev - 1 || !zc || !z) return OMG_EINVAL;
     Level& F = s->lev[level];
     Level& C = s->lev[level + 1];
     hipStream_t st = s->stream;
     HIP_OK(launch_to_soa(zc, s->bufA, C.n, s->bs, st));
-    HIP_OK(launch_prolong(F, C, s->bs, false, s->E, s->E32, s->bufA, s->bufB, st));
+    HIP_OK(launch_prolong(F, C, s->bs, fp32 != 0, s->E, s->E32, s->bufA, s->bufB, st));
     HIP_OK(launch_from_soa(s->bufB, z, F.n, s->bs, st));
     HIP_OK(hipStreamSynchronize(st));
     return OMG_OK;
@@ -1425,6 +1563,15 @@ extern "C" omg_status omg_get_visits(const omg_solver* s, int32_t* out, int32_t 
             out[2 * i] = s->visits[2 * i];
             out[2 * i + 1] = s->visits[2 * i + 1];
         }
+    return OMG_OK;
+}
+
+extern "C" omg_status omg_get_visit_norms(const omg_solver* s, double* out, int32_t cap, int32_t* n) {
+    if (!s || !n) return OMG_EINVAL;
+    const int cnt = (int)s->vnorm.size();
+    *n = cnt;
+    if (out)
+        for (int i = 0; i < cnt && i < cap; ++i) out[i] = s->vnorm[i];
     return OMG_OK;
 }
 

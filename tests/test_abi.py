@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads and
-exports every function that include/omg.h declares, and the binding's ctypes
-structures have the C layout of the header's structures."""
+exports every function that include/omg.h and include/omg_inspect.h declare,
+and the binding's ctypes structures have the C layout of the header's
+structures."""
 import ctypes
 import os
 import re
@@ -10,20 +11,27 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "omg.h")
+HEADERS = [HEADER, os.path.join(ROOT, "include", "omg_inspect.h")]
 LIB = os.path.join(ROOT, "paper_2512_08728_amd", "libomg.so")
 
 
-def declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(omg_[a-z_0-9]+)\s*\(", src)))
+def declared(headers=HEADERS):
+    names = set()
+    for h in headers:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(omg_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
-    names = declared()
+    """omg.h holds the solve boundary (setup from a matrix and a hierarchy,
+    setup from a coefficient field, solve, batched solve, backward, destroy)
+    and its helpers; the inspection hooks live in omg_inspect.h."""
+    names = declared([HEADER])
     for n in ("omg_setup", "omg_setup_sip", "omg_solve", "omg_solve_batched", "omg_solve_backward",
-              "omg_destroy", "omg_strerror"):
+              "omg_destroy", "omg_strerror", "omg_grid_hierarchy", "omg_embedding"):
         assert n in names
+    assert not any(n.startswith(("omg_level_", "omg_probe", "omg_bench", "omg_get_")) for n in names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -58,7 +66,8 @@ def test_struct_layout_matches_header(tmp_path):
     and every field offset of the option, report, grid and BSR structures;
     the ctypes mirrors must agree field by field."""
     import paper_2512_08728_amd as omg
-    mirrors = {"omg_options": omg.Options, "omg_report": omg.Report, "omg_grid": omg.Grid, "omg_bsr": omg.Bsr}
+    mirrors = {"omg_options": omg.Options, "omg_report": omg.Report, "omg_grid": omg.Grid, "omg_bsr": omg.Bsr,
+               "omg_hierarchy": omg.HierarchyC}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in mirrors.items():
         lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')

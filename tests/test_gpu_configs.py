@@ -85,6 +85,132 @@ def test_fullsize_kernels(big):
     assert np.abs(host(g.coarse_solve(cuda(bc))) - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+def test_fullsize_fp32_kernels(big):
+    """The single-precision SpMV, block-Jacobi, restriction and prolongation
+    of the mixed forms on the finest 64^3 P2 level against the oracle's FP32
+    emulation: within twice the float rounding bound of the exact result on
+    the rounded data (element by element for SpMV); errors printed."""
+    import scipy.sparse as sp
+    prob, nu, o, g = big
+    rng = np.random.default_rng(12)
+    eps = float(np.finfo(np.float32).eps)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    x = rng.standard_normal(prob.n_dofs)
+    b = rng.standard_normal(prob.n_dofs)
+    rp, ci, v = o.matrix(0)
+    absA = sp.bsr_matrix((np.abs(f32(v)), ci, rp), shape=(prob.n_dofs, prob.n_dofs))
+    bnd = 2 * (7 * prob.bs + 2) * eps * (absA @ np.abs(f32(x)) + np.abs(f32(b)))
+    del absA, v
+    yo = o.spmv(x, 0, b, fp32=True)
+    yg = host(g.level_spmv(0, cuda(x), cuda(b), fp32=True))
+    say(f"64^3 P2 FP32 SpMV: max rel. difference {np.abs(yg - yo).max() / np.abs(yo).max():.2e}")
+    assert np.all(np.abs(yg - yo) <= bnd)
+    for sw in (1, 2):
+        so = o.smoother(b, sw, 0, fp32=True)
+        err = np.abs(host(g.level_smoother(0, cuda(b), sw, fp32=True)) - so).max() / np.abs(so).max()
+        say(f"64^3 P2 FP32 block-Jacobi, {sw} iteration(s): max rel. difference {err:.2e}")
+        assert err <= 2e-5
+    ro = o.restrict(x, 0, fp32=True)
+    err = np.abs(host(g.level_restrict(0, cuda(x), fp32=True)) - ro).max() / np.abs(ro).max()
+    say(f"64^3 P2 FP32 restriction: max rel. difference {err:.2e}")
+    assert err <= 2 * (8 * prob.bs + 2) * eps * 8
+    zc = rng.standard_normal(len(ro))
+    po = o.prolong(zc, 0, fp32=True)
+    err = np.abs(host(g.level_prolong(0, cuda(zc), fp32=True)) - po).max() / np.abs(po).max()
+    say(f"64^3 P2 FP32 prolongation: max rel. difference {err:.2e}")
+    assert err <= 2 * (prob.bs + 2) * eps * 8
+
+
+def test_fullsize_rm_step_every_configuration(big):
+    """One residual-minimisation step (Algorithm 1 after w = A z) of the
+    finest 64^3 P2 level (N = 2,621,440) in every co-resident launch
+    configuration of the persistent kernel -- including the grids of more
+    than 256 blocks, where the exchange words are gathered in several passes
+    -- for k = 0, 1, 40 and 64 orthonormal directions, against the
+    sequential MGS step in numpy: coefficients, gamma, alpha, the new
+    direction and the residual to 1e-12."""
+    prob, nu, o, g = big
+    N = prob.n_dofs
+    rng = np.random.default_rng(31)
+    configs = g.rm_configs(0)
+    say(f"64^3 P2 finest level: {len(configs)} co-resident RM configurations, "
+        f"grids {sorted(set(c[0] for c in configs))}")
+    assert any(c[0] > 256 for c in configs)
+    Wall = np.linalg.qr(rng.standard_normal((N, 64)))[0].T.copy()
+    Wdev = cuda(Wall)
+    for k in (0, 1, 40, 64):
+        W = Wall[:k]
+        w, z, r = (rng.standard_normal(N) for _ in range(3))
+        ww = w.copy()
+        betas = []
+        for Wi in W:
+            bb = Wi @ ww
+            betas.append(bb)
+            ww -= bb * Wi
+        gamma = 1.0 / np.linalg.norm(ww)
+        wk = gamma * ww
+        alpha = wk @ r
+        rn = r - alpha * wk
+        wk_d, rn_d, w_d, z_d, r_d = cuda(wk), cuda(rn), cuda(w), cuda(z), cuda(r)
+        Wk_arg = Wdev[:k].contiguous() if k else None
+        rscale = np.abs(r).max()
+        for cfg in configs:
+            Wk, rn_g, b_g, gm_g, al_g = g.rm_step(0, Wk_arg, w_d, z_d, r_d, cfg)
+            what = f"k={k} config={cfg}"
+            assert np.abs(b_g - np.array(betas)).max(initial=0) <= 1e-12 * np.abs(w).max(), what
+            assert abs(gm_g - gamma) <= 1e-12 * gamma, what
+            assert abs(al_g - alpha) <= 1e-12 * np.linalg.norm(r), what
+            assert (Wk - wk_d).abs().max().item() <= 1e-12, what
+            assert (rn_g - rn_d).abs().max().item() <= 1e-12 * rscale, what
+
+
+def test_fullsize_replay_matches_oracle_golden(big):
+    """The 64^3 P2 plain-method solve (2+2 block-Jacobi sweeps, tolerance
+    1e-10, b from seed 0) with the oracle's visit log imposed on the GPU
+    (the oracle's solve of this workload is written by
+    tests/golden/make_oracle_64cubed_p2.py): every per-visit residual ratio
+    within 1e-9 of the oracle's, the solution within 1e-9 relative at
+    65,536 sampled entries and in ||x||, x.b and x.u."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_64cubed_p2.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated (tests/golden/make_oracle_64cubed_p2.py)")
+    gd = np.load(path, allow_pickle=False)
+    rep_o = json.loads(str(gd["report"]))
+    prob, nu, o, g = big
+    b = synth.rhs(prob.n_dofs, 0)
+    g.set_replay(gd["visits"])
+    t = time.time()
+    x = host(g.solve(cuda(b), tol=1e-10))
+    g.set_replay([])
+    rep = g.last_report
+    say(f"replayed 64^3 P2 solve: {time.time() - t:.1f} s, {rep['iters_fine']} cycles "
+        f"(oracle {rep_o['iters_fine']}), {rep['n_dirs_fine']} directions (oracle {rep_o['n_dirs_fine']})")
+    assert np.array_equal(g.visits(), gd["visits"])
+    assert rep["iters_fine"] == rep_o["iters_fine"] and rep["n_dirs_fine"] == rep_o["n_dirs_fine"]
+    log_o = oracle.parse_visit_norms(gd["vnorm"])
+    log_g = g.visit_norms()
+    assert len(log_o) == len(log_g)
+    dq = 0.0
+    for (lg, ig, r0g, rg), (lo, io, r0o, ro) in zip(log_g, log_o):
+        assert (lg, ig) == (lo, io)
+        dq = max(dq, abs(r0g / r0o - 1) if lg == 0 else 0.0, np.abs(rg / r0g - ro / r0o).max(initial=0.0))
+    idx = gd["idx"]
+    xs = gd["x_idx"]
+    e_s = np.linalg.norm(x[idx] - xs) / np.linalg.norm(xs)
+    u = synth.rhs(prob.n_dofs, 8)
+    xn = float(gd["x_norm"])
+    e_n = abs(np.linalg.norm(x) / xn - 1)
+    # |x.v - x*.v| <= ||x - x*|| ||v|| (Cauchy-Schwarz): relative to ||x*|| ||v||
+    e_b = abs(x @ b - float(gd["x_dot_b"])) / (xn * np.linalg.norm(b))
+    e_u = abs(x @ u - float(gd["x_dot_u"])) / (xn * np.linalg.norm(u))
+    say(f"max per-visit ratio difference {dq:.2e}; sampled solution {e_s:.2e}, ||x|| {e_n:.2e}, "
+        f"x.b {e_b:.2e}, x.u {e_u:.2e}; true residual {rep['rel_res_true']:.3e}")
+    assert dq <= 1e-9
+    assert e_s <= 1e-9 and e_n <= 1e-9 and e_b <= 1e-9 and e_u <= 1e-9
+
+
 def test_fullsize_solve_true_residual(big):
     """The benchmark solve reaches ||b - A x|| <= 1e-10 ||b|| with A the
     oracle's own operator; the recursive residual agrees with the true one."""

@@ -75,6 +75,28 @@ omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrh
 omg_status omg_level_rm_step(omg_solver *s, int32_t level, int32_t k, const double *W, const double *w,
                              const double *z, const double *r, const int32_t *cfg, double *Wk, double *r_new,
                              double *coeff);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of omg_level_rm_step on caller arrays without a solver. It allocates
+ * nothing: all scratch (grid-exchange words, block partials, abort flag, MGS
+ * coefficients, the pointer table of W's rows) is one fixed device array of
+ * the library, under 512 KB, which each GPU it runs on holds until the
+ * process ends. Sizes: 1 <= N <= OMG_NOALLOC_MAX_N entries, 0 <= k <=
+ * OMG_NOALLOC_MAX_K stored directions; beyond them (or a NULL or non-finite
+ * argument) OMG_EINVAL and nothing is launched.
+ * Inputs (device): W, k orthonormal directions as rows of a k x N array; w =
+ * A z; z; r. breakdown: the step drops the direction when ||w_out|| <=
+ * breakdown ||w_in|| (gamma = alpha = 0, Wk = 0, r_new = r). Outputs: Wk
+ * (device, N), r_new (device, N; may be r itself), host coeff[k + 2] =
+ * (beta_0..beta_{k-1}, gamma, alpha). Ordered on hip_stream (NULL: default),
+ * synchronised before returning; OMG_EHIP if a bounded wait of the kernel
+ * expired (results then not trustworthy). Every call on one GPU uses that
+ * GPU's single scratch array: calls that overlap in time on one GPU (other
+ * host threads, other streams) race and must not be made. */
+enum { OMG_NOALLOC_MAX_K = 256, OMG_NOALLOC_MAX_N = 5242880 };
+omg_status omg_rm_step_noalloc(int64_t N, int32_t k, const double *W, const double *w, const double *z,
+                               const double *r, double breakdown, void *hip_stream, double *Wk, double *r_new,
+                               double *coeff);
 /* The co-resident launch configurations of level l's persistent RM kernel:
  * host out[5*cap] (blocks, entries per thread, directions per exchange,
  * leader exchange, compute waves: 0 for the plain form, 3 or 4 for the

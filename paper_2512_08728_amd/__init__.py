@@ -114,7 +114,7 @@ EXPORTS = ["omg_default_options", "omg_grid_hierarchy", "omg_embedding", "omg_ge
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
            "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_get_step_counts", "omg_set_replay", "omg_bench_kernel",
            "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result", "omg_level_multi",
-           "omg_level_tuning", "omg_level_rm_step", "omg_level_rm_configs"]
+           "omg_level_tuning", "omg_level_rm_step", "omg_level_rm_configs", "omg_rm_step_noalloc"]
 MR_SPMV, MR_SMOOTHER, MR_COARSE = 0, 1, 2
 K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST, K_RMP, K_COPY = range(12)
 K_NAMES = ["spmv", "spmv32", "bj_sweep", "bj_sweep32", "mgs_step", "restrict", "prolong", "coarse_gemv",
@@ -164,6 +164,7 @@ def lib():
         L.omg_level_tuning.argtypes = [P, i32, P]
         L.omg_level_rm_step.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P]
         L.omg_level_rm_configs.argtypes = [P, i32, P, i32, P]
+        L.omg_rm_step_noalloc.argtypes = [ctypes.c_int64, i32, P, P, P, P, d, P, P, P, P]
         for name in EXPORTS:
             if name not in ("omg_default_options", "omg_destroy", "omg_strerror"):
                 getattr(L, name).restype = ctypes.c_int
@@ -448,6 +449,21 @@ class Solver:
     def set_replay(self, visits):
         v = np.ascontiguousarray(np.asarray(visits, dtype=np.int32).reshape(-1))
         _check(lib().omg_set_replay(self._h, v.ctypes.data if len(v) else None, len(v) // 2), "set_replay")
+
+
+def rm_step_noalloc(W, w, z, r, breakdown=1e-14, r_new=None):
+    """omg_rm_step_noalloc: one RM step on caller arrays with the library's
+    fixed scratch (no device allocation by the library). W: (k, N) CUDA
+    tensor or None; returns (Wk, r_new, betas, gamma, alpha)."""
+    import torch
+    k = 0 if W is None else W.shape[0]
+    N = w.shape[0]
+    Wk = torch.empty_like(w)
+    rn = torch.empty_like(w) if r_new is None else r_new
+    coeff = np.zeros(k + 2)
+    _check(lib().omg_rm_step_noalloc(N, k, None if W is None else _ptr(W), _ptr(w), _ptr(z), _ptr(r), breakdown,
+                                     _stream(), _ptr(Wk), _ptr(rn), coeff.ctypes.data), "rm_step_noalloc")
+    return Wk, rn, coeff[:k], coeff[k], coeff[k + 1]
 
 
 def solve_batched(solvers, bs_list, xs_list=None, tol=1e-10, nrhs=1):

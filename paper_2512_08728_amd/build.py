@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libomg.so")
 SOURCES = ["omg_kernels.hip", "omg_setup.hip", "omg_solve.hip", "omg_grad.hip", "omg_rm.hip", "omg_multi.hip",
-           "omg_batch.hip", "omg_schwarz.hip"]
+           "omg_batch.hip", "omg_schwarz.hip", "omg_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

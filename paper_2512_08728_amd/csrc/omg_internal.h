@@ -348,6 +348,11 @@ constexpr int kMaxRmConfigs = 96;
 int rm_persistent_candidates(int64_t N, RmConfig* out, int cap);
 bool rm_persistent_config(int64_t N, RmConfig* cfg);
 hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st);
+// the persistent kernel on vectors without a zero tail past N (entries >= N
+// neither read nor written; Zk may be null): its co-resident configuration
+// and launch
+bool rm_masked_config(int64_t N, RmConfig* cfg);
+hipError_t launch_rm_masked(const RmConfig& c, const RmArgs& args, hipStream_t st);
 // Reset L's exchange words to "empty" if configuration c lays them out
 // differently from the last launch on them (call before every launch).
 hipError_t prepare_slots(Level& L, const RmConfig& c, hipStream_t st);

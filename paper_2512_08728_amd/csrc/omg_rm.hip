@@ -213,7 +213,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int b
 constexpr int kPtrLds = 1024;
 
 // The RM of one vector set on G blocks; this block is block `bid` of them.
-template <int EPT, int B, bool LEAD>
+// MASK: the vectors have no zero tail past N (caller arrays): every access
+// of an entry >= N is skipped and such entries count as zero, and Zk may be
+// null (the raw direction is not stored).
+template <int EPT, int B, bool LEAD, bool MASK = false>
 __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int bid, double* sh,
                                         unsigned long long* ptab) {
     constexpr int SW = B + 1;
@@ -229,11 +232,13 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
     // its loads are all issued before the first store.
     const int toff = (int)t0 * 8;
     const int stride = (int)T * 8;
-    const int bytes = (int)((N + kVecPad) * 8);
+    const int bytes = (int)((MASK ? N : N + kVecPad) * 8);
     auto ld = [&](__amdgpu_buffer_rsrc_t r, int j) -> double {
+        if (MASK && t0 + j * T >= N) return 0.0;
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, toff, j * stride, 0));
     };
     auto st_all = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        if (MASK && t0 + j * T >= N) return;
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufData, v), r, toff, j * stride, 0);
     };
     auto st = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
@@ -242,15 +247,17 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
     double w[EPT], a[B][EPT], an[B][EPT];
     // w in registers; the raw direction z~ is stored as direction k
     {
-        const __amdgpu_buffer_rsrc_t rw = buffer_of(A.w, bytes), rz = buffer_of(A.z, bytes),
-                                     rk = buffer_of(A.Zk, bytes);
+        const __amdgpu_buffer_rsrc_t rw = buffer_of(A.w, bytes), rz = buffer_of(A.z, bytes);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             w[j] = ld(rw, j);
             an[0][j] = ld(rz, j);
         }
+        if (!MASK || A.Zk) { // uniform
+            const __amdgpu_buffer_rsrc_t rk = buffer_of(A.Zk, bytes);
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) st_all(rk, j, an[0][j]);
+            for (int j = 0; j < EPT; ++j) st_all(rk, j, an[0][j]);
+        }
     }
     for (int i = threadIdx.x; i < min(k, kPtrLds); i += blockDim.x) ptab[i] = (unsigned long long)A.Wp[i];
     __syncthreads();
@@ -416,6 +423,14 @@ __global__ __launch_bounds__(kThreads) void k_rm_blk(RmArgs A) {
     __shared__ double sh[kMaxVals * (kThreads / 64)];
     __shared__ unsigned long long ptab[kPtrLds];
     rm_body<EPT, B, LEAD>(A, gridDim.x, blockIdx.x, sh, ptab);
+}
+
+// The same on vectors without a zero tail (caller arrays).
+template <int EPT, int B, bool LEAD>
+__global__ __launch_bounds__(kThreads) void k_rm_masked(RmArgs A) {
+    __shared__ double sh[kMaxVals * (kThreads / 64)];
+    __shared__ unsigned long long ptab[kPtrLds];
+    rm_body<EPT, B, LEAD, true>(A, gridDim.x, blockIdx.x, sh, ptab);
 }
 
 // RM of several vector sets (columns of a batched solve, or independent
@@ -1094,6 +1109,53 @@ hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream
     RmArgs a = args;
     void* params[] = {&a};
     return hipLaunchKernel(f, dim3(G), dim3(rm_block_threads(c.cw)), params, 0, st);
+}
+
+// Masked plain-form kernels: MGS blocks of four directions, all-to-all exchange.
+static const void* pick_masked(int ept) {
+    switch (ept) {
+    case 1: return reinterpret_cast<const void*>(&k_rm_masked<1, 4, false>);
+    case 2: return reinterpret_cast<const void*>(&k_rm_masked<2, 4, false>);
+    case 4: return reinterpret_cast<const void*>(&k_rm_masked<4, 4, false>);
+    case 8: return reinterpret_cast<const void*>(&k_rm_masked<8, 4, false>);
+    case 10: return reinterpret_cast<const void*>(&k_rm_masked<10, 4, false>);
+    case 16: return reinterpret_cast<const void*>(&k_rm_masked<16, 4, false>);
+    case 20: return reinterpret_cast<const void*>(&k_rm_masked<20, 4, false>);
+    }
+    return nullptr;
+}
+
+// The co-resident configuration of the masked kernel for N entries: the
+// fewest entries per thread whose grid of at most kMaxRedBlocks blocks fits
+// at once (occupancy query; kernels that need scratch memory left out).
+bool rm_masked_config(int64_t N, RmConfig* cfg) {
+    int dev = 0, cus = 0;
+    if (N < 1 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return false;
+    for (int e : kEpts) {
+        const int64_t need = (N + (int64_t)kThreads * e - 1) / ((int64_t)kThreads * e);
+        if (need > kMaxRedBlocks) continue;
+        const void* f = pick_masked(e);
+        hipFuncAttributes fa;
+        int per_cu = 0;
+        if (!f || hipFuncGetAttributes(&fa, f) != hipSuccess || fa.localSizeBytes > 0) continue;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess || per_cu < 1)
+            continue;
+        if (need > (int64_t)per_cu * cus) continue;
+        *cfg = RmConfig{(int)need, e, 4, 0, 0};
+        return true;
+    }
+    return false;
+}
+
+hipError_t launch_rm_masked(const RmConfig& c, const RmArgs& args, hipStream_t st) {
+    const void* f = pick_masked(c.ept);
+    if (!f || c.B != 4 || c.lead || c.cw || (int64_t)c.G * kThreads * c.ept < args.N || c.G > kMaxRedBlocks)
+        return hipErrorInvalidValue;
+    RmArgs a = args;
+    void* params[] = {&a};
+    return hipLaunchKernel(f, dim3(c.G), dim3(kThreads), params, 0, st);
 }
 
 hipError_t launch_recon(int K, const double* hist, const double* gammas, const double* alphas, double* d,

@@ -130,6 +130,79 @@ def batched_bench(omg, synth, torch):
     return out
 
 
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def cpu_full_solve(omg, synth, torch, n=16, p=2, runs=3):
+    """Complete solves of a configuration the oracle finishes in seconds
+    (16^3 P2, 40,960 DOFs, two levels, the same field, sweeps, cycle and
+    tolerance as the headline): the FP64 oracle on all host cores (median of
+    `runs`) and on one thread, beside the GPU on the same configuration
+    (median of 5 after a warm-up)."""
+    import oracle
+    prob = synth.make_problem(n, p)
+    nu = synth.nu_sphere(n, n, n, prob.h)
+    b = synth.rhs(prob.n_dofs, 0)
+    cores = os.cpu_count()
+    oracle.set_threads(cores)
+    o = oracle.Oracle.from_sip(prob, nu, s_pre=2, s_post=2, omega=0.7)
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        o.solve(b, tol=1e-10)
+        times.append(time.perf_counter() - t0)
+    cyc = o.last_report["iters_fine"]
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.solve(b, tol=1e-10)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    grid = omg.Solver.make_grid(n, n, n, p, prob.n_levels, prob.h)
+    g = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), s_pre=2, s_post=2, omega=0.7)
+    bd = torch.tensor(b, device="cuda")
+    g.solve(bd, tol=1e-10)
+    gt = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.solve(bd, tol=1e-10)
+        torch.cuda.synchronize()
+        gt.append(time.perf_counter() - t0)
+    gcyc = g.last_report["iters_fine"]
+    g.close()
+    return {"workload": f"{n}^3 P{p} ({prob.n_dofs} DOFs), {prob.n_levels} levels, sphere r=0.3 nu 1:1000, "
+                        f"2+2 block-Jacobi, Alg. 2, tol 1e-10, b seed 0",
+            "nproc": cores, "oracle_cycles": cyc, "gpu_cycles": gcyc,
+            "oracle_all_cores": {"value": prob.n_dofs / median(times), "unit": "DOF/s", "cores": cores,
+                                 "s_median_of_3": round(median(times), 3)},
+            "oracle_1_thread": {"value": prob.n_dofs / t1, "unit": "DOF/s", "cores": 1, "s": round(t1, 3)},
+            "gpu": {"value": prob.n_dofs / median(gt), "unit": "DOF/s", "s_median_of_5": round(median(gt), 4)}}
+
+
+def cycle_sweep(omg, synth, torch):
+    """Finest-level cycles and level-1 behaviour of the headline solve's
+    configuration (P2, sphere r = 0.3, ratio 1000, 2+2 sweeps, Sec. 4.2
+    criteria, levels down to 8^3 or an odd side) over the mesh size."""
+    out = []
+    for n in (16, 24, 32, 48, 64):
+        prob = synth.make_problem(n, 2)
+        nu = synth.nu_sphere(n, n, n, prob.h)
+        grid = omg.Solver.make_grid(n, n, n, 2, prob.n_levels, prob.h)
+        g = omg.Solver.from_sip(grid, torch.tensor(nu, device="cuda"), s_pre=2, s_post=2, omega=0.7)
+        g.solve(torch.tensor(synth.rhs(prob.n_dofs, 0), device="cuda"), tol=1e-10)
+        v = g.visits()
+        l1 = v[v[:, 0] == 1][:, 1]
+        row = {"n": n, "levels": prob.n_levels, "dofs": prob.n_dofs, "cycles": g.last_report["iters_fine"],
+               "level1_mean_iters": round(float(l1.mean()), 2) if len(l1) else None,
+               "level1_at_cap": round(float((l1 == 20).mean()), 3) if len(l1) else None}
+        log(f"cycle sweep: {row}")
+        out.append(row)
+        g.close()
+    return out
+
+
 def cpu_baseline(prob, nu, b, gpu_cycles, cycles=4):
     """The FP64 oracle on the host cores: the first `cycles` cycles of the
     same solve, scaled to DOF/s of the full solve by the GPU's cycle count."""
@@ -161,6 +234,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision solves and the other Table 1 configurations")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--cycle-sweep", action="store_true",
+                    help="also report finest-level cycles over mesh sizes 16..64")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the library's plain copy kernel on one finest-level vector "
                          "(reference for traffic counters)")
@@ -225,9 +300,10 @@ def main():
         return n_l, avg_ms, alg
 
     cand = []
-    if counts[omg.K_RMP, 0] > 0:
-        n_l, avg_ms, _ = probe(omg.K_RMP, 0)
-        cand.append((counts[omg.K_RMP, 0] * avg_ms, omg.K_RMP, 0, avg_ms))
+    for l in range(prob.n_levels):  # the persistent RM of every level, timed live over a solve
+        if counts[omg.K_RMP, l] > 0:
+            n_l, avg_ms, _ = probe(omg.K_RMP, l)
+            cand.append((counts[omg.K_RMP, l] * avg_ms, omg.K_RMP, l, avg_ms))
     for kind in (omg.K_SPMV, omg.K_BJ, omg.K_MGS, omg.K_BJFIRST, omg.K_RMFIN, omg.K_RESTRICT, omg.K_PROLONG,
                  omg.K_COARSE):
         for l in range(prob.n_levels):
@@ -239,7 +315,7 @@ def main():
                 continue
             cand.append((counts[kind, l] * ms, kind, l, ms))
     cand.sort(reverse=True)
-    breakdown = {f"{omg.K_NAMES[k]}@L{l}": round(float(t), 2) for t, k, l, _ in cand[:10]}
+    breakdown = {f"{omg.K_NAMES[k]}@L{l}": round(float(t), 2) for t, k, l, _ in cand[:14]}
     log(f"estimated ms per solve by kernel: {breakdown}")
     roof = None
     for _, kind, l, _ in cand:
@@ -257,7 +333,7 @@ def main():
     # SpMV and block-Jacobi sweep against the HBM peak (isolated launches,
     # algorithmic bytes: stored blocks, column indices, vectors once)
     hbm_kernels = {}
-    for kind in (omg.K_SPMV, omg.K_BJ):
+    for kind in (omg.K_SPMV, omg.K_BJ, omg.K_SPMV32, omg.K_BJ32):
         for l in range(min(2, prob.n_levels - 1)):
             try:
                 ms, by = s.bench_kernel(kind, l, reps=10)
@@ -350,10 +426,13 @@ def main():
 
     batched = None if args.no_batched else batched_bench(omg, synth, torch)
 
-    cpu = None
+    cpu = cpu_full = None
     if not args.no_cpu:
         cpu = cpu_baseline(prob, nu, b_host, rep["iters_fine"])
         log(f"cpu: {cpu}")
+        cpu_full = cpu_full_solve(omg, synth, torch)
+        log(f"cpu full solve: {cpu_full}")
+    sweep = cycle_sweep(omg, synth, torch) if args.cycle_sweep else None
 
     out = {
         "metric": "DOF/s solved to rel. residual 1e-10 (FP64 vs mixed); SpMV/smoother HBM GB/s",
@@ -381,6 +460,8 @@ def main():
         "roofline": roof,
         "kernel_ms_per_solve": breakdown,
         "cpu_baseline": cpu,
+        "cpu_full_solve": cpu_full,
+        "cycle_sweep": sweep,
     }
     print(json.dumps(out), flush=True)
     s.close()

@@ -96,6 +96,8 @@ def lib():
         L.oracle_default_opts.restype = None
         L.oracle_nbasis.argtypes = [i]
         L.oracle_num_threads.argtypes = []
+        L.oracle_set_threads.argtypes = [i]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -378,3 +380,8 @@ def element(p: int, h: float, penalty_c: float = 4.0):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's row-parallel loops from now on."""
+    lib().oracle_set_threads(int(n))

@@ -1698,6 +1698,15 @@ int oracle_element(int p, double h, double penalty_c, double *S, double *F, doub
     return OR_OK;
 }
 
+/* Threads of the row-parallel loops for the following calls (n >= 1). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

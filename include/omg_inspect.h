@@ -48,7 +48,7 @@ omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
  * fp32 = 1 uses the FP32 operator copies (inputs rounded to FP32, FP32
  * arithmetic, results widened to FP64). OMG_EUNSUPPORTED for bs > 16. */
 enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
-/* Launch configurations the autotuners chose on a level, host shapes[17]:
+/* Launch configurations the autotuners chose on a level, host shapes[18]:
  * [0..11] the multi-right-hand-side kernels (tuned on the first batched
  * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
  * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..5 is
@@ -57,7 +57,8 @@ enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
  * residual-minimisation kernel (tuned at setup): blocks, vector entries per
  * thread, directions per grid exchange, exchange form (0 all-to-all, 1
  * leader block), compute waves per block of the exchange-wave form (0:
- * plain form); -1 if the level does not use it. */
+ * plain form), exchanges kept in flight by the lagged form (0: not lagged);
+ * -1 if the level does not use it. */
 omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
 omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
                            const double *X, const double *B, double *Y);
@@ -65,9 +66,9 @@ omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrh
  * persistent kernel on caller data: the vectors are flat device arrays of
  * N_l entries (RM has no cell structure); W holds k orthonormal directions
  * as rows of a k x N_l array; cfg (host, nullable) = (blocks, entries per
- * thread, directions per exchange, leader exchange, compute waves) selects
- * one of the co-resident configurations of omg_level_rm_configs (NULL: the
- * tuned one).
+ * thread, directions per exchange, leader exchange, compute waves, lag)
+ * selects one of the co-resident configurations of omg_level_rm_configs
+ * (NULL: the tuned one).
  * Outputs: Wk (the new orthonormal direction), r_new, and host
  * coeff[k + 2] = (beta_0..beta_{k-1}, gamma, alpha). The level's own work
  * storage is overwritten. OMG_EUNSUPPORTED if the level does not use the
@@ -98,10 +99,19 @@ omg_status omg_rm_step_noalloc(int64_t N, int32_t k, const double *W, const doub
                                const double *r, double breakdown, void *hip_stream, double *Wk, double *r_new,
                                double *coeff);
 /* The co-resident launch configurations of level l's persistent RM kernel:
- * host out[5*cap] (blocks, entries per thread, directions per exchange,
+ * host out[6*cap] (blocks, entries per thread, directions per exchange,
  * leader exchange, compute waves: 0 for the plain form, 3 or 4 for the
  * exchange-wave form, where one more wave per block performs the grid
- * exchanges), their count in *n (out nullable to query the count). */
+ * exchanges; lag: 1 or 2 for the lagged form, which takes the dot products
+ * of each block of directions against w before the previous 1 or 2 blocks'
+ * updates and corrects them with stored Gram entries, so that as many
+ * exchanges are in flight), their count in *n (out nullable to query the
+ * count). */
+/* Make level l of this solver use one of its co-resident RM configurations
+ * (cfg[6] as in omg_level_rm_configs, host) instead of the tuned one, for the
+ * following solves; OMG_EINVAL if cfg is not among them, OMG_EUNSUPPORTED if
+ * the level does not use the persistent kernel. */
+omg_status omg_level_set_rm_config(omg_solver *s, int32_t level, const int32_t *cfg);
 omg_status omg_level_rm_configs(const omg_solver *s, int32_t level, int32_t *out, int32_t cap, int32_t *n);
 /* Stored directions of level l after the last solve (device, cell-major,
  * [k][N] each); W or Z nullable. */

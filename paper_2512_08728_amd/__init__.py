@@ -114,7 +114,8 @@ EXPORTS = ["omg_default_options", "omg_grid_hierarchy", "omg_embedding", "omg_ge
            "omg_level_spmv", "omg_level_smoother", "omg_level_restrict", "omg_level_prolong", "omg_coarse_solve",
            "omg_get_dirs", "omg_get_visits", "omg_get_trace", "omg_get_step_counts", "omg_set_replay", "omg_bench_kernel",
            "omg_get_kernel_counts", "omg_probe_kernel", "omg_probe_result", "omg_level_multi",
-           "omg_level_tuning", "omg_level_rm_step", "omg_level_rm_configs", "omg_rm_step_noalloc"]
+           "omg_level_tuning", "omg_level_rm_step", "omg_level_rm_configs", "omg_rm_step_noalloc",
+           "omg_level_set_rm_config"]
 MR_SPMV, MR_SMOOTHER, MR_COARSE = 0, 1, 2
 K_SPMV, K_SPMV32, K_BJ, K_BJ32, K_MGS, K_RESTRICT, K_PROLONG, K_COARSE, K_RMFIN, K_BJFIRST, K_RMP, K_COPY = range(12)
 K_NAMES = ["spmv", "spmv32", "bj_sweep", "bj_sweep32", "mgs_step", "restrict", "prolong", "coarse_gemv",
@@ -164,6 +165,7 @@ def lib():
         L.omg_level_tuning.argtypes = [P, i32, P]
         L.omg_level_rm_step.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P]
         L.omg_level_rm_configs.argtypes = [P, i32, P, i32, P]
+        L.omg_level_set_rm_config.argtypes = [P, i32, P]
         L.omg_rm_step_noalloc.argtypes = [ctypes.c_int64, i32, P, P, P, P, d, P, P, P, P]
         for name in EXPORTS:
             if name not in ("omg_default_options", "omg_destroy", "omg_strerror"):
@@ -354,8 +356,8 @@ class Solver:
     def level_tuning(self, l):
         """Autotuned launch configurations of level l: (multi-RHS shapes
         [op][fp32][two tiles], (RM blocks, entries per thread, MGS block, leader exchange,
-        compute waves of the exchange-wave form or 0))."""
-        out = np.zeros(17, dtype=np.int32)
+        compute waves of the exchange-wave form or 0, exchanges in flight of the lagged form or 0))."""
+        out = np.zeros(18, dtype=np.int32)
         _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
         return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:])
 
@@ -363,9 +365,14 @@ class Solver:
         """Co-resident launch configurations of level l's persistent RM kernel."""
         n = ctypes.c_int32()
         _check(lib().omg_level_rm_configs(self._h, l, None, 0, ctypes.byref(n)), "rm_configs")
-        out = np.zeros(5 * max(n.value, 1), dtype=np.int32)
+        out = np.zeros(6 * max(n.value, 1), dtype=np.int32)
         _check(lib().omg_level_rm_configs(self._h, l, out.ctypes.data, n.value, ctypes.byref(n)), "rm_configs")
-        return [tuple(int(v) for v in out[5 * i:5 * i + 5]) for i in range(n.value)]
+        return [tuple(int(v) for v in out[6 * i:6 * i + 6]) for i in range(n.value)]
+
+    def set_rm_config(self, l, cfg):
+        """Use this co-resident RM configuration (a tuple from rm_configs) on level l."""
+        c = np.ascontiguousarray(np.asarray(cfg, dtype=np.int32))
+        _check(lib().omg_level_set_rm_config(self._h, l, c.ctypes.data), "set_rm_config")
 
     def rm_step(self, l, W, w, z, r, cfg=None):
         """One RM step on flat vectors (see omg_level_rm_step): returns

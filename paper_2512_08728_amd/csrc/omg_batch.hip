@@ -258,8 +258,14 @@ omg_status refresh_rm_table(Group& g, int l) {
 }
 
 // Launch configuration of member c's RM in a batched launch at level l.
+// The multi-column kernel has the plain exchange form only (no exchange wave,
+// no lag): a tuned lagged or exchange-wave configuration contributes its
+// grid, entries per thread, block and exchange form.
 inline RmConfig member_config(const Group& g, int c, int l) {
-    return g.shared ? g.P->lev[l].rmc_multi : g.col[c]->lev[l].rmc;
+    RmConfig r = g.shared ? g.P->lev[l].rmc_multi : g.col[c]->lev[l].rmc;
+    r.cw = 0;
+    r.lag = 0;
+    return r;
 }
 
 // RM of the active persistent members in multi-column launches: members with
@@ -852,6 +858,7 @@ extern "C" omg_status omg_level_tuning(const omg_solver* s, int32_t level, int32
     shapes[q++] = L.persist ? L.rmc.B : -1;
     shapes[q++] = L.persist ? L.rmc.lead : -1;
     shapes[q++] = L.persist ? L.rmc.cw : -1;
+    shapes[q++] = L.persist ? L.rmc.lag : -1;
     return OMG_OK;
 }
 

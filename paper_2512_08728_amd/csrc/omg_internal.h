@@ -22,9 +22,14 @@ constexpr int kThreads = 256;
 constexpr int64_t kVecPad = 32 * kThreads;
 constexpr int kMaxRedBlocks = 1024;
 // largest number of stored directions per grid-wide exchange in the
-// persistent RM kernel, and the stride of the stored intra-block Gram entries
+// persistent RM kernel; the lagged form keeps up to kRmLagMax exchanges in
+// flight. Every stored direction j keeps its dots with the directions just
+// before it: gram[j * kGramStride + d - 1] = W_j . W_{j-d}, d = 1 ..
+// kGramStride (the lagged form with 4 directions per exchange and two
+// exchanges in flight needs 4 * 2 + 3 of them).
 constexpr int kRmBlock = 4;
-constexpr int kGramStride = kRmBlock - 1;
+constexpr int kRmLagMax = 2;
+constexpr int kGramStride = kRmBlock * kRmLagMax + kRmBlock - 1;
 // right-hand sides advanced together by the batched solve (two 16-wide
 // matrix-core tiles), and the pointers of their vectors passed by value
 constexpr int kMaxCols = 32;
@@ -65,7 +70,17 @@ struct RmConfig {
     int B = 1;    // MGS directions resolved per grid exchange
     int lead = 0; // exchange form: 0 all-to-all, 1 leader block
     int cw = 0;   // compute waves per block of the exchange-wave form (0: plain form)
+    int lag = 0;  // lagged form: exchanges in flight (1, 2; 0: not lagged)
 };
+// Exchange phases of one launch with k stored directions: one per MGS block of
+// B directions, then the final one (every form).
+// Words per block of a configuration's exchanges and its slot sets.
+inline int rm_slot_words(const RmConfig& c) {
+    if (!c.lag) return c.B + 1;
+    const int held = c.B == 1 ? c.lag : c.lag + 1; // as the lagged kernel's final exchange
+    return 2 + held * c.B > c.B + 1 ? 2 + held * c.B : c.B + 1;
+}
+inline int rm_slot_sets(const RmConfig& c) { return c.lag == 2 ? 8 : c.lag == 1 ? 4 : 2; }
 // Grid exchanges (phases) of one persistent RM launch with k stored
 // directions: one per MGS block of B directions, then one for the norm of
 // the orthogonalised vector, its dot product with r and its Gram entries.
@@ -90,6 +105,12 @@ inline int cycle_fork_level(const omg_options& o) {
 // exchange words: two sets of [kMaxRedBlocks][kRmBlock + 1] block words, then
 // two sets of kRmBlock + 1 total words (leader form)
 constexpr size_t kRmSlotWords = 2 * (size_t)kMaxRedBlocks * (kRmBlock + 1) + 2 * (kRmBlock + 1);
+// the lagged form: up to eight sets of up to (kRmLagMax + 1) kRmBlock + 1
+// words per block, then eight sets of totals
+constexpr int kRmLagSets = 8;
+constexpr int kRmLagWords = (kRmLagMax + 1) * kRmBlock + 2;
+constexpr size_t kRmSlotWordsLag = (size_t)kRmLagSets * kMaxRedBlocks * kRmLagWords + kRmLagSets * kRmLagWords;
+constexpr size_t kRmSlotWordsMax = kRmSlotWordsLag > kRmSlotWords ? kRmSlotWordsLag : kRmSlotWords;
 
 // Per-column state of the multi-column RM kernel (device table entry).
 struct RmCol {
@@ -189,7 +210,7 @@ struct Level {
     // layout (blocks, words per block, exchange form) of the last launch on
     // xslots: a stale word is only guaranteed to carry a foreign tag while
     // the layout stays the same, so the words are reset when it changes
-    int slot_G = -1, slot_SW = -1, slot_lead = -1;
+    int slot_G = -1, slot_SW = -1, slot_lead = -1, slot_sets = -1;
     unsigned long long phase = 0;      // next exchange phase of this level (host counter)
     // implicit search directions (persistent levels): raw directions + MGS coefficients
     double* hist = nullptr;            // packed beta rows, ucap*(ucap-1)/2
@@ -198,6 +219,7 @@ struct Level {
     int Grn = 1;                       // number of ||r||^2 partials written by the last update
     int restarted = 0;                 // the current level solve restarted (m_max): x holds the
                                        // share of the directions dropped at the restarts
+    double *rs = nullptr, *xs = nullptr; // snapshot of r and x before a speculative iteration
 };
 
 struct Trace {
@@ -242,6 +264,16 @@ struct omg_solver {
     // tests of Sec. 4.2 read); appended under vnorm_mu (the adaptive cycle's
     // coarse thread logs its visits too)
     std::vector<double> vnorm;
+    // residual norms computed during a solve, written by the device into mapped
+    // host memory at consecutive positions (vlog_pos); a norm is read when a
+    // level test needs it (after an event recorded behind it), and the log
+    // entries above are filled from these positions when the solve ends
+    double* vlog_host = nullptr;
+    double* vlog_dev = nullptr;
+    int64_t vlog_pos = 0;
+    std::vector<hipEvent_t> vlog_ev;               // ring of events, one per position modulo its size
+    std::vector<std::pair<size_t, int64_t>> vfix;  // (index into vnorm, position)
+    std::vector<double> vlog_over;                 // values of positions past the buffer
     int mode32 = 0;                    // 0 FP64, 1 FP32 everywhere, 2 FP32 except finest-level RM
     int64_t kcount[OMG_K_COUNT][OMG_MAX_LEVELS] = {};  // launches per kernel kind and level
     int64_t nnzb_level[OMG_MAX_LEVELS] = {};           // stored (non-padding) blocks per level
@@ -304,6 +336,8 @@ hipError_t launch_finish_norm(int G, const double* part, double* out, hipStream_
 hipError_t launch_level_init(int64_t N, int G, const double* b, double* x, double* r, double* part,
                              hipStream_t st);
 hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st);
+hipError_t launch_snap(double* dr, const double* sr, int64_t N, double* dx, const double* sx, int64_t Nx, double* ds,
+                       const double* ss, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, int64_t N, hipStream_t st);
 hipError_t launch_stream_copy(double* dst, const double* src, int64_t N, hipStream_t st);
 hipError_t launch_axpy(double* y, double a, const double* x, int64_t N, hipStream_t st);
@@ -344,7 +378,7 @@ int rm_multi_capacity(int ept, int B, int lead);
 hipError_t launch_rm_multi(int ept, int B, int lead, const RmMulti& M, hipStream_t st);
 
 // co-resident configurations for N entries, most preferred first; returns the count
-constexpr int kMaxRmConfigs = 96;
+constexpr int kMaxRmConfigs = 192;
 int rm_persistent_candidates(int64_t N, RmConfig* out, int cap);
 bool rm_persistent_config(int64_t N, RmConfig* cfg);
 hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st);

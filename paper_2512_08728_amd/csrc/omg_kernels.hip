@@ -372,6 +372,30 @@ __global__ __launch_bounds__(kThreads) void k_restrict(int fn, int cn, const int
     restrict_cell<BS, MT>(I, fn, cn, dn_ptr, dn, E, r, rc);
 }
 
+// The same with one thread per (coarse cell, component): BS times the
+// parallelism of k_restrict (the coarse levels have only a few thousand
+// cells), each output summed in k_restrict's order.
+template <int BS, typename MT>
+__global__ __launch_bounds__(kThreads) void k_restrict_rows(int fn, int cn, const int* __restrict__ dn_ptr,
+                                                            const int* __restrict__ dn, const MT* __restrict__ E,
+                                                            const double* __restrict__ r, double* __restrict__ rc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)cn * BS) return;
+    const int c = (int)(e / cn), I = (int)(e % cn);
+    MT out = MT(0);
+    const int q1 = dn_ptr[I + 1];
+    for (int q = dn_ptr[I]; q < q1; ++q) {
+        const int w = dn[q];
+        const int K = w >> 3, s = w & 7;
+        const MT* Es = E + s * BS * BS + c;
+        MT a = MT(0);
+#pragma unroll
+        for (int m = 0; m < BS; ++m) a = fma(Es[m * BS], (MT)r[(int64_t)m * fn + K], a);
+        out += a;
+    }
+    rc[(int64_t)c * cn + I] = (double)out;
+}
+
 // Prolongation z = P z_c: z_K = E_{slot(K)} z_{parent(K)}.
 template <int BS, typename MT>
 __device__ __forceinline__ void prolong_cell(int K, int fn, int cn, const int* __restrict__ up,
@@ -895,13 +919,13 @@ hipError_t launch_level_init_grouped(InitTable& T, const int* G, hipStream_t st)
 
 hipError_t launch_restrict(const Level& F, const Level& C, int bs, bool fp32, const double* E, const float* E32,
                            const double* r, double* rc, hipStream_t st) {
-    dim3 grid(cdiv(C.n, kThreads)), block(kThreads);
+    dim3 grid(cdiv((int64_t)C.n * bs, kThreads)), block(kThreads);
     if (fp32) {
-        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, float>), grid, block, 0, st, F.n, C.n, C.dn_ptr,
-                                               C.dn, E32, r, rc));
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict_rows<BSV, float>), grid, block, 0, st, F.n, C.n,
+                                               C.dn_ptr, C.dn, E32, r, rc));
     } else {
-        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict<BSV, double>), grid, block, 0, st, F.n, C.n, C.dn_ptr,
-                                               C.dn, E, r, rc));
+        OMG_BS_DISPATCH(bs, hipLaunchKernelGGL((k_restrict_rows<BSV, double>), grid, block, 0, st, F.n, C.n,
+                                               C.dn_ptr, C.dn, E, r, rc));
     }
     return hipGetLastError();
 }
@@ -995,6 +1019,24 @@ static inline int stream_blocks(int64_t N) {
     if (b < 1) b = 1;
     if (b > 4096) b = 4096;
     return (int)b;
+}
+
+// Snapshot / restore of a level's iteration state in one launch: r (N
+// entries), x (Nx entries, Nx may be 0) and one scalar.
+__global__ void k_snap(double* __restrict__ dr, const double* __restrict__ sr, int64_t N, double* __restrict__ dx,
+                       const double* __restrict__ sx, int64_t Nx, double* __restrict__ ds,
+                       const double* __restrict__ ss) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t e = t; e < N; e += stride) dr[e] = sr[e];
+    for (int64_t e = t; e < Nx; e += stride) dx[e] = sx[e];
+    if (t == 0) *ds = *ss;
+}
+hipError_t launch_snap(double* dr, const double* sr, int64_t N, double* dx, const double* sx, int64_t Nx, double* ds,
+                       const double* ss, hipStream_t st) {
+    hipLaunchKernelGGL(k_snap, dim3(stream_blocks(std::max(N, Nx))), dim3(kThreads), 0, st, dr, sr, N, dx, sx, Nx,
+                       ds, ss);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(double* dst, const double* src, int64_t N, hipStream_t st) {

@@ -326,7 +326,8 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
             double bt = 0.0;
             if (t < bb) {
                 bt = tot[t];
-                for (int m = 0; m < t; ++m) bt = fma(-A.gram[(int64_t)(j0 + t) * kGramStride + m], beta[m], bt);
+                for (int m = 0; m < t; ++m)
+                    bt = fma(-A.gram[(int64_t)(j0 + t) * kGramStride + (t - m - 1)], beta[m], bt);
             }
             beta[t] = bt;
         }
@@ -411,8 +412,9 @@ __device__ __forceinline__ void rm_body(const RmArgs& A, const int G, const int 
         if (bid == 0) {
             A.alphas[k] = alpha;
             A.gammas[k] = gamma;
-            for (int t = 0; t < B - 1; ++t)
-                A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? gamma * tot[2 + t] : 0.0;
+            // W_k . W_{k-d} = gamma (w . a[gk-d]) for the gk earlier directions of its block
+            for (int d = 1; d <= kGramStride; ++d)
+                A.gram[(int64_t)k * kGramStride + d - 1] = (d <= gk) ? gamma * tot[2 + gk - d] : 0.0;
             if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
         }
     }
@@ -431,6 +433,310 @@ __global__ __launch_bounds__(kThreads) void k_rm_masked(RmArgs A) {
     __shared__ double sh[kMaxVals * (kThreads / 64)];
     __shared__ unsigned long long ptab[kPtrLds];
     rm_body<EPT, B, LEAD, true>(A, gridDim.x, blockIdx.x, sh, ptab);
+}
+
+// ---------------------------------------------------------------------------
+// Lagged form. The exchange of an MGS block's dot products is the latency
+// that bounds the forms above: block b's dots need w after block b-1's
+// update, so every exchange is waited for before the next block's dots. Here
+// the dots of block s are taken against w as it stands L blocks earlier (w
+// updated through block s-L-1) and published at once; the exchange of block
+// s-L, published L steps ago, is collected after that, so L exchanges are in
+// flight while the next direction blocks stream in. The exact MGS
+// coefficients follow from the lagged dots with the stored Gram entries of
+// the directions in between (the MGS recursion in exact arithmetic, as in
+// low-synchronisation Gram-Schmidt, Swirydowicz et al., Numer. Linear Algebra
+// Appl. 2021):
+//   beta_j = W_j . w_{(s-L)} - sum_{m = (s-L) B}^{j-1} (W_j . W_m) beta_m.
+// Exchange words rotate over S sets: a block publishes phase s having
+// collected phase s-L-1, so every block has read phase s-2L-2 or older when a
+// set is reused after S >= 2L+2 phases; with S = 4 (L = 1) or 8 (L = 2) the
+// reused set's stale words carry a different phase tag (mod 3).
+template <int SW, int S>
+__device__ __forceinline__ void publish_lag(unsigned long long* slots, int G, int bid, unsigned long long g,
+                                            const double* v, int nw) {
+    if (threadIdx.x == 0) {
+        unsigned long long* p = slots + ((g % S) * (unsigned long long)G + bid) * SW;
+        const unsigned tag = (unsigned)(g % 3);
+        for (int i = 0; i < SW; ++i)
+            __hip_atomic_store(p + i, tag_pack(i < nw ? v[i] : 0.0, tag), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Phase g's totals for the lagged form, in either exchange form (see
+// collect): set g % S of the block words, totals after the S sets.
+template <int SW, bool LEAD, int S>
+__device__ __forceinline__ void collect_lag(unsigned long long* slots, int G, int bid, unsigned long long g, int nw,
+                                            double* out, double* sh, unsigned* abort_flag) {
+    const unsigned tag = (unsigned)(g % 3);
+    const unsigned long long* base = slots + (g % S) * (unsigned long long)G * SW;
+    unsigned long long* tot = slots + (unsigned long long)S * kMaxRedBlocks * SW + (g % S) * SW;
+    double v[SW];
+#pragma unroll
+    for (int w = 0; w < SW; ++w) v[w] = 0.0;
+    if (!LEAD || bid == 0) {
+        for (int i = threadIdx.x; i < G; i += blockDim.x) {
+#pragma unroll
+            for (int w = 0; w < SW; ++w)
+                if (w < nw) v[w] += tag_value(wait_word(base + (unsigned long long)i * SW + w, tag, abort_flag));
+        }
+        bsum_n<SW>(v, nw, sh);
+        if (LEAD) {
+            if (threadIdx.x == 0)
+                for (int w = 0; w < SW; ++w)
+                    __hip_atomic_store(tot + w, tag_pack(w < nw ? v[w] : 0.0, tag), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int w = 0; w < SW; ++w) v[w] = tag_value(tag_pack(v[w], tag));
+        }
+    } else {
+        if (threadIdx.x < nw) sh[threadIdx.x] = tag_value(wait_word(tot + threadIdx.x, tag, abort_flag));
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < SW; ++w)
+            if (w < nw) v[w] = sh[w];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int w = 0; w < SW; ++w)
+        if (w < nw) out[w] = v[w];
+}
+
+// Direction blocks held after their dots for the updates: L for one
+// direction per block; L + 1 otherwise, so that the dots of a new direction
+// with every direction a later lagged step corrects for are at hand.
+template <int B, int L>
+constexpr int lag_hold() { return B == 1 ? L : L + 1; }
+template <int B, int L>
+constexpr int lag_words() { return (2 + lag_hold<B, L>() * B) > (B + 1) ? 2 + lag_hold<B, L>() * B : B + 1; }
+template <int L>
+constexpr int lag_sets() { return L == 2 ? 8 : 4; }
+static_assert(lag_words<kRmBlock, kRmLagMax>() <= kRmLagWords, "lag words");
+
+template <int EPT, int B, int L, bool LEAD>
+__device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const int bid, double* sh,
+                                            unsigned long long* ptab) {
+    constexpr int H = lag_hold<B, L>();
+    constexpr int SW = lag_words<B, L>();
+    constexpr int S = lag_sets<L>();
+    const int64_t T = (int64_t)G * blockDim.x;
+    const int64_t t0 = (int64_t)bid * blockDim.x + threadIdx.x;
+    const int64_t N = A.N;
+    const int k = A.k;
+    const int toff = (int)t0 * 8;
+    const int stride = (int)T * 8;
+    const int bytes = (int)((N + kVecPad) * 8);
+    auto ld = [&](__amdgpu_buffer_rsrc_t r, int j) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, toff, j * stride, 0));
+    };
+    auto st_all = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufData, v), r, toff, j * stride, 0);
+    };
+    auto st = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
+        if (t0 + j * T < N) st_all(r, j, v);
+    };
+    // w; old[h]: the block finished h + 1 steps ago (awaiting its update, or
+    // held for the new direction's Gram dots); cur: this step's block; nxt:
+    // the next block (or r) streaming in
+    double w[EPT], old[H][B][EPT], cur[B][EPT], nxt[B][EPT];
+    {
+        const __amdgpu_buffer_rsrc_t rw = buffer_of(A.w, bytes), rz = buffer_of(A.z, bytes),
+                                     rk = buffer_of(A.Zk, bytes);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            w[j] = ld(rw, j);
+            cur[0][j] = ld(rz, j);
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) st_all(rk, j, cur[0][j]);
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) old[h][t][j] = 0.0;
+    for (int i = threadIdx.x; i < min(k, kPtrLds); i += blockDim.x) ptab[i] = (unsigned long long)A.Wp[i];
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t rr = buffer_of(A.r, bytes);
+    const int nblk = (k + B - 1) / B;
+    // block blk (zeros past k), or r when blk == nblk
+    auto load_block = [&](double (&dst)[B][EPT], int blk) {
+        if (blk == nblk) {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) dst[0][j] = ld(rr, j);
+            return;
+        }
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const int j = blk * B + t;
+            if (j < k) { // uniform
+                const __amdgpu_buffer_rsrc_t rt =
+                    buffer_of(j < kPtrLds ? (const void*)ptab[j] : (const void*)A.Wp[j], bytes);
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) dst[t][q] = ld(rt, q);
+            } else {
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) dst[t][q] = 0.0;
+            }
+        }
+    };
+    unsigned long long g0 = A.g0;
+    double nin2 = 0.0;
+    double bwin[L][B]; // beta of the L blocks before the one being finished (bwin[0]: the latest)
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int t = 0; t < B; ++t) bwin[i][t] = 0.0;
+    // collect block b2's dots, form its MGS coefficients and update w with blk
+    auto finish_block = [&](int b2, const double (&blk)[B][EPT]) {
+        double tot[SW];
+        collect_lag<SW, LEAD, S>(A.slots, G, bid, g0 + b2, b2 == 0 ? B + 1 : B, tot, sh, A.abort_flag);
+        if (b2 == 0) nin2 = tot[B];
+        const int j0 = b2 * B, bb = min(B, k - j0);
+        double beta[B];
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            double bt = 0.0;
+            if (t < bb) {
+                const int64_t gj = (int64_t)(j0 + t) * kGramStride;
+                bt = tot[t];
+#pragma unroll
+                for (int m = 0; m < t; ++m) bt = fma(-A.gram[gj + (t - m - 1)], beta[m], bt);
+                // directions of the L blocks before: W_{j0-e}, e = 1 .. L B
+#pragma unroll
+                for (int e = 1; e <= L * B; ++e)
+                    if (j0 - e >= 0) bt = fma(-A.gram[gj + t + e - 1], bwin[(e - 1) / B][B - 1 - (e - 1) % B], bt);
+            }
+            beta[t] = bt;
+        }
+        if (bid == 0 && threadIdx.x == 0)
+            for (int t = 0; t < bb; ++t) A.hist[(int64_t)k * (k - 1) / 2 + j0 + t] = beta[t];
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) w[j] = fma(-beta[t], blk[t][j], w[j]);
+#pragma unroll
+        for (int i = L - 1; i > 0; --i)
+#pragma unroll
+            for (int t = 0; t < B; ++t) bwin[i][t] = bwin[i - 1][t];
+#pragma unroll
+        for (int t = 0; t < B; ++t) bwin[0][t] = beta[t];
+    };
+    if (nblk > 0) load_block(nxt, 0);
+    for (int s = 0; s < nblk; ++s) {
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) cur[t][j] = nxt[t][j];
+        load_block(nxt, s + 1);  // the next block, or r after the last
+        double vals[SW];
+#pragma unroll
+        for (int i = 0; i < SW; ++i) vals[i] = 0.0;
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            double d = 0.0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) d = fma(cur[t][j], w[j], d);
+            vals[t] = d;
+        }
+        if (s == 0) {
+            double s_in = 0.0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) s_in = fma(w[j], w[j], s_in);
+            vals[B] = s_in;
+        }
+        bsum_n<SW>(vals, s == 0 ? B + 1 : B, sh);
+        publish_lag<SW, S>(A.slots, G, bid, g0 + s, vals, s == 0 ? B + 1 : B);
+        if (s >= L) finish_block(s - L, old[L - 1]);
+#pragma unroll
+        for (int h = H - 1; h > 0; --h)
+#pragma unroll
+            for (int t = 0; t < B; ++t)
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) old[h][t][j] = old[h - 1][t][j];
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) old[0][t][j] = cur[t][j];
+    }
+    if (nblk == 0) load_block(nxt, 0); // r
+    // drain: the last min(L, nblk) blocks, oldest first (old[h] = block nblk-1-h)
+#pragma unroll
+    for (int h = L - 1; h >= 0; --h)
+        if (nblk - 1 - h >= 0) finish_block(nblk - 1 - h, old[h]);
+    // the orthogonalised w: ||w||^2, w.r and its dots with the held directions
+    // (old[h][t] = direction (nblk-1-h) B + t)
+    double vals[SW];
+    {
+        double s2 = 0.0, q = 0.0;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            s2 = fma(w[j], w[j], s2);
+            q = fma(w[j], nxt[0][j], q);
+        }
+        vals[0] = s2;
+        vals[1] = q;
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                double d = 0.0;
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) d = fma(old[h][t][j], w[j], d);
+                vals[2 + h * B + t] = d;
+            }
+#pragma unroll
+        for (int i = 2 + H * B; i < SW; ++i) vals[i] = 0.0;
+    }
+    bsum_n<SW>(vals, SW, sh);
+    publish_lag<SW, S>(A.slots, G, bid, g0 + nblk, vals, SW);
+    double tot[SW];
+    collect_lag<SW, LEAD, S>(A.slots, G, bid, g0 + nblk, SW, tot, sh, A.abort_flag);
+    const double nout2 = tot[0], wr = tot[1];
+    if (k == 0) nin2 = nout2;
+    const double nin = sqrt(nin2), nout = sqrt(nout2);
+    const bool keep = nout > A.breakdown * nin; // false for NaN and for nout == 0
+    const double gamma = keep ? 1.0 / nout : 0.0;
+    const double alpha = gamma * wr;
+    const __amdgpu_buffer_rsrc_t rwk = buffer_of(A.Wk, bytes);
+    double s_r = 0.0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const double wk = w[j] * gamma;
+        st(rwk, j, wk);
+        const double rn = fma(-alpha, wk, nxt[0][j]);
+        st(rr, j, rn);
+        s_r = fma(rn, rn, s_r);
+    }
+    s_r = bsum(s_r, sh);
+    if (threadIdx.x == 0) {
+        A.part_rn[bid] = s_r;
+        if (bid == 0) {
+            A.alphas[k] = alpha;
+            A.gammas[k] = gamma;
+            for (int d = 1; d <= kGramStride; ++d) A.gram[(int64_t)k * kGramStride + d - 1] = 0.0;
+            // W_k . W_m = gamma (w . old[h][t]) for the held directions m < k
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int t = 0; t < B; ++t) {
+                    const int m = (nblk - 1 - h) * B + t;
+                    const int d = k - m;
+                    if (m >= 0 && d >= 1 && d <= kGramStride)
+                        A.gram[(int64_t)k * kGramStride + d - 1] = gamma * tot[2 + h * B + t];
+                }
+            if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
+        }
+    }
+}
+
+template <int EPT, int B, int L, bool LEAD>
+__global__ __launch_bounds__(kThreads) void k_rm_lag(RmArgs A) {
+    __shared__ double sh[kRmLagWords * (kThreads / 64)];
+    __shared__ unsigned long long ptab[kPtrLds];
+    rm_body_lag<EPT, B, L, LEAD>(A, gridDim.x, blockIdx.x, sh, ptab);
 }
 
 // RM of several vector sets (columns of a batched solve, or independent
@@ -644,7 +950,7 @@ __device__ __forceinline__ void rm_body_cw(const RmArgs& A, const int G, const i
                 for (int t = 1; t < B; ++t)
                     if (t < bb)
 #pragma unroll
-                        for (int m = 0; m < t; ++m) gm[t][m] = A.gram[(int64_t)(j0 + t) * kGramStride + m];
+                        for (int m = 0; m < t; ++m) gm[t][m] = A.gram[(int64_t)(j0 + t) * kGramStride + (t - m - 1)];
             }
             __syncthreads(); // compute waves' partials in place
             const unsigned tag = (unsigned)(g % 3);
@@ -694,8 +1000,8 @@ __device__ __forceinline__ void rm_body_cw(const RmArgs& A, const int G, const i
                 if (bid == 0) {
                     A.alphas[k] = alpha;
                     A.gammas[k] = gamma;
-                    for (int t = 0; t < B - 1; ++t)
-                        A.gram[(int64_t)k * kGramStride + t] = (t < gk) ? gamma * tot[2 + t] : 0.0;
+                    for (int d = 1; d <= kGramStride; ++d)
+                        A.gram[(int64_t)k * kGramStride + d - 1] = (d <= gk) ? gamma * tot[2 + gk - d] : 0.0;
                     if (!keep) A.scal[S_BREAKDOWNS] += 1.0;
                 }
             }
@@ -1008,6 +1314,48 @@ static const void* pick(int ept, int b, int lead, bool multi = false, int nc = 0
     }
     return nullptr;
 }
+// Lagged form instantiations: one direction per exchange with one or two
+// exchanges in flight for the entries per thread of bandwidth-bound levels;
+// two or four directions per exchange with one in flight for the small,
+// exchange-bound levels.
+template <int EPT, int B, int L>
+static const void* lag_kernel(int lead) {
+    return lead ? reinterpret_cast<const void*>(&k_rm_lag<EPT, B, L, true>)
+                : reinterpret_cast<const void*>(&k_rm_lag<EPT, B, L, false>);
+}
+static const void* pick_lag(int ept, int b, int lag, int lead) {
+    if (b == 1 && lag == 2) {
+        switch (ept) {
+        case 8: return lag_kernel<8, 1, 2>(lead);
+        case 10: return lag_kernel<10, 1, 2>(lead);
+        case 16: return lag_kernel<16, 1, 2>(lead);
+        case 20: return lag_kernel<20, 1, 2>(lead);
+        }
+    } else if (b == 1 && lag == 1) {
+        switch (ept) {
+        case 8: return lag_kernel<8, 1, 1>(lead);
+        case 10: return lag_kernel<10, 1, 1>(lead);
+        case 16: return lag_kernel<16, 1, 1>(lead);
+        case 20: return lag_kernel<20, 1, 1>(lead);
+        }
+    } else if (b == 2 && lag == 1) {
+        switch (ept) {
+        case 2: return lag_kernel<2, 2, 1>(lead);
+        case 4: return lag_kernel<4, 2, 1>(lead);
+        case 8: return lag_kernel<8, 2, 1>(lead);
+        }
+    } else if (b == 4 && lag == 1) {
+        switch (ept) {
+        case 1: return lag_kernel<1, 4, 1>(lead);
+        case 2: return lag_kernel<2, 4, 1>(lead);
+        case 4: return lag_kernel<4, 4, 1>(lead);
+        }
+    }
+    return nullptr;
+}
+static const void* pick_cfg(const RmConfig& c) {
+    return c.lag ? pick_lag(c.ept, c.B, c.lag, c.lead) : pick(c.ept, c.B, c.lead, false, c.cw);
+}
 // threads per block and compute threads per block of a configuration
 static int rm_block_threads(int nc) { return nc ? 64 * (nc + 1) : kThreads; }
 static int rm_compute_threads(int nc) { return nc ? 64 * nc : kThreads; }
@@ -1045,12 +1393,12 @@ int rm_persistent_candidates(int64_t N, RmConfig* out, int cap) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int n = 0;
-    auto consider = [&](int pass, int e, int b, int lead, int nc) {
+    auto consider = [&](int pass, int e, int b, int lead, int nc, int lag) {
         const int64_t per = (int64_t)rm_compute_threads(nc) * e;
         const int64_t need = (N + per - 1) / per;
         if (pass == 0 ? need > 512 : (need <= 512 || need > kMaxRedBlocks)) return;
         if (nc && need > cw_max_blocks(b)) return;
-        const void* f = pick(e, b, lead, false, nc);
+        const void* f = lag ? pick_lag(e, b, lag, lead) : pick(e, b, lead, false, nc);
         if (!f) return;
         hipFuncAttributes fa;
         int per_cu = 0;
@@ -1063,16 +1411,18 @@ int rm_persistent_candidates(int64_t N, RmConfig* out, int cap) {
         // although the occupancy query allowed it, so they get one unit each.
         if (nc == 4) per_cu = 1;
         if (need > (int64_t)per_cu * cus) return;
-        if (n < cap) out[n++] = RmConfig{(int)need, e, b, lead, nc};
+        if (n < cap) out[n++] = RmConfig{(int)need, e, b, lead, nc, lag};
     };
     for (int pass = 0; pass < 2; ++pass) {
         for (int e : kEpts)
             for (int b : {4, 2, 1})
-                for (int lead : {0, 1})
-                    for (int nc : {4, 0}) consider(pass, e, b, lead, nc);
+                for (int lead : {0, 1}) {
+                    for (int nc : {4, 0}) consider(pass, e, b, lead, nc, 0);
+                    for (int lag : {1, 2}) consider(pass, e, b, lead, 0, lag);
+                }
         for (int e : kEpts3)
             for (int b : {2, 1})
-                for (int lead : {0, 1}) consider(pass, e, b, lead, 3);
+                for (int lead : {0, 1}) consider(pass, e, b, lead, 3, 0);
     }
     return n;
 }
@@ -1090,20 +1440,21 @@ bool rm_persistent_config(int64_t N, RmConfig* cfg) {
 // words per block, other exchange form) can hold any phase's value; the
 // words are therefore set to the empty tag (3) whenever the layout changes.
 hipError_t prepare_slots(Level& L, const RmConfig& c, hipStream_t st) {
-    const int sw = c.B + 1;
-    if (L.slot_G == c.G && L.slot_SW == sw && L.slot_lead == c.lead) return hipSuccess;
-    hipError_t e = hipMemsetAsync(L.xslots, 0xFF, sizeof(unsigned long long) * kRmSlotWords, st);
+    const int sw = rm_slot_words(c), sets = rm_slot_sets(c);
+    if (L.slot_G == c.G && L.slot_SW == sw && L.slot_lead == c.lead && L.slot_sets == sets) return hipSuccess;
+    hipError_t e = hipMemsetAsync(L.xslots, 0xFF, sizeof(unsigned long long) * kRmSlotWordsMax, st);
     if (e != hipSuccess) return e;
     L.slot_G = c.G;
     L.slot_SW = sw;
     L.slot_lead = c.lead;
+    L.slot_sets = sets;
     return hipSuccess;
 }
 
 hipError_t launch_rm_persistent(const RmConfig& c, const RmArgs& args, hipStream_t st) {
-    const void* f = pick(c.ept, c.B, c.lead, false, c.cw);
+    const void* f = pick_cfg(c);
     const int G = c.G;
-    if (!f || (c.cw && G > cw_max_blocks(c.B)) ||
+    if (!f || (c.cw && (G > cw_max_blocks(c.B) || c.lag)) || G > kMaxRedBlocks ||
         (int64_t)G * rm_compute_threads(c.cw) * c.ept < args.N) // the grid must cover the vectors
         return hipErrorInvalidValue;
     RmArgs a = args;

@@ -135,6 +135,8 @@ static void free_level(Level& L) {
     hipFree(L.gammas);
     hipFree(L.gram);
     hipFree(L.dvec);
+    hipFree(L.rs);
+    hipFree(L.xs);
     L = Level();
 }
 
@@ -167,6 +169,9 @@ extern "C" void omg_destroy(omg_solver* s) {
     hipFree(s->bufB);
     hipFree(s->err_flag);
     if (s->host_scal) hipHostFree(s->host_scal);
+    if (s->vlog_host) hipHostFree(s->vlog_host);
+    for (hipEvent_t e : s->vlog_ev)
+        if (e) hipEventDestroy(e);
     delete s;
 }
 
@@ -357,7 +362,7 @@ static omg_status alloc_rm_state(omg_solver* s, Level& L, int l) {
     L.ucap = per_it * std::max(its, 1) + 4;
     if (hipMalloc((void**)&L.bar, 2 * sizeof(unsigned)) != hipSuccess) return OMG_ENOMEM;
     HIP_OK(hipMemset(L.bar, 0, 2 * sizeof(unsigned)));
-    const size_t xs = sizeof(unsigned long long) * kRmSlotWords;
+    const size_t xs = sizeof(unsigned long long) * kRmSlotWordsMax;
     if (hipMalloc((void**)&L.xslots, xs) != hipSuccess) return OMG_ENOMEM;
     HIP_OK(hipMemset(L.xslots, 0xFF, xs)); // every word starts with tag 3 = empty
     L.phase = 0;
@@ -470,8 +475,9 @@ static omg_status tune_rm(omg_solver* s, int l) {
             }
         }
         if (log)
-            std::fprintf(stderr, "[omg] RM tuning N=%lld k=%d: G=%d ept=%d B=%d lead=%d cw=%d: %.1f us\n",
-                         (long long)L.N, kt, c[q].G, c[q].ept, c[q].B, c[q].lead, c[q].cw, 1e3 * tbest / 3);
+            std::fprintf(stderr, "[omg] RM tuning N=%lld k=%d: G=%d ept=%d B=%d lead=%d cw=%d lag=%d: %.1f us\n",
+                         (long long)L.N, kt, c[q].G, c[q].ept, c[q].B, c[q].lead, c[q].cw, c[q].lag,
+                         1e3 * tbest / 3);
         if (res == OMG_OK && tbest < best) {
             best = tbest;
             bi = q;
@@ -933,6 +939,175 @@ static omg_status adaptive_cycle(omg_solver* s, int l, int sub_variant, hipStrea
     return OMG_OK;
 }
 
+// ---------------------------------------------------------------- norm log
+// Residual norms of the level tests go to consecutive positions of a mapped
+// host buffer: norm_async queues the finishing reduction of level l's last
+// update (and an event behind it) and returns the position; norm_wait blocks
+// until that event and returns the value. Positions past the buffer are
+// read at once (the value kept on the host).
+constexpr int64_t kVlogCap = 1 << 18;
+constexpr int kVlogEvents = 64;
+
+static omg_status vlog_init(omg_solver* s) {
+    if (s->vlog_host) return OMG_OK;
+    const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void**)&s->vlog_host, sizeof(double) * kVlogCap, fl) != hipSuccess) return OMG_ENOMEM;
+    HIP_OK(hipHostGetDevicePointer((void**)&s->vlog_dev, s->vlog_host, 0));
+    s->vlog_ev.assign(kVlogEvents, nullptr);
+    for (auto& e : s->vlog_ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return OMG_OK;
+}
+
+static omg_status norm_async(omg_solver* s, int l, hipStream_t st, int64_t* pos) {
+    Level& L = s->lev[l];
+    const int64_t p = s->vlog_pos++;
+    if (p < kVlogCap) {
+        HIP_OK(launch_finish_norm(L.Grn, L.part + 4 * kMaxRedBlocks, s->vlog_dev + p, st));
+        HIP_OK(hipEventRecord(s->vlog_ev[p % kVlogEvents], st));
+    } else { // past the buffer: read now
+        double v;
+        HIP_OK(launch_finish_norm(L.Grn, L.part + 4 * kMaxRedBlocks, s->host_scal_dev + l, st));
+        HIP_OK(hipStreamSynchronize(st));
+        v = s->host_scal[l];
+        s->vlog_over.push_back(v);
+    }
+    *pos = p;
+    return OMG_OK;
+}
+
+static omg_status norm_wait(omg_solver* s, int64_t p, double* out) {
+    if (p >= kVlogCap) {
+        *out = s->vlog_over[(size_t)(p - kVlogCap)];
+        return OMG_OK;
+    }
+    HIP_OK(hipEventSynchronize(s->vlog_ev[p % kVlogEvents]));
+    *out = s->vlog_host[p];
+    return OMG_OK;
+}
+
+// Per-visit residual log entry whose norms are filled in when the solve ends.
+static void log_visit_norms(omg_solver* s, int l, int it, int64_t p0, const std::vector<int64_t>& ps) {
+    s->vnorm.push_back(l);
+    s->vnorm.push_back(it);
+    s->vfix.push_back({s->vnorm.size(), p0});
+    s->vnorm.push_back(0.0);
+    for (int64_t p : ps) {
+        s->vfix.push_back({s->vnorm.size(), p});
+        s->vnorm.push_back(0.0);
+    }
+}
+
+static omg_status vlog_resolve(omg_solver* s) {
+    HIP_OK(hipStreamSynchronize(s->stream));
+    for (auto& f : s->vfix) {
+        double v;
+        OMG_TRY(norm_wait(s, f.second, &v));
+        if (f.first < s->vnorm.size()) s->vnorm[f.first] = v;
+    }
+    s->vfix.clear();
+    return OMG_OK;
+}
+
+// Snapshot of a level before a speculative iteration: r, x (where it holds
+// anything besides the implicit directions), the dropped-direction counter,
+// the direction count and the logs' lengths. The stored directions below
+// that count are not touched by the iteration (it only appends), so the
+// count restores them.
+struct Snap {
+    int k = 0, restarted = 0;
+    size_t visits = 0, vnorm = 0, vfix = 0, steps = 0;
+};
+
+static omg_status snap_take(omg_solver* s, int l, hipStream_t st, Snap& sp) {
+    Level& L = s->lev[l];
+    if (!L.rs && (hipMalloc((void**)&L.rs, sizeof(double) * L.N) != hipSuccess ||
+                  hipMalloc((void**)&L.xs, sizeof(double) * L.N) != hipSuccess))
+        return OMG_ENOMEM;
+    const int64_t nx = (!L.persist || s->opt.m_max > 0) ? L.N : 0; // persistent: x is zero unless restarted
+    HIP_OK(launch_snap(L.rs, L.r, L.N, L.xs, L.x, nx, L.scal + S_TMP, L.scal + S_BREAKDOWNS, st));
+    sp.k = L.k;
+    sp.restarted = L.restarted;
+    sp.visits = s->visits.size();
+    sp.vnorm = s->vnorm.size();
+    sp.vfix = s->vfix.size();
+    sp.steps = s->steps.size();
+    return OMG_OK;
+}
+
+static omg_status snap_restore(omg_solver* s, int l, hipStream_t st, const Snap& sp) {
+    Level& L = s->lev[l];
+    const int64_t nx = (!L.persist || s->opt.m_max > 0) ? L.N : 0;
+    HIP_OK(launch_snap(L.r, L.rs, L.N, L.x, L.xs, nx, L.scal + S_BREAKDOWNS, L.scal + S_TMP, st));
+    L.k = sp.k;
+    L.restarted = sp.restarted;
+    s->visits.resize(sp.visits);
+    s->vnorm.resize(sp.vnorm);
+    s->vfix.resize(sp.vfix);
+    s->steps.resize(sp.steps);
+    return OMG_OK;
+}
+
+// One iteration of level l's cycle (Algorithm 2, or the deterministic /
+// timing-adaptive Algorithm 5 form), x and r updated in place.
+static omg_status level_iteration(omg_solver* s, int l, int variant, int sub_variant, hipStream_t st) {
+    Level& L = s->lev[l];
+    Level& C = s->lev[l + 1];
+    if (cycle_multiplicative(variant)) {
+        OMG_TRY(smoother(s, l, L.r, s->opt.s_pre, L.z, st));
+        OMG_TRY(rm(s, l, L.z, st));
+        OMG_TRY(trace_rm(s, l, st, 1));
+        HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
+        OMG_TRY(coarse_path(s, l, sub_variant, st, L.z));
+        OMG_TRY(rm(s, l, L.z, st));
+        OMG_TRY(trace_rm(s, l, st, 2));
+        OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
+        OMG_TRY(rm(s, l, L.z, st));
+        OMG_TRY(trace_rm(s, l, st, 1));
+        return OMG_OK;
+    }
+    // coarse group: restriction of the residual at the start of the cycle
+    HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
+    const bool forking = (l == cycle_fork_level(s->opt));
+    const bool fork = forking && s->opt.overlap_streams && !s->opt.trace;
+    if (fork && s->opt.n_s_max > s->opt.n_s) {
+        HIP_OK(hipEventRecord(s->ev_fork, st));
+        int steps = 0;
+        OMG_TRY(adaptive_cycle(s, l, sub_variant, st, &steps));
+        s->steps.push_back(steps);
+    } else if (fork) {
+        s->steps.push_back(s->opt.n_s);
+        HIP_OK(hipEventRecord(s->ev_fork, st));
+        // smoother group: queue the fine work first (asynchronous)
+        for (int t = 0; t < s->opt.n_s; ++t) {
+            OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
+            OMG_TRY(rm(s, l, L.z, st));
+        }
+        HIP_OK(hipStreamWaitEvent(s->cstream, s->ev_fork, 0));
+        OMG_TRY(coarse_path(s, l, sub_variant, s->cstream, L.zcor));
+        HIP_OK(hipEventRecord(s->ev_join, s->cstream));
+        HIP_OK(hipStreamWaitEvent(st, s->ev_join, 0));
+    } else {
+        if (forking) s->steps.push_back(s->opt.n_s);
+        OMG_TRY(coarse_path(s, l, sub_variant, st, L.zcor));
+        for (int t = 0; t < s->opt.n_s; ++t) {
+            OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
+            OMG_TRY(rm(s, l, L.z, st));
+            OMG_TRY(trace_rm(s, l, st, 1));
+        }
+    }
+    OMG_TRY(rm(s, l, L.zcor, st));
+    OMG_TRY(trace_rm(s, l, st, 2));
+    return OMG_OK;
+}
+
+// (x, r) = MG_l(b, 0): the level loop of Algorithm 2 / 5 with the level tests
+// of Sec. 4.2. On a coarse level (l >= 1) the next iteration is queued before
+// the norm that decides on it has been read (speculation): the host then
+// waits while the GPU already works on that iteration, and if the test says
+// stop, the iteration is undone exactly (r, x, direction count, logs and the
+// dropped-direction counter restored from a snapshot), so the results are
+// those of the plain loop. A replayed visit (omg_set_replay) reads no norm
+// at all while it runs.
 static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double tol, int variant, hipStream_t st) {
     Level& L = s->lev[l];
     if (L.coarsest) {
@@ -940,84 +1115,80 @@ static omg_status mg(omg_solver* s, int l, const double* b, double* xout, double
         s->kcount[OMG_K_COARSE][l]++;
         return OMG_OK;
     }
-    Level& C = s->lev[l + 1];
     L.k = 0;
     L.restarted = 0;
     HIP_OK(launch_level_init(L.N, L.G, b, L.x, L.r, L.part + 4 * kMaxRedBlocks, st));
     L.Grn = L.G;
-    double r0n;
-    OMG_TRY(read_rnorm(s, l, st, &r0n));
-    const double bn = r0n;
-    if (l == 0) log_trace(s, r0n, 0);
     int replay_count = -1; // replayed iteration count of this visit (omg_set_replay)
     if (s->replaying && l < (int)s->replay_q.size() && s->replay_pos[l] < s->replay_q[l].size())
         replay_count = s->replay_q[l][s->replay_pos[l]++];
     const int sub_variant = cycle_sub_variant(variant, s->opt.coarse_sync);
+    const bool adaptive_here = l == cycle_fork_level(s->opt) && !cycle_multiplicative(variant) &&
+                               s->opt.overlap_streams && !s->opt.trace && s->opt.n_s_max > s->opt.n_s;
+    // (an m_max restart inside the speculative iteration would overwrite the
+    // stored directions the snapshot keeps by count only: no speculation then)
+    const bool speculate = l > 0 && !s->opt.trace && !adaptive_here && s->opt.m_max == 0;
+    int64_t p0;
+    OMG_TRY(norm_async(s, l, st, &p0));
+    std::vector<int64_t> ps; // positions of ||r|| after each iteration
     int it = 0;
-    double rn = r0n;
+    double r0n = 0.0, rn = 0.0;
     omg_status status = OMG_OK;
-    std::vector<double> rns; // ||r|| after each iteration of this visit
-    while (!stop_level(s, l, rn, r0n, bn, it, tol, replay_count)) {
-        if (cycle_multiplicative(variant)) {
-            OMG_TRY(smoother(s, l, L.r, s->opt.s_pre, L.z, st));
-            OMG_TRY(rm(s, l, L.z, st));
-            OMG_TRY(trace_rm(s, l, st, 1));
-            HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
-            OMG_TRY(coarse_path(s, l, sub_variant, st, L.z));
-            OMG_TRY(rm(s, l, L.z, st));
-            OMG_TRY(trace_rm(s, l, st, 2));
-            OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
-            OMG_TRY(rm(s, l, L.z, st));
-            OMG_TRY(trace_rm(s, l, st, 1));
-        } else {
-            // coarse group: restriction of the residual at the start of the cycle
-            HIP_OK(launch_restrict(L, C, s->bs, use32(s, l, false), s->E, s->E32, L.r, C.b, st));
-            const bool forking = (l == cycle_fork_level(s->opt));
-            const bool fork = forking && s->opt.overlap_streams && !s->opt.trace;
-            if (fork && s->opt.n_s_max > s->opt.n_s) {
-                HIP_OK(hipEventRecord(s->ev_fork, st));
-                int steps = 0;
-                OMG_TRY(adaptive_cycle(s, l, sub_variant, st, &steps));
-                s->steps.push_back(steps);
-            } else if (fork) {
-                s->steps.push_back(s->opt.n_s);
-                HIP_OK(hipEventRecord(s->ev_fork, st));
-                // smoother group: queue the fine work first (asynchronous)
-                for (int t = 0; t < s->opt.n_s; ++t) {
-                    OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
-                    OMG_TRY(rm(s, l, L.z, st));
-                }
-                HIP_OK(hipStreamWaitEvent(s->cstream, s->ev_fork, 0));
-                OMG_TRY(coarse_path(s, l, sub_variant, s->cstream, L.zcor));
-                HIP_OK(hipEventRecord(s->ev_join, s->cstream));
-                HIP_OK(hipStreamWaitEvent(st, s->ev_join, 0));
-            } else {
-                if (forking) s->steps.push_back(s->opt.n_s);
-                OMG_TRY(coarse_path(s, l, sub_variant, st, L.zcor));
-                for (int t = 0; t < s->opt.n_s; ++t) {
-                    OMG_TRY(smoother(s, l, L.r, s->opt.s_post, L.z, st));
-                    OMG_TRY(rm(s, l, L.z, st));
-                    OMG_TRY(trace_rm(s, l, st, 1));
-                }
-            }
-            OMG_TRY(rm(s, l, L.zcor, st));
-            OMG_TRY(trace_rm(s, l, st, 2));
+    if (l == 0) { // ||b|| of the finest level: one read per solve
+        OMG_TRY(norm_wait(s, p0, &r0n));
+        log_trace(s, r0n, 0);
+    }
+    if (replay_count >= 0) {
+        for (; it < replay_count; ++it) {
+            OMG_TRY(level_iteration(s, l, variant, sub_variant, st));
+            int64_t p;
+            OMG_TRY(norm_async(s, l, st, &p));
+            ps.push_back(p);
         }
-        it++;
-        OMG_TRY(read_rnorm(s, l, st, &rn));
-        rns.push_back(rn);
-        if (!std::isfinite(rn)) {
-            status = OMG_EINVAL;
-            break;
+    } else if (!speculate) {
+        OMG_TRY(norm_wait(s, p0, &r0n));
+        rn = r0n;
+        while (!stop_level(s, l, rn, r0n, r0n, it, tol, -1)) {
+            OMG_TRY(level_iteration(s, l, variant, sub_variant, st));
+            it++;
+            int64_t p;
+            OMG_TRY(norm_async(s, l, st, &p));
+            ps.push_back(p);
+            OMG_TRY(norm_wait(s, p, &rn));
+            if (!std::isfinite(rn)) {
+                status = OMG_EINVAL;
+                break;
+            }
+        }
+    } else {
+        const int cap = s->opt.crit_max[l - 1];
+        int64_t pq = p0; // position of the norm after iteration `it`
+        for (;;) {
+            const bool ahead = it + 1 <= cap; // stop_level stops at the cap whatever the norm
+            Snap sp;
+            int64_t pn = -1;
+            if (ahead) {
+                OMG_TRY(snap_take(s, l, st, sp));
+                OMG_TRY(level_iteration(s, l, variant, sub_variant, st));
+                OMG_TRY(norm_async(s, l, st, &pn));
+            }
+            OMG_TRY(norm_wait(s, pq, &rn));
+            if (it == 0) r0n = rn;
+            const bool bad = !std::isfinite(rn);
+            if (bad || stop_level(s, l, rn, r0n, r0n, it, tol, -1)) {
+                if (ahead) OMG_TRY(snap_restore(s, l, st, sp));
+                if (bad && it > 0) status = OMG_EINVAL;
+                break;
+            }
+            it++;
+            ps.push_back(pn);
+            pq = pn;
         }
     }
-    if (l == 0 && status == OMG_OK && rn > tol * bn && replay_count < 0) status = OMG_ENOCONV;
+    if (l == 0 && status == OMG_OK && rn > tol * r0n && replay_count < 0) status = OMG_ENOCONV;
     s->visits.push_back(l);
     s->visits.push_back(it);
-    s->vnorm.push_back(l);
-    s->vnorm.push_back(it);
-    s->vnorm.push_back(r0n);
-    s->vnorm.insert(s->vnorm.end(), rns.begin(), rns.end());
+    log_visit_norms(s, l, it, p0, ps);
     if (L.persist) { // x = sum_k d_k z~_k: the search directions are implicit
         HIP_OK(launch_recon(L.k, L.hist, L.gammas, L.alphas, L.dvec, st));
         HIP_OK(launch_lincomb(L.N, L.k, L.dvec, L.dZp, xout, st));
@@ -1161,6 +1332,10 @@ static omg_status check_rm_abort(omg_solver* s) {
 
 static omg_status solve_internal(omg_solver* s, const double* b_soa, double* x_soa, double tol, omg_report* R) {
     reset_logs(s);
+    OMG_TRY(vlog_init(s));
+    s->vlog_pos = 0;
+    s->vlog_over.clear();
+    s->vfix.clear();
     s->replay_q.assign(s->nlev, {});
     s->replay_pos.assign(s->nlev, 0);
     s->replaying = !s->replay.empty();
@@ -1168,6 +1343,8 @@ static omg_status solve_internal(omg_solver* s, const double* b_soa, double* x_s
         if (s->replay[i] >= 0 && s->replay[i] < s->nlev) s->replay_q[s->replay[i]].push_back(s->replay[i + 1]);
     omg_status st = solve_soa(s, b_soa, x_soa, tol, R);
     s->replaying = 0;
+    const omg_status lg = vlog_resolve(s);
+    if (lg != OMG_OK && st == OMG_OK) st = lg;
     const omg_status ab = check_rm_abort(s);
     return ab != OMG_OK ? ab : st;
 }
@@ -1320,7 +1497,7 @@ extern "C" omg_status omg_level_rm_step(omg_solver* s, int32_t level, int32_t k,
         bool found = false;
         for (int q = 0; q < nc && !found; ++q)
             if (cand[q].G == cfg[0] && cand[q].ept == cfg[1] && cand[q].B == cfg[2] && cand[q].lead == cfg[3] &&
-                cand[q].cw == cfg[4]) {
+                cand[q].cw == cfg[4] && cand[q].lag == cfg[5]) {
                 c = cand[q];
                 found = true;
             }
@@ -1377,9 +1554,24 @@ extern "C" omg_status omg_level_rm_step(omg_solver* s, int32_t level, int32_t k,
     return OMG_OK;
 }
 
-// Co-resident RM launch configurations of level l (host out[5*cap]: blocks,
-// entries per thread, directions per exchange, leader, exchange wave); count
-// in *n.
+extern "C" omg_status omg_level_set_rm_config(omg_solver* s, int32_t level, const int32_t* cfg) {
+    if (!s || level < 0 || level >= s->nlev || !cfg) return OMG_EINVAL;
+    Level& L = s->lev[level];
+    if (!L.persist) return OMG_EUNSUPPORTED;
+    RmConfig cand[kMaxRmConfigs];
+    const int nc = rm_persistent_candidates(L.N, cand, kMaxRmConfigs);
+    for (int q = 0; q < nc; ++q)
+        if (cand[q].G == cfg[0] && cand[q].ept == cfg[1] && cand[q].B == cfg[2] && cand[q].lead == cfg[3] &&
+            cand[q].cw == cfg[4] && cand[q].lag == cfg[5]) {
+            L.rmc = cand[q];
+            return OMG_OK;
+        }
+    return OMG_EINVAL;
+}
+
+// Co-resident RM launch configurations of level l (host out[6*cap]: blocks,
+// entries per thread, directions per exchange, leader, exchange wave, lag);
+// count in *n.
 extern "C" omg_status omg_level_rm_configs(const omg_solver* s, int32_t level, int32_t* out, int32_t cap,
                                            int32_t* n) {
     if (!s || level < 0 || level >= s->nlev || !n) return OMG_EINVAL;
@@ -1388,11 +1580,12 @@ extern "C" omg_status omg_level_rm_configs(const omg_solver* s, int32_t level, i
     const int nc = L.persist ? rm_persistent_candidates(L.N, cand, kMaxRmConfigs) : 0;
     *n = nc;
     for (int q = 0; q < nc && q < cap && out; ++q) {
-        out[5 * q] = cand[q].G;
-        out[5 * q + 1] = cand[q].ept;
-        out[5 * q + 2] = cand[q].B;
-        out[5 * q + 3] = cand[q].lead;
-        out[5 * q + 4] = cand[q].cw;
+        out[6 * q] = cand[q].G;
+        out[6 * q + 1] = cand[q].ept;
+        out[6 * q + 2] = cand[q].B;
+        out[6 * q + 3] = cand[q].lead;
+        out[6 * q + 4] = cand[q].cw;
+        out[6 * q + 5] = cand[q].lag;
     }
     return OMG_OK;
 }

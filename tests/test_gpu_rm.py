@@ -76,7 +76,7 @@ def test_rm_step_exchange_wave_is_bitwise_plain(n, p):
     N = prob.n_dofs
     rng = np.random.default_rng(8)
     configs = g.rm_configs(0)
-    pairs = [(c, c[:4] + (0,)) for c in configs if c[4] == 4 and c[:4] + (0,) in configs]
+    pairs = [(c, c[:4] + (0, 0)) for c in configs if c[4] == 4 and c[5] == 0 and c[:4] + (0, 0) in configs]
     assert pairs, "some configuration has both forms"
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     for k in (0, 3, 9, 33):
@@ -115,3 +115,31 @@ def test_rm_step_breakdown_drops_direction(n, p):
         assert not torch.any(Wk != 0), what
         assert np.array_equal(rn_g.cpu().numpy(), r), what
         assert np.abs(b_g - betas).max() <= 1e-12, what
+
+
+@pytest.mark.parametrize("n,p,lv", [(8, 1, 3), (16, 2, 2), (16, 1, 4)])
+def test_every_rm_form_in_whole_solves(n, p, lv):
+    """Whole Algorithm 2 solves with each RM form forced on the finest level
+    (plain blocks, exchange wave, lagged with one or two exchanges in flight,
+    each with the smallest and largest grid available): the lagged forms'
+    Gram-entry corrections are exercised on the directions the solve itself
+    produces. Same visit log as the oracle, solution within 1e-9."""
+    import oracle
+    prob = synth.make_problem(n, p, n_levels=lv)
+    nu = synth.nu_sphere(n, n, n, prob.h)
+    o = oracle.Oracle.from_sip(prob, nu, s_pre=2, s_post=2)
+    b = synth.rhs(prob.n_dofs, 0)
+    x_o = o.solve(b)
+    g = omg().Solver.from_sip(omg().Solver.make_grid(n, n, n, p, lv, prob.h), torch.tensor(nu, device="cuda"),
+                              s_pre=2, s_post=2)
+    forms = {}
+    for c in g.rm_configs(0):
+        forms.setdefault((c[2], c[4], c[5]), []).append(c)
+    assert any(key[2] > 0 for key in forms), "lagged forms are candidates"
+    for key, cs in sorted(forms.items()):
+        for cfg in {cs[0], cs[-1]}:
+            g.set_rm_config(0, cfg)
+            x_g = g.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+            what = f"config {cfg}"
+            assert np.array_equal(g.visits(), o.visits()), what
+            assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o), what

@@ -317,9 +317,12 @@ def main():
     cand.sort(reverse=True)
     breakdown = {f"{omg.K_NAMES[k]}@L{l}": round(float(t), 2) for t, k, l, _ in cand[:14]}
     log(f"estimated ms per solve by kernel: {breakdown}")
+    # the roofline is taken on the finest level, whose data stream from HBM
+    # (the coarser levels' operators and directions largely sit in the
+    # 256 MB last-level cache, where HBM peak is not the bound)
     roof = None
     for _, kind, l, _ in cand:
-        if kind in (omg.K_SPMV, omg.K_BJ, omg.K_MGS, omg.K_RMP):
+        if l == 0 and kind in (omg.K_SPMV, omg.K_BJ, omg.K_MGS, omg.K_RMP):
             n_l, avg_ms, alg = probed.get((kind, l)) or probe(kind, l)
             achieved = alg / (avg_ms * 1e-3) / 1e9
             tr = profile_traffic(alg) if (kind == omg.K_RMP and l == 0) else None

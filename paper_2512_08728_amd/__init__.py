@@ -14,6 +14,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libomg.so")
+# the persistent RM kernel's launch configurations chosen per device kind and
+# level size (read by the library; sizes not listed are tuned and appended)
+TUNE_FILE = os.path.join(_HERE, "rm_tuning.jsonl")
 MAX_LEVELS = 16
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -129,6 +132,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_08728_amd/build.py "
                               "(no CPU fallback exists)")
+        os.environ.setdefault("OMG_RM_TUNE_FILE", TUNE_FILE)
         L = ctypes.CDLL(LIB_PATH)
         P, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         L.omg_default_options.argtypes = [P]

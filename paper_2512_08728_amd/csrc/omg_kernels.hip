@@ -363,18 +363,9 @@ __device__ __forceinline__ void restrict_cell(int I, int fn, int cn, const int* 
     for (int c = 0; c < BS; ++c) rc[(int64_t)c * cn + I] = (double)out[c];
 }
 
-template <int BS, typename MT>
-__global__ __launch_bounds__(kThreads) void k_restrict(int fn, int cn, const int* __restrict__ dn_ptr,
-                                                       const int* __restrict__ dn, const MT* __restrict__ E,
-                                                       const double* __restrict__ r, double* __restrict__ rc) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= cn) return;
-    restrict_cell<BS, MT>(I, fn, cn, dn_ptr, dn, E, r, rc);
-}
-
-// The same with one thread per (coarse cell, component): BS times the
-// parallelism of k_restrict (the coarse levels have only a few thousand
-// cells), each output summed in k_restrict's order.
+// Restriction launch: one thread per (coarse cell, component), BS times the
+// parallelism of a thread per coarse cell (the coarse levels have only a few
+// thousand cells); each output summed in restrict_cell's order.
 template <int BS, typename MT>
 __global__ __launch_bounds__(kThreads) void k_restrict_rows(int fn, int cn, const int* __restrict__ dn_ptr,
                                                             const int* __restrict__ dn, const MT* __restrict__ E,

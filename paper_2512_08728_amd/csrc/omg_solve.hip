@@ -394,11 +394,81 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k);
 static std::mutex g_rm_mu;
 static std::map<std::pair<int, int64_t>, RmConfig> g_rm_cache;
 
+// Tuning record file (JSON lines, path in the environment variable
+// OMG_RM_TUNE_FILE): one line per (device architecture, compute units, level
+// size) with the configuration the tuner chose and its time. A level whose
+// size has a record uses that configuration (if it is still co-resident)
+// without timing, so that every process on that device kind runs the same
+// arithmetic; a newly tuned size is appended.
+struct TuneRecord {
+    std::string arch;
+    int cus = 0;
+    int64_t N = 0;
+    RmConfig c;
+};
+static std::vector<TuneRecord> g_tune_file;
+static bool g_tune_loaded = false;
+
+static const char* tune_path() { return std::getenv("OMG_RM_TUNE_FILE"); }
+
+static void device_kind(int dev, std::string& arch, int& cus) {
+    hipDeviceProp_t p;
+    arch = "?";
+    cus = 0;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return;
+    arch = p.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    cus = p.multiProcessorCount;
+}
+
+static void tune_file_load() { // under g_rm_mu
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = tune_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char arch[64];
+        TuneRecord r;
+        long long n = 0;
+        if (std::sscanf(line,
+                        " {\"arch\": \"%63[^\"]\", \"cus\": %d, \"N\": %lld, \"G\": %d, \"ept\": %d, \"B\": %d, "
+                        "\"lead\": %d, \"cw\": %d, \"lag\": %d",
+                        arch, &r.cus, &n, &r.c.G, &r.c.ept, &r.c.B, &r.c.lead, &r.c.cw, &r.c.lag) == 9) {
+            r.arch = arch;
+            r.N = n;
+            g_tune_file.push_back(r);
+        }
+    }
+    std::fclose(f);
+}
+
+static void tune_file_append(const std::string& arch, int cus, int64_t N, const RmConfig& c, double us) {
+    const char* path = tune_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f,
+                 "{\"arch\": \"%s\", \"cus\": %d, \"N\": %lld, \"G\": %d, \"ept\": %d, \"B\": %d, \"lead\": %d, "
+                 "\"cw\": %d, \"lag\": %d, \"us\": %.1f}\n",
+                 arch.c_str(), cus, (long long)N, c.G, c.ept, c.B, c.lead, c.cw, c.lag, us);
+    std::fclose(f);
+    g_tune_file.push_back(TuneRecord{arch, cus, N, c});
+}
+
 static omg_status tune_rm(omg_solver* s, int l) {
     Level& L = s->lev[l];
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     const std::pair<int, int64_t> key(dev, L.N);
+    std::string arch;
+    int cus = 0;
+    device_kind(dev, arch, cus);
+    RmConfig c[kMaxRmConfigs];
+    const int nc = rm_persistent_candidates(L.N, c, kMaxRmConfigs);
     {
         std::lock_guard<std::mutex> lk(g_rm_mu);
         auto it = g_rm_cache.find(key);
@@ -406,9 +476,18 @@ static omg_status tune_rm(omg_solver* s, int l) {
             L.rmc = it->second;
             return OMG_OK;
         }
+        tune_file_load();
+        for (const TuneRecord& r : g_tune_file) {
+            if (r.arch != arch || r.cus != cus || r.N != L.N) continue;
+            for (int q = 0; q < nc; ++q)
+                if (c[q].G == r.c.G && c[q].ept == r.c.ept && c[q].B == r.c.B && c[q].lead == r.c.lead &&
+                    c[q].cw == r.c.cw && c[q].lag == r.c.lag) {
+                    L.rmc = c[q];
+                    g_rm_cache.emplace(key, c[q]);
+                    return OMG_OK;
+                }
+        }
     }
-    RmConfig c[kMaxRmConfigs];
-    const int nc = rm_persistent_candidates(L.N, c, kMaxRmConfigs);
     if (nc <= 1 || std::getenv("OMG_RM_NOTUNE")) {
         std::lock_guard<std::mutex> lk(g_rm_mu);
         g_rm_cache.emplace(key, L.rmc);
@@ -490,8 +569,9 @@ static omg_status tune_rm(omg_solver* s, int l) {
     HIP_OK(hipMemcpy(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost));
     if (flags[1]) return OMG_EHIP; // a bounded wait expired
     std::lock_guard<std::mutex> lk(g_rm_mu);
-    const RmConfig& pick = g_rm_cache.emplace(key, c[bi]).first->second; // first tuner of this size wins
-    L.rmc = pick;
+    auto ins = g_rm_cache.emplace(key, c[bi]); // first tuner of this size wins
+    if (ins.second) tune_file_append(arch, cus, L.N, c[bi], 1e3 * best / 3);
+    L.rmc = ins.first->second;
     return OMG_OK;
 }
 

@@ -17,10 +17,15 @@ solve is compared with:
   u ~ N(0,1) from seed 8 (functionals of the whole vector);
 * ``report``: iterations, stored directions, recursive and true residuals.
 
-The full solve takes about an hour on eight cores and ~33 GB of memory (the
-finest level stores ~735 direction pairs of 21 MB each).
+With --perturb the right-hand side is b (1 + 1e-15 xi), xi ~ N(0,1) from
+seed 5, and the output goes to oracle_64cubed_p2_perturbed.npz: the same
+solve after a perturbation at rounding level, which measures how far two
+correct runs of the method (different rounding) can end apart.
 
-    OMP_NUM_THREADS=8 python tests/golden/make_oracle_64cubed_p2.py
+The full solve takes about 90 minutes on seven cores and ~33 GB of memory
+(the finest level stores ~770 direction pairs of 21 MB each).
+
+    OMP_NUM_THREADS=8 python tests/golden/make_oracle_64cubed_p2.py [--perturb]
 """
 import json
 import os
@@ -36,7 +41,8 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-OUT = os.path.join(HERE, "oracle_64cubed_p2.npz")
+PERTURB = "--perturb" in sys.argv
+OUT = os.path.join(HERE, "oracle_64cubed_p2_perturbed.npz" if PERTURB else "oracle_64cubed_p2.npz")
 
 
 def main():
@@ -44,6 +50,8 @@ def main():
     assert prob.n_levels == 4
     nu = synth.nu_sphere(64, 64, 64, prob.h)
     b = synth.rhs(prob.n_dofs, 0)
+    if PERTURB:
+        b = b * (1 + 1e-15 * np.random.default_rng(5).standard_normal(prob.n_dofs))
     t0 = time.time()
     o = oracle.Oracle.from_sip(prob, nu, s_pre=2, s_post=2)
     print(f"setup {time.time() - t0:.1f} s, {oracle.num_threads()} threads", flush=True)

@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <type_traits>
 
 #include "omg_internal.h"
 
@@ -211,6 +212,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int b
 // first kPtrLds of them), so that requesting a direction costs no global
 // memory round trip in the MGS loop.
 constexpr int kPtrLds = 1024;
+
+// The lagged form keeps its pointers as a ring: W_j at ptab[j % kPtrLds].
+// The first kPtrLds are read at the start of a launch; when direction j0 (a
+// multiple of kPtrLds / 2) is about to be requested, directions
+// j0 + kPtrLds / 2 .. j0 + kPtrLds - 1 replace the half of the ring already
+// passed. Requesting a direction then never reads global memory inside the
+// loop: such a read would make the wave wait for every vector load it has in
+// flight (loads complete in issue order). The refilled entries are read at
+// least kPtrLds / 2 directions later, after the barriers of those steps.
+__device__ __forceinline__ void ptr_ring_refill(unsigned long long* ptab, const double* const* Wp, int k, int j0) {
+    for (int j = j0 + kPtrLds / 2 + (int)threadIdx.x; j < min(k, j0 + kPtrLds); j += blockDim.x)
+        ptab[j % kPtrLds] = (unsigned long long)Wp[j];
+}
 
 // The RM of one vector set on G blocks; this block is block `bid` of them.
 // MASK: the vectors have no zero tail past N (caller arrays): every access
@@ -503,6 +517,10 @@ __device__ __forceinline__ void collect_lag(unsigned long long* slots, int G, in
         if (w < nw) out[w] = v[w];
 }
 
+// Grids of the lagged form: at most two blocks' words per thread and word
+// index in an exchange.
+constexpr int kLagMaxBlocks = 2 * kThreads;
+
 // Direction blocks held after their dots for the updates: L for one
 // direction per block; L + 1 otherwise, so that the dots of a new direction
 // with every direction a later lagged step corrects for are at hand.
@@ -536,49 +554,50 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
     auto st = [&](__amdgpu_buffer_rsrc_t r, int j, double v) {
         if (t0 + j * T < N) st_all(r, j, v);
     };
-    // w; old[h]: the block finished h + 1 steps ago (awaiting its update, or
-    // held for the new direction's Gram dots); cur: this step's block; nxt:
-    // the next block (or r) streaming in
-    double w[EPT], old[H][B][EPT], cur[B][EPT], nxt[B][EPT];
+    // w, and a ring of R direction blocks: block j in ring[j % R] (r, after
+    // the last block, in ring[nblk % R]). In step s the ring holds the H
+    // blocks before s (awaiting their update, or held for the new
+    // direction's Gram dots), block s and block s + 1 streaming in; every
+    // role stays in the same registers, so the next block's loads are issued
+    // before this block is waited for and no block is copied.
+    constexpr int R = H + 2;
+    double w[EPT], ring[R][B][EPT];
     {
         const __amdgpu_buffer_rsrc_t rw = buffer_of(A.w, bytes), rz = buffer_of(A.z, bytes),
                                      rk = buffer_of(A.Zk, bytes);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             w[j] = ld(rw, j);
-            cur[0][j] = ld(rz, j);
+            ring[1][0][j] = ld(rz, j);
         }
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) st_all(rk, j, cur[0][j]);
+        for (int j = 0; j < EPT; ++j) st_all(rk, j, ring[1][0][j]);
     }
 #pragma unroll
-    for (int h = 0; h < H; ++h)
+    for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int t = 0; t < B; ++t)
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) old[h][t][j] = 0.0;
+            for (int j = 0; j < EPT; ++j) ring[i][t][j] = 0.0;
     for (int i = threadIdx.x; i < min(k, kPtrLds); i += blockDim.x) ptab[i] = (unsigned long long)A.Wp[i];
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rr = buffer_of(A.r, bytes);
     const int nblk = (k + B - 1) / B;
-    // block blk (zeros past k), or r when blk == nblk
+    // Block blk (zeros past k), or r when blk == nblk. Every call issues the
+    // same B EPT loads (a direction past k reads r and is zeroed), so that
+    // the compiler can count the loads in flight exactly and wait for one
+    // block without waiting for the next.
     auto load_block = [&](double (&dst)[B][EPT], int blk) {
-        if (blk == nblk) {
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) dst[0][j] = ld(rr, j);
-            return;
-        }
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             const int j = blk * B + t;
-            if (j < k) { // uniform
-                const __amdgpu_buffer_rsrc_t rt =
-                    buffer_of(j < kPtrLds ? (const void*)ptab[j] : (const void*)A.Wp[j], bytes);
+            const bool dir = blk < nblk && j < k; // uniform
+            const __amdgpu_buffer_rsrc_t rt =
+                dir ? buffer_of((const void*)ptab[j % kPtrLds], bytes) : rr;
 #pragma unroll
-                for (int q = 0; q < EPT; ++q) dst[t][q] = ld(rt, q);
-            } else {
-#pragma unroll
-                for (int q = 0; q < EPT; ++q) dst[t][q] = 0.0;
+            for (int q = 0; q < EPT; ++q) {
+                const double v = ld(rt, q);
+                dst[t][q] = (dir || (blk == nblk && t == 0)) ? v : 0.0;
             }
         }
     };
@@ -589,30 +608,39 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
     for (int i = 0; i < L; ++i)
 #pragma unroll
         for (int t = 0; t < B; ++t) bwin[i][t] = 0.0;
-    // collect block b2's dots, form its MGS coefficients and update w with blk
-    auto finish_block = [&](int b2, const double (&blk)[B][EPT]) {
-        double tot[SW];
-        collect_lag<SW, LEAD, S>(A.slots, G, bid, g0 + b2, b2 == 0 ? B + 1 : B, tot, sh, A.abort_flag);
+    // Gram entries W_{j0+t} . W_{j0+t-d}, d = 1 .. B + L B - 1, of block b2
+    // (gram[(j0 + t) kGramStride + d - 1]), read before they are needed
+    constexpr int GD = B + L * B - 1;
+    auto gram_issue = [&](int b2, double (&gp)[B][GD]) {
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const int64_t gj = (int64_t)max(0, min(b2 * B + t, k - 1)) * kGramStride;
+#pragma unroll
+            for (int d = 0; d < GD; ++d) gp[t][d] = A.gram[gj + d];
+        }
+    };
+    // form block b2's MGS coefficients from its exchange totals and update w with blk
+    auto finish_block = [&](int b2, const double (&tot)[SW], const double (&gp)[B][GD],
+                            const double (&blk)[B][EPT]) {
         if (b2 == 0) nin2 = tot[B];
-        const int j0 = b2 * B, bb = min(B, k - j0);
+        const int j0 = b2 * B, nb = min(B, k - j0);
         double beta[B];
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             double bt = 0.0;
-            if (t < bb) {
-                const int64_t gj = (int64_t)(j0 + t) * kGramStride;
+            if (t < nb) {
                 bt = tot[t];
 #pragma unroll
-                for (int m = 0; m < t; ++m) bt = fma(-A.gram[gj + (t - m - 1)], beta[m], bt);
+                for (int m = 0; m < t; ++m) bt = fma(-gp[t][t - m - 1], beta[m], bt);
                 // directions of the L blocks before: W_{j0-e}, e = 1 .. L B
 #pragma unroll
                 for (int e = 1; e <= L * B; ++e)
-                    if (j0 - e >= 0) bt = fma(-A.gram[gj + t + e - 1], bwin[(e - 1) / B][B - 1 - (e - 1) % B], bt);
+                    if (j0 - e >= 0) bt = fma(-gp[t][t + e - 1], bwin[(e - 1) / B][B - 1 - (e - 1) % B], bt);
             }
             beta[t] = bt;
         }
         if (bid == 0 && threadIdx.x == 0)
-            for (int t = 0; t < bb; ++t) A.hist[(int64_t)k * (k - 1) / 2 + j0 + t] = beta[t];
+            for (int t = 0; t < nb; ++t) A.hist[(int64_t)k * (k - 1) / 2 + j0 + t] = beta[t];
 #pragma unroll
         for (int t = 0; t < B; ++t)
 #pragma unroll
@@ -624,13 +652,103 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
 #pragma unroll
         for (int t = 0; t < B; ++t) bwin[0][t] = beta[t];
     };
-    if (nblk > 0) load_block(nxt, 0);
-    for (int s = 0; s < nblk; ++s) {
+    // Exchange reads of the main loop. The first read of every word a step
+    // needs is issued at the top of the step, before that step's direction
+    // loads: a wave's loads complete in issue order, so a word read after
+    // them could only be seen once the next block has arrived. The words are
+    // normally there by then (published at least one step earlier); a word
+    // that is not is read again until it is.
+    // All-to-all: every block reads all block words of phase s - L.
+    // Leader with two exchanges in flight: block 0 gathers phase s - 1 in
+    // step s and publishes its totals, which the other blocks read in step
+    // s + 1 as phase (s + 1) - L; block 0 keeps them for that step. With one
+    // exchange in flight the leader gathers phase s - L in step s.
+    // The number of loads issued does not depend on the block, the phase or
+    // the lane (a block index past the grid reads a valid word, ignored).
+    // Only the B dot-product words are read early; the first exchange's
+    // extra word (||w||^2) is read when it is needed.
+    constexpr int NL = B;                       // words read early
+    constexpr int P = kLagMaxBlocks / kThreads; // block words per thread and word index
+    constexpr bool AHEAD = LEAD && L == 2;
+    const bool gather = !LEAD || bid == 0;
+    const unsigned tot_off = (unsigned)S * kMaxRedBlocks * SW;
+    unsigned long long pw[P][NL];
+    auto nw_of = [&](int g) { return g == 0 ? B + 1 : B; };
+    auto word_addr = [&](int g, int i, int q) -> const unsigned long long* {
+        const unsigned long long ph = g0 + g;
+        const int blk = min((int)threadIdx.x + i * kThreads, G - 1);
+        return gather ? A.slots + ((ph % S) * (unsigned long long)G + blk) * SW + q
+                      : A.slots + tot_off + (ph % S) * SW + q;
+    };
+    auto poll_issue = [&](int g) { // phase g (relative to g0)
 #pragma unroll
-        for (int t = 0; t < B; ++t)
+        for (int i = 0; i < P; ++i)
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) cur[t][j] = nxt[t][j];
-        load_block(nxt, s + 1);  // the next block, or r after the last
+            for (int q = 0; q < NL; ++q)
+                pw[i][q] = __hip_atomic_load(word_addr(g, i, q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // phase g's totals from the words read by poll_issue (the sums of
+    // collect_lag); the leader publishes them
+    auto poll_finish = [&](int g, double (&tot)[SW]) {
+        const unsigned long long ph = g0 + g;
+        const unsigned tag = (unsigned)(ph % 3);
+        const int nw = nw_of(g);
+#pragma unroll
+        for (int q = 0; q < SW; ++q) tot[q] = 0.0;
+        if (gather) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                if ((int)threadIdx.x + i * kThreads < G) {
+#pragma unroll
+                    for (int q = 0; q <= NL; ++q) {
+                        if (q < nw) {
+                            // the extra word of the first exchange was not read early
+                            unsigned long long v = pw[i][q < NL ? q : 0];
+                            if (q == NL || (unsigned)(v & 3ull) != tag)
+                                v = wait_word(word_addr(g, i, q), tag, A.abort_flag);
+                            tot[q] += tag_value(v);
+                        }
+                    }
+                }
+            }
+            bsum_n<SW>(tot, nw, sh);
+            if (LEAD) {
+                unsigned long long* tp = A.slots + tot_off + (ph % S) * SW;
+                if (threadIdx.x == 0)
+                    for (int q = 0; q < SW; ++q)
+                        __hip_atomic_store(tp + q, tag_pack(q < nw ? tot[q] : 0.0, tag), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int q = 0; q < SW; ++q) tot[q] = tag_value(tag_pack(tot[q], tag));
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q <= NL; ++q) {
+                if (q < nw) {
+                    unsigned long long v = pw[0][q < NL ? q : 0];
+                    if (q == NL || (unsigned)(v & 3ull) != tag) v = wait_word(word_addr(g, 0, q), tag, A.abort_flag);
+                    tot[q] = tag_value(v);
+                }
+            }
+        }
+    };
+    double ahead[SW]; // leader with two exchanges in flight: totals gathered one step early
+#pragma unroll
+    for (int q = 0; q < SW; ++q) ahead[q] = 0.0;
+    int ahead_g = -1;
+    // step s, C = s % R: ring[C] holds block s (arriving), ring[C + 1]
+    // receives block s + 1 (or r), ring[C - L] holds block s - L
+    auto step = [&](int s, auto cr) {
+        constexpr int C = decltype(cr)::value;
+        double (&cb)[B][EPT] = ring[C];
+        double (&nb)[B][EPT] = ring[(C + 1) % R];
+        const int pg = (AHEAD && bid == 0) ? s - 1 : s - L; // the phase whose words are read
+        const int fb = s - L;                               // the block finished
+        poll_issue(max(pg, 0));
+        double gp[B][GD];
+        gram_issue(fb, gp);
+        if ((s + 1) * B % (kPtrLds / 2) == 0) ptr_ring_refill(ptab, A.Wp, k, (s + 1) * B);
+        load_block(nb, s + 1);
         double vals[SW];
 #pragma unroll
         for (int i = 0; i < SW; ++i) vals[i] = 0.0;
@@ -638,7 +756,7 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
         for (int t = 0; t < B; ++t) {
             double d = 0.0;
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) d = fma(cur[t][j], w[j], d);
+            for (int j = 0; j < EPT; ++j) d = fma(cb[t][j], w[j], d);
             vals[t] = d;
         }
         if (s == 0) {
@@ -649,25 +767,77 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
         }
         bsum_n<SW>(vals, s == 0 ? B + 1 : B, sh);
         publish_lag<SW, S>(A.slots, G, bid, g0 + s, vals, s == 0 ? B + 1 : B);
-        if (s >= L) finish_block(s - L, old[L - 1]);
+        if (pg >= 0) {
+            double tot[SW];
+            poll_finish(pg, tot);
+            if (AHEAD && bid == 0) {
+                // finish block s - L with the totals gathered in the previous step
+                if (fb >= 0) finish_block(fb, ahead, gp, ring[(C + R - L) % R]);
 #pragma unroll
-        for (int h = H - 1; h > 0; --h)
-#pragma unroll
-            for (int t = 0; t < B; ++t)
-#pragma unroll
-                for (int j = 0; j < EPT; ++j) old[h][t][j] = old[h - 1][t][j];
+                for (int q = 0; q < SW; ++q) ahead[q] = tot[q];
+                ahead_g = pg;
+            } else {
+                finish_block(fb, tot, gp, ring[(C + R - L) % R]);
+            }
+        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    static_assert(R == 3 || R == 4, "ring of three or four blocks");
+    load_block(ring[0], 0); // block 0, or r when there is no direction
+    int s = 0;
+    for (; s + R <= nblk; s += R) {
+        step(s, I0{});
+        step(s + 1, I1{});
+        step(s + 2, I2{});
+        if constexpr (R == 4) step(s + 3, I3{});
+    }
+    if (s < nblk) step(s, I0{});
+    if (s + 1 < nblk) step(s + 1, I1{});
+    if constexpr (R == 4)
+        if (s + 2 < nblk) step(s + 2, I2{});
+    // rotate the ring so that r is in ring[0] and block nblk - 1 - h in
+    // ring[R - 1 - h] (one uniform selection per entry, no indexed registers)
+    {
+        const int rot = nblk % R;
 #pragma unroll
         for (int t = 0; t < B; ++t)
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) old[0][t][j] = cur[t][j];
-    }
-    if (nblk == 0) load_block(nxt, 0); // r
-    // drain: the last min(L, nblk) blocks, oldest first (old[h] = block nblk-1-h)
+            for (int j = 0; j < EPT; ++j) {
+                double v[R];
 #pragma unroll
-    for (int h = L - 1; h >= 0; --h)
-        if (nblk - 1 - h >= 0) finish_block(nblk - 1 - h, old[h]);
+                for (int i = 0; i < R; ++i) v[i] = ring[i][t][j];
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    double x = v[i];
+#pragma unroll
+                    for (int q = 1; q < R; ++q)
+                        if (rot == q) x = v[(i + q) % R];
+                    ring[i][t][j] = x;
+                }
+            }
+    }
+    double (&nxt)[B][EPT] = ring[0]; // r
+    // drain: the last min(L, nblk) blocks, oldest first (block nblk-1-h in ring[R-1-h])
+#pragma unroll
+    for (int h = L - 1; h >= 0; --h) {
+        const int b2 = nblk - 1 - h;
+        if (b2 >= 0) {
+            double tot[SW], gp[B][GD];
+            gram_issue(b2, gp);
+            if (AHEAD && bid == 0 && b2 == ahead_g) {
+#pragma unroll
+                for (int q = 0; q < SW; ++q) tot[q] = ahead[q];
+            } else {
+                collect_lag<SW, LEAD, S>(A.slots, G, bid, g0 + b2, nw_of(b2), tot, sh, A.abort_flag);
+            }
+            finish_block(b2, tot, gp, ring[R - 1 - h]);
+        }
+    }
     // the orthogonalised w: ||w||^2, w.r and its dots with the held directions
-    // (old[h][t] = direction (nblk-1-h) B + t)
+    // (ring[R-1-h][t] = direction (nblk-1-h) B + t)
     double vals[SW];
     {
         double s2 = 0.0, q = 0.0;
@@ -684,7 +854,7 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
             for (int t = 0; t < B; ++t) {
                 double d = 0.0;
 #pragma unroll
-                for (int j = 0; j < EPT; ++j) d = fma(old[h][t][j], w[j], d);
+                for (int j = 0; j < EPT; ++j) d = fma(ring[R - 1 - h][t][j], w[j], d);
                 vals[2 + h * B + t] = d;
             }
 #pragma unroll
@@ -717,7 +887,7 @@ __device__ __forceinline__ void rm_body_lag(const RmArgs& A, const int G, const 
             A.alphas[k] = alpha;
             A.gammas[k] = gamma;
             for (int d = 1; d <= kGramStride; ++d) A.gram[(int64_t)k * kGramStride + d - 1] = 0.0;
-            // W_k . W_m = gamma (w . old[h][t]) for the held directions m < k
+            // W_k . W_m = gamma (w . ring[R-1-h][t]) for the held directions m < k
 #pragma unroll
             for (int h = 0; h < H; ++h)
 #pragma unroll
@@ -1398,6 +1568,7 @@ int rm_persistent_candidates(int64_t N, RmConfig* out, int cap) {
         const int64_t need = (N + per - 1) / per;
         if (pass == 0 ? need > 512 : (need <= 512 || need > kMaxRedBlocks)) return;
         if (nc && need > cw_max_blocks(b)) return;
+        if (lag && need > kLagMaxBlocks) return;
         const void* f = lag ? pick_lag(e, b, lag, lead) : pick(e, b, lead, false, nc);
         if (!f) return;
         hipFuncAttributes fa;

@@ -1,10 +1,12 @@
 """The persistent residual-minimisation kernel (Algorithm 1 after w = A z) in
 every co-resident launch configuration (entries per thread, directions per
-grid exchange, exchange form, exchange wave, grid) against the sequential
-modified Gram-Schmidt step written out in numpy (FP64): MGS coefficients
-beta_i = W_i . w (w updated after each), gamma = 1/||w||, the new direction
-gamma w, alpha = w_k . r and the updated residual. k covers no direction,
-fewer directions than one exchange block, and partial last blocks. The
+grid exchange, exchange form, exchange wave, lag, grid) against the
+sequential modified Gram-Schmidt step written out in numpy (FP64): MGS
+coefficients beta_i = W_i . w (w updated after each), gamma = 1/||w||, the
+new direction gamma w, alpha = w_k . r and the updated residual. k covers no
+direction, fewer directions than one exchange block, partial last blocks,
+and (on the smallest level) more directions than the kernel's pointer table
+holds at once. The
 exchange-wave form with four compute waves sums in the same order as the
 plain form, so the two are compared bit for bit."""
 import numpy as np
@@ -50,7 +52,8 @@ def test_rm_step_every_configuration(n, p):
     rng = np.random.default_rng(7)
     configs = g.rm_configs(0)
     assert configs, "finest level uses the persistent kernel"
-    for k in (0, 1, 4, 7, 40):
+    # 1100 directions: the lagged form's pointer ring is refilled twice
+    for k in (0, 1, 4, 7, 40) + ((1100,) if n == 8 else ()):
         W = np.linalg.qr(rng.standard_normal((N, k)))[0].T.copy() if k else np.zeros((0, N))
         w = rng.standard_normal(N)
         z = rng.standard_normal(N)

@@ -164,19 +164,45 @@ def test_fullsize_rm_step_every_configuration(big):
             assert (rn_g - rn_d).abs().max().item() <= 1e-12 * rscale, what
 
 
+def _visit_divergence(log_a, log_b):
+    """Per visit, while the two logs agree on (level, iterations): the
+    largest difference of the residual ratios ||r_i|| / ||r_0|| (and, on the
+    finest level, of ||r_0|| itself, relative)."""
+    dq = []
+    for (la, ia, r0a, ra), (lb, ib, r0b, rb) in zip(log_a, log_b):
+        if (la, ia) != (lb, ib):
+            break
+        dq.append(max(abs(r0a / r0b - 1) if la == 0 else 0.0, np.abs(ra / r0a - rb / r0b).max(initial=0.0)))
+    return np.array(dq)
+
+
 def test_fullsize_replay_matches_oracle_golden(big):
     """The 64^3 P2 plain-method solve (2+2 block-Jacobi sweeps, tolerance
-    1e-10, b from seed 0) with the oracle's visit log imposed on the GPU
-    (the oracle's solve of this workload is written by
-    tests/golden/make_oracle_64cubed_p2.py): every per-visit residual ratio
-    within 1e-9 of the oracle's, the solution within 1e-9 relative at
-    65,536 sampled entries and in ||x||, x.b and x.u."""
+    1e-10, b from seed 0) with the oracle's visit log imposed on the GPU,
+    against the oracle's solve of this workload
+    (tests/golden/make_oracle_64cubed_p2.py).
+
+    At this size two correct runs of the method do not agree to 1e-9: the
+    same oracle with b perturbed by 1e-15 relative (the --perturb solve of
+    the same script) follows the same visit sequence but its per-visit
+    residual ratios drift from the unperturbed ones from visit ~125 on
+    (1e-12), pass 1e-9 at visit ~380 and reach 0.58; it stops after 241
+    cycles instead of 256 and its solution differs by 1.1e-8 at the sampled
+    entries. The GPU's rounding differs from the oracle's at every reduction,
+    so the bar is that envelope: the running maximum of the GPU's per-visit
+    divergence from the oracle stays within 10x that of the perturbed
+    oracle (plus 1e-12), and the solution differences stay within 5x the
+    perturbed oracle's. Same visits, cycles and directions;
+    true residual within 2e-10 after the oracle's 256 cycles."""
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_64cubed_p2.npz")
-    if not os.path.exists(path):
-        pytest.skip("golden file not generated (tests/golden/make_oracle_64cubed_p2.py)")
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    path = os.path.join(here, "oracle_64cubed_p2.npz")
+    path_p = os.path.join(here, "oracle_64cubed_p2_perturbed.npz")
+    if not (os.path.exists(path) and os.path.exists(path_p)):
+        pytest.skip("golden files not generated (tests/golden/make_oracle_64cubed_p2.py [--perturb])")
     gd = np.load(path, allow_pickle=False)
+    gp = np.load(path_p, allow_pickle=False)
     rep_o = json.loads(str(gd["report"]))
     prob, nu, o, g = big
     b = synth.rhs(prob.n_dofs, 0)
@@ -191,11 +217,17 @@ def test_fullsize_replay_matches_oracle_golden(big):
     assert rep["iters_fine"] == rep_o["iters_fine"] and rep["n_dirs_fine"] == rep_o["n_dirs_fine"]
     log_o = oracle.parse_visit_norms(gd["vnorm"])
     log_g = g.visit_norms()
-    assert len(log_o) == len(log_g)
-    dq = 0.0
-    for (lg, ig, r0g, rg), (lo, io, r0o, ro) in zip(log_g, log_o):
-        assert (lg, ig) == (lo, io)
-        dq = max(dq, abs(r0g / r0o - 1) if lg == 0 else 0.0, np.abs(rg / r0g - ro / r0o).max(initial=0.0))
+    assert [(l, i) for l, i, _, _ in log_g] == [(l, i) for l, i, _, _ in log_o]
+    d_g = _visit_divergence(log_g, log_o)
+    d_p = _visit_divergence(oracle.parse_visit_norms(gp["vnorm"]), log_o)
+    n = len(d_p)
+    env_g = np.maximum.accumulate(d_g[:n])
+    env_p = np.maximum.accumulate(d_p)
+    worst = int(np.argmax(env_g / (env_p + 1e-12)))
+    say(f"per-visit divergence: GPU first > 1e-9 at visit {int(np.argmax(d_g > 1e-9))}, perturbed oracle at "
+        f"{int(np.argmax(d_p > 1e-9))}; largest envelope ratio {env_g[worst] / (env_p[worst] + 1e-12):.2f} "
+        f"at visit {worst}")
+    assert np.all(env_g <= 10 * env_p + 1e-12)
     idx = gd["idx"]
     xs = gd["x_idx"]
     e_s = np.linalg.norm(x[idx] - xs) / np.linalg.norm(xs)
@@ -205,10 +237,14 @@ def test_fullsize_replay_matches_oracle_golden(big):
     # |x.v - x*.v| <= ||x - x*|| ||v|| (Cauchy-Schwarz): relative to ||x*|| ||v||
     e_b = abs(x @ b - float(gd["x_dot_b"])) / (xn * np.linalg.norm(b))
     e_u = abs(x @ u - float(gd["x_dot_u"])) / (xn * np.linalg.norm(u))
-    say(f"max per-visit ratio difference {dq:.2e}; sampled solution {e_s:.2e}, ||x|| {e_n:.2e}, "
-        f"x.b {e_b:.2e}, x.u {e_u:.2e}; true residual {rep['rel_res_true']:.3e}")
-    assert dq <= 1e-9
-    assert e_s <= 1e-9 and e_n <= 1e-9 and e_b <= 1e-9 and e_u <= 1e-9
+    p_s = np.linalg.norm(gp["x_idx"] - xs) / np.linalg.norm(xs)
+    p_n = abs(float(gp["x_norm"]) / xn - 1)
+    p_u = abs(float(gp["x_dot_u"]) - float(gd["x_dot_u"])) / (xn * np.linalg.norm(u))
+    say(f"solution vs oracle: sampled {e_s:.2e} (perturbed oracle {p_s:.2e}), ||x|| {e_n:.2e} ({p_n:.2e}), "
+        f"x.u {e_u:.2e} ({p_u:.2e}), x.b {e_b:.2e}; true residual {rep['rel_res_true']:.3e}")
+    # | ||x|| - ||x*|| | <= ||x - x*||: the norm is held to the sampled bound
+    assert e_s <= 5 * p_s and e_n <= 5 * p_s and e_u <= 5 * p_u and e_b <= 5 * p_u
+    assert rep["rel_res_true"] <= 2e-10
 
 
 def test_fullsize_solve_true_residual(big):

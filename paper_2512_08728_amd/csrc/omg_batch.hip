@@ -259,8 +259,9 @@ omg_status refresh_rm_table(Group& g, int l) {
 
 // Launch configuration of member c's RM in a batched launch at level l.
 // The multi-column kernel has the plain exchange form only (no exchange wave,
-// no lag): a tuned lagged or exchange-wave configuration contributes its
-// grid, entries per thread, block and exchange form.
+// no lag): a tuned exchange-wave configuration contributes its grid, entries
+// per thread, block and exchange form (the two forms sum in the same order);
+// members tuned to the lagged form are not batched (rm_b).
 inline RmConfig member_config(const Group& g, int c, int l) {
     RmConfig r = g.shared ? g.P->lev[l].rmc_multi : g.col[c]->lev[l].rmc;
     r.cw = 0;
@@ -337,6 +338,10 @@ omg_status rm_b(Group& g, const std::vector<int>& act, int l, bool zcor) {
         omg_solver* s = g.col[act[i]];
         bool ok = LV(s, l).persist && g.P->babort && !g.P->batch_rm_off;
         if (ok && g.shared) ok = g.P->lev[l].rmc_multi_m > 0;
+        // an instance whose level is tuned to the lagged form keeps its own
+        // launch: the multi-column kernel's plain form sums in another order,
+        // and each instance must equal its own omg_solve bit for bit
+        if (ok && !g.shared) ok = LV(s, l).rmc.lag == 0;
         if (ok) {
             const RmConfig c = member_config(g, act[i], l);
             ok = c.G <= rm_multi_capacity(c.ept, c.B, c.lead);

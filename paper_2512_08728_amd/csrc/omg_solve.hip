@@ -23,6 +23,7 @@
 
 #include <atomic>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <thread>
 
@@ -392,18 +393,22 @@ static omg_status ensure_dir(omg_solver* s, Level& L, int k);
 // of that size then runs the same arithmetic, and results do not depend on
 // which solver was timed.
 static std::mutex g_rm_mu;
-static std::map<std::pair<int, int64_t>, RmConfig> g_rm_cache;
+// keyed by (device, level size, stored directions the tuner times with): a
+// level of the same size deep in one hierarchy (a few directions per visit)
+// and finest in another (hundreds) need not share a configuration
+static std::map<std::tuple<int, int64_t, int>, RmConfig> g_rm_cache;
 
 // Tuning record file (JSON lines, path in the environment variable
 // OMG_RM_TUNE_FILE): one line per (device architecture, compute units, level
-// size) with the configuration the tuner chose and its time. A level whose
-// size has a record uses that configuration (if it is still co-resident)
-// without timing, so that every process on that device kind runs the same
-// arithmetic; a newly tuned size is appended.
+// size, stored directions timed with) with the configuration the tuner chose
+// and its time. A level with a record uses that configuration (if it is
+// still co-resident) without timing, so that every process on that device
+// kind runs the same arithmetic; a newly tuned level is appended.
 struct TuneRecord {
     std::string arch;
     int cus = 0;
     int64_t N = 0;
+    int k = 0;
     RmConfig c;
 };
 static std::vector<TuneRecord> g_tune_file;
@@ -435,9 +440,9 @@ static void tune_file_load() { // under g_rm_mu
         TuneRecord r;
         long long n = 0;
         if (std::sscanf(line,
-                        " {\"arch\": \"%63[^\"]\", \"cus\": %d, \"N\": %lld, \"G\": %d, \"ept\": %d, \"B\": %d, "
-                        "\"lead\": %d, \"cw\": %d, \"lag\": %d",
-                        arch, &r.cus, &n, &r.c.G, &r.c.ept, &r.c.B, &r.c.lead, &r.c.cw, &r.c.lag) == 9) {
+                        " {\"arch\": \"%63[^\"]\", \"cus\": %d, \"N\": %lld, \"k\": %d, \"G\": %d, \"ept\": %d, "
+                        "\"B\": %d, \"lead\": %d, \"cw\": %d, \"lag\": %d",
+                        arch, &r.cus, &n, &r.k, &r.c.G, &r.c.ept, &r.c.B, &r.c.lead, &r.c.cw, &r.c.lag) == 10) {
             r.arch = arch;
             r.N = n;
             g_tune_file.push_back(r);
@@ -446,24 +451,27 @@ static void tune_file_load() { // under g_rm_mu
     std::fclose(f);
 }
 
-static void tune_file_append(const std::string& arch, int cus, int64_t N, const RmConfig& c, double us) {
+static void tune_file_append(const std::string& arch, int cus, int64_t N, int k, const RmConfig& c, double us) {
     const char* path = tune_path();
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
     std::fprintf(f,
-                 "{\"arch\": \"%s\", \"cus\": %d, \"N\": %lld, \"G\": %d, \"ept\": %d, \"B\": %d, \"lead\": %d, "
-                 "\"cw\": %d, \"lag\": %d, \"us\": %.1f}\n",
-                 arch.c_str(), cus, (long long)N, c.G, c.ept, c.B, c.lead, c.cw, c.lag, us);
+                 "{\"arch\": \"%s\", \"cus\": %d, \"N\": %lld, \"k\": %d, \"G\": %d, \"ept\": %d, \"B\": %d, "
+                 "\"lead\": %d, \"cw\": %d, \"lag\": %d, \"us\": %.1f}\n",
+                 arch.c_str(), cus, (long long)N, k, c.G, c.ept, c.B, c.lead, c.cw, c.lag, us);
     std::fclose(f);
-    g_tune_file.push_back(TuneRecord{arch, cus, N, c});
+    g_tune_file.push_back(TuneRecord{arch, cus, N, k, c});
 }
 
 static omg_status tune_rm(omg_solver* s, int l) {
     Level& L = s->lev[l];
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
-    const std::pair<int, int64_t> key(dev, L.N);
+    // the tuner times RM with kt stored directions: half the level's
+    // direction capacity, at most 256
+    const int kt = std::max(1, std::min((L.ucap - 1) / 2, 256));
+    const std::tuple<int, int64_t, int> key(dev, L.N, kt);
     std::string arch;
     int cus = 0;
     device_kind(dev, arch, cus);
@@ -478,7 +486,7 @@ static omg_status tune_rm(omg_solver* s, int l) {
         }
         tune_file_load();
         for (const TuneRecord& r : g_tune_file) {
-            if (r.arch != arch || r.cus != cus || r.N != L.N) continue;
+            if (r.arch != arch || r.cus != cus || r.N != L.N || r.k != kt) continue;
             for (int q = 0; q < nc; ++q)
                 if (c[q].G == r.c.G && c[q].ept == r.c.ept && c[q].B == r.c.B && c[q].lead == r.c.lead &&
                     c[q].cw == r.c.cw && c[q].lag == r.c.lag) {
@@ -493,7 +501,6 @@ static omg_status tune_rm(omg_solver* s, int l) {
         g_rm_cache.emplace(key, L.rmc);
         return OMG_OK;
     }
-    const int kt = std::max(1, std::min((L.ucap - 1) / 2, 256));
     OMG_TRY(ensure_dir(s, L, kt));
     if ((int)L.W.size() <= kt || (int)L.dcap <= kt) return OMG_EINVAL;
     hipStream_t st = s->stream;
@@ -570,7 +577,7 @@ static omg_status tune_rm(omg_solver* s, int l) {
     if (flags[1]) return OMG_EHIP; // a bounded wait expired
     std::lock_guard<std::mutex> lk(g_rm_mu);
     auto ins = g_rm_cache.emplace(key, c[bi]); // first tuner of this size wins
-    if (ins.second) tune_file_append(arch, cus, L.N, c[bi], 1e3 * best / 3);
+    if (ins.second) tune_file_append(arch, cus, L.N, kt, c[bi], 1e3 * best / 3);
     L.rmc = ins.first->second;
     return OMG_OK;
 }

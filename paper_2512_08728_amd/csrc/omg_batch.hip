@@ -258,14 +258,15 @@ omg_status refresh_rm_table(Group& g, int l) {
 }
 
 // Launch configuration of member c's RM in a batched launch at level l.
-// The multi-column kernel has the plain exchange form only (no exchange wave,
-// no lag): a tuned exchange-wave configuration contributes its grid, entries
-// per thread, block and exchange form (the two forms sum in the same order);
-// members tuned to the lagged form are not batched (rm_b).
+// The multi-column kernels have no exchange wave: a tuned exchange-wave
+// configuration contributes its grid, entries per thread, block and exchange
+// form (the two forms sum in the same order). A lagged configuration keeps
+// its lag (the multi-column lagged kernel), so that an instance runs the
+// arithmetic of its own solve.
 inline RmConfig member_config(const Group& g, int c, int l) {
     RmConfig r = g.shared ? g.P->lev[l].rmc_multi : g.col[c]->lev[l].rmc;
     r.cw = 0;
-    r.lag = 0;
+    if (g.shared) r.lag = 0;
     return r;
 }
 
@@ -289,7 +290,7 @@ omg_status rm_multi(Group& g, const std::vector<int>& act, int l, bool zcor) {
     for (size_t i0 = 0; i0 < act.size(); ++i0) {
         if (done[i0]) continue;
         const RmConfig c0 = cfg[i0];
-        const int cap = rm_multi_capacity(c0.ept, c0.B, c0.lead);
+        const int cap = rm_multi_capacity(c0.ept, c0.B, c0.lead, c0.lag);
         RmMulti M;
         std::memset(&M, 0, sizeof(M));
         M.tab = P->btab[l];
@@ -300,7 +301,9 @@ omg_status rm_multi(Group& g, const std::vector<int>& act, int l, bool zcor) {
         std::vector<int> members;
         int blocks = 0;
         for (size_t i = i0; i < act.size() && M.ncol < kMaxCols; ++i) {
-            if (done[i] || cfg[i].ept != c0.ept || cfg[i].B != c0.B || cfg[i].lead != c0.lead) continue;
+            if (done[i] || cfg[i].ept != c0.ept || cfg[i].B != c0.B || cfg[i].lead != c0.lead ||
+                cfg[i].lag != c0.lag)
+                continue;
             if (M.ncol > 0 && blocks + cfg[i].G > cap) continue;
             HIP_OK(prepare_slots(LV(g.col[act[i]], l), cfg[i], g.st));
             M.idx[M.ncol] = act[i];
@@ -313,7 +316,7 @@ omg_status rm_multi(Group& g, const std::vector<int>& act, int l, bool zcor) {
         }
         M.blk0[M.ncol] = blocks;
         if (blocks > cap) return OMG_EINVAL; // a single member larger than the device
-        HIP_OK(launch_rm_multi(c0.ept, c0.B, c0.lead, M, g.st));
+        HIP_OK(launch_rm_multi(c0.ept, c0.B, c0.lead, c0.lag, M, g.st));
         P->kcount[OMG_K_RMP][l]++;
         for (int i : members) {
             Level& L = LV(g.col[act[i]], l);
@@ -338,13 +341,9 @@ omg_status rm_b(Group& g, const std::vector<int>& act, int l, bool zcor) {
         omg_solver* s = g.col[act[i]];
         bool ok = LV(s, l).persist && g.P->babort && !g.P->batch_rm_off;
         if (ok && g.shared) ok = g.P->lev[l].rmc_multi_m > 0;
-        // an instance whose level is tuned to the lagged form keeps its own
-        // launch: the multi-column kernel's plain form sums in another order,
-        // and each instance must equal its own omg_solve bit for bit
-        if (ok && !g.shared) ok = LV(s, l).rmc.lag == 0;
         if (ok) {
             const RmConfig c = member_config(g, act[i], l);
-            ok = c.G <= rm_multi_capacity(c.ept, c.B, c.lead);
+            ok = c.G <= rm_multi_capacity(c.ept, c.B, c.lead, c.lag);
         }
         if (ok) multi.push_back(act[i]);
         else OMG_TRY(engine_rm_apply(s, l, Z.p[i], g.st));

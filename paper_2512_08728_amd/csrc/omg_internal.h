@@ -374,8 +374,8 @@ struct RmMulti {
     int blk0[kMaxCols + 1];            // block range of column q
     unsigned long long g0[kMaxCols];   // first exchange phase of column q
 };
-int rm_multi_capacity(int ept, int B, int lead);
-hipError_t launch_rm_multi(int ept, int B, int lead, const RmMulti& M, hipStream_t st);
+int rm_multi_capacity(int ept, int B, int lead, int lag = 0);
+hipError_t launch_rm_multi(int ept, int B, int lead, int lag, const RmMulti& M, hipStream_t st);
 
 // co-resident configurations for N entries, most preferred first; returns the count
 constexpr int kMaxRmConfigs = 192;

@@ -909,15 +909,10 @@ __global__ __launch_bounds__(kThreads) void k_rm_lag(RmArgs A) {
     rm_body_lag<EPT, B, L, LEAD>(A, gridDim.x, blockIdx.x, sh, ptab);
 }
 
-// RM of several vector sets (columns of a batched solve, or independent
-// solvers of one level configuration) in one launch: column q owns blocks
-// [blk0[q], blk0[q+1]) and exchanges only among them, with its own words,
-// phase and storage (table entry idx[q]); all columns share k.
-template <int EPT, int B, bool LEAD>
-__global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
-    __shared__ double sh[kMaxVals * (kThreads / 64)];
-    __shared__ unsigned long long ptab[kPtrLds];
-    int q = 0;
+// Column q of a multi-column launch (the column whose block range holds this
+// block) and its RM arguments.
+__device__ __forceinline__ RmArgs multi_args(const RmMulti& M, int& q) {
+    q = 0;
     while (q + 1 < M.ncol && (int)blockIdx.x >= M.blk0[q + 1]) ++q;
     const RmCol& C = M.tab[M.idx[q]];
     RmArgs A;
@@ -939,8 +934,33 @@ __global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
     A.gammas = C.gammas;
     A.alphas = C.alphas;
     A.gram = C.gram;
+    return A;
+}
+
+// RM of several vector sets (columns of a batched solve, or independent
+// solvers of one level configuration) in one launch: column q owns blocks
+// [blk0[q], blk0[q+1]) and exchanges only among them, with its own words,
+// phase and storage (table entry idx[q]); all columns share k.
+template <int EPT, int B, bool LEAD>
+__global__ __launch_bounds__(kThreads) void k_rm_multi(RmMulti M) {
+    __shared__ double sh[kMaxVals * (kThreads / 64)];
+    __shared__ unsigned long long ptab[kPtrLds];
+    int q = 0;
+    const RmArgs A = multi_args(M, q);
     rm_body<EPT, B, LEAD>(A, M.blk0[q + 1] - M.blk0[q], (int)blockIdx.x - M.blk0[q], sh, ptab);
 }
+
+// The lagged form of the same (every column tuned to this lagged
+// configuration, so that each column runs the arithmetic of its own solve).
+template <int EPT, int B, int L, bool LEAD>
+__global__ __launch_bounds__(kThreads) void k_rm_multi_lag(RmMulti M) {
+    __shared__ double sh[kRmLagWords * (kThreads / 64)];
+    __shared__ unsigned long long ptab[kPtrLds];
+    int q = 0;
+    const RmArgs A = multi_args(M, q);
+    rm_body_lag<EPT, B, L, LEAD>(A, M.blk0[q + 1] - M.blk0[q], (int)blockIdx.x - M.blk0[q], sh, ptab);
+}
+
 
 // ---------------------------------------------------------------------------
 // Exchange-wave form of the same kernel. The vector memory reads of one wave
@@ -1489,36 +1509,39 @@ static const void* pick(int ept, int b, int lead, bool multi = false, int nc = 0
 // two or four directions per exchange with one in flight for the small,
 // exchange-bound levels.
 template <int EPT, int B, int L>
-static const void* lag_kernel(int lead) {
+static const void* lag_kernel(int lead, bool multi) {
+    if (multi)
+        return lead ? reinterpret_cast<const void*>(&k_rm_multi_lag<EPT, B, L, true>)
+                    : reinterpret_cast<const void*>(&k_rm_multi_lag<EPT, B, L, false>);
     return lead ? reinterpret_cast<const void*>(&k_rm_lag<EPT, B, L, true>)
                 : reinterpret_cast<const void*>(&k_rm_lag<EPT, B, L, false>);
 }
-static const void* pick_lag(int ept, int b, int lag, int lead) {
+static const void* pick_lag(int ept, int b, int lag, int lead, bool multi = false) {
     if (b == 1 && lag == 2) {
         switch (ept) {
-        case 8: return lag_kernel<8, 1, 2>(lead);
-        case 10: return lag_kernel<10, 1, 2>(lead);
-        case 16: return lag_kernel<16, 1, 2>(lead);
-        case 20: return lag_kernel<20, 1, 2>(lead);
+        case 8: return lag_kernel<8, 1, 2>(lead, multi);
+        case 10: return lag_kernel<10, 1, 2>(lead, multi);
+        case 16: return lag_kernel<16, 1, 2>(lead, multi);
+        case 20: return lag_kernel<20, 1, 2>(lead, multi);
         }
     } else if (b == 1 && lag == 1) {
         switch (ept) {
-        case 8: return lag_kernel<8, 1, 1>(lead);
-        case 10: return lag_kernel<10, 1, 1>(lead);
-        case 16: return lag_kernel<16, 1, 1>(lead);
-        case 20: return lag_kernel<20, 1, 1>(lead);
+        case 8: return lag_kernel<8, 1, 1>(lead, multi);
+        case 10: return lag_kernel<10, 1, 1>(lead, multi);
+        case 16: return lag_kernel<16, 1, 1>(lead, multi);
+        case 20: return lag_kernel<20, 1, 1>(lead, multi);
         }
     } else if (b == 2 && lag == 1) {
         switch (ept) {
-        case 2: return lag_kernel<2, 2, 1>(lead);
-        case 4: return lag_kernel<4, 2, 1>(lead);
-        case 8: return lag_kernel<8, 2, 1>(lead);
+        case 2: return lag_kernel<2, 2, 1>(lead, multi);
+        case 4: return lag_kernel<4, 2, 1>(lead, multi);
+        case 8: return lag_kernel<8, 2, 1>(lead, multi);
         }
     } else if (b == 4 && lag == 1) {
         switch (ept) {
-        case 1: return lag_kernel<1, 4, 1>(lead);
-        case 2: return lag_kernel<2, 4, 1>(lead);
-        case 4: return lag_kernel<4, 4, 1>(lead);
+        case 1: return lag_kernel<1, 4, 1>(lead, multi);
+        case 2: return lag_kernel<2, 4, 1>(lead, multi);
+        case 4: return lag_kernel<4, 4, 1>(lead, multi);
         }
     }
     return nullptr;
@@ -1531,9 +1554,9 @@ static int rm_block_threads(int nc) { return nc ? 64 * (nc + 1) : kThreads; }
 static int rm_compute_threads(int nc) { return nc ? 64 * nc : kThreads; }
 
 // Blocks of the multi-column kernel in this configuration that fit at once.
-int rm_multi_capacity(int ept, int B, int lead) {
+int rm_multi_capacity(int ept, int B, int lead, int lag) {
     int dev = 0, cus = 0, per_cu = 0;
-    const void* f = pick(ept, B, lead, true);
+    const void* f = lag ? pick_lag(ept, B, lag, lead, true) : pick(ept, B, lead, true);
     hipFuncAttributes fa;
     if (!f || hipFuncGetAttributes(&fa, f) != hipSuccess || fa.localSizeBytes > 0) return 0; // see candidates
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1543,8 +1566,8 @@ int rm_multi_capacity(int ept, int B, int lead) {
     return per_cu * cus;
 }
 
-hipError_t launch_rm_multi(int ept, int B, int lead, const RmMulti& M, hipStream_t st) {
-    const void* f = pick(ept, B, lead, true);
+hipError_t launch_rm_multi(int ept, int B, int lead, int lag, const RmMulti& M, hipStream_t st) {
+    const void* f = lag ? pick_lag(ept, B, lag, lead, true) : pick(ept, B, lead, true);
     if (!f || M.ncol < 1 || M.ncol > kMaxCols) return hipErrorInvalidValue;
     RmMulti a = M;
     void* params[] = {&a};

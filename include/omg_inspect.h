@@ -51,9 +51,9 @@ enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
 /* Launch configurations the autotuners chose on a level, host shapes[18]:
  * [0..11] the multi-right-hand-side kernels (tuned on the first batched
  * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
- * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..5 is
- * (wavefronts per block, 16-column tiles per wavefront) = (4,2), (2,2),
- * (1,2), (4,1), (2,1), (1,1); -1 = not tuned. [12..16] the persistent
+ * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..1 is the
+ * number of consecutive cells a block of four wavefronts handles for all
+ * columns: 16, 8; -1 = not tuned. [12..16] the persistent
  * residual-minimisation kernel (tuned at setup): blocks, vector entries per
  * thread, directions per grid exchange, exchange form (0 all-to-all, 1
  * leader block), compute waves per block of the exchange-wave form (0:

@@ -3,12 +3,12 @@
 // With many right-hand sides on one operator, the block products Y = A X,
 // T = R - A X and D^-1 T become small dense products per cell,
 // (bs x bs) x (bs x nrhs), and the coarsest-level solve becomes a dense
-// (N x N) x (N x nrhs) product. One wavefront handles one cell for up to
-// kMaxCols = 32 right-hand sides (two 16-wide tiles) with the FP64
-// instruction V_MFMA_F64_16X16X4F64 (C[16x16] += A[16x4] B[4x16]; the FP32
-// variant for the mixed-precision inner solve). bs <= 16 rows/columns are
-// padded with zeros; the operator block is read once per cell for all
-// right-hand sides, which divides the operator traffic of a sweep by nrhs.
+// (N x N) x (N x nrhs) product. Each (cell, 16-column tile) product runs on
+// the FP64 instruction V_MFMA_F64_16X16X4F64 (C[16x16] += A[16x4] B[4x16];
+// the FP32 variant for the mixed-precision inner solve) for up to kMaxCols =
+// 32 right-hand sides; bs <= 16 rows/columns are padded with zeros; the
+// operator block is read once per cell for all right-hand sides, which
+// divides the operator traffic of a sweep by nrhs.
 //
 // Operand layout (64 lanes): the A element of lane l is (row l%16, k l/16),
 // the B element is (k l/16, column l%16); the FP64 result of lane l, register
@@ -43,208 +43,278 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int l, int i) { return 4 * (l >> 4) + i; }
 };
 
-// Tile shape of a launch (chosen per level and column count by the
-// autotuner below): WAVES wavefronts per block, and TPW 16-column tiles per
-// wavefront (TPW = 2: one wavefront covers both tiles of a cell and loads
-// each operator block once; TPW = 1: one wavefront per (cell, tile), twice
-// the wavefronts for the same work).
-struct WaveTask {
-    int cell, tb, nt; // cell, first tile, tiles of this wavefront
-};
-template <int WAVES, int TPW>
-__device__ __forceinline__ bool wave_task(int n, int nr, WaveTask& w) {
-    const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
-    const int ntile = (nr + 15) >> 4;
-    if (TPW == 2) {
-        w.cell = wave;
-        w.tb = 0;
-        w.nt = ntile;
-    } else {
-        w.cell = wave / ntile;
-        w.tb = wave % ntile;
-        w.nt = 1;
-    }
-    return w.cell < n;
+// Cell tiles. A block of four wavefronts handles CT consecutive cells for
+// all nr columns. Every right-hand side is its own component-major vector,
+// so a lane-per-(column, component) access pattern would touch one 8-byte
+// entry per cache line; instead the vector entries of a tile move between
+// HBM and the block's LDS with consecutive lanes on consecutive cells of one
+// (column, component) (CT * 8 contiguous bytes per row, neighbour cells of a
+// structured grid are consecutive too), the matrix-core products read their
+// B operand from LDS, and their results return to LDS before the same kind
+// of coalesced store. Wavefront w computes cells w CT/4 .. (w+1) CT/4 - 1;
+// per (cell, 16-column tile) the products are accumulated in the order of
+// the block row (slot), then of the component steps of 4.
+constexpr int kTileWaves = 4;
+
+// Tile of this block. Blocks are dispatched to the eight XCDs in turn, each
+// XCD with its own L2; tiles are handed out so that the blocks of one XCD
+// take one contiguous range of cells, and the neighbour entries a tile reads
+// were mostly read by that XCD's previous tiles (a bijection for any grid,
+// whatever the dispatch order: only the cache reuse depends on it).
+__device__ __forceinline__ int tile_of_block() {
+    constexpr int X = 8;
+    const int g = gridDim.x, b = blockIdx.x;
+    const int q = g / X, r = g % X, x = b % X, i = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
-// Y[c] = A X[c], or Y[c] = B[c] - A X[c] when hasB (columns c < nr).
-// Ablk: [n][width][BS][BS] (type MT).
-template <int BS, typename MT, bool hasB, int WAVES, int TPW>
-__global__ __launch_bounds__(64 * WAVES) void k_spmv_mr(int n, int width, const int* __restrict__ col,
-                                                        const MT* __restrict__ Ablk, int nr, ColPtrs X, ColPtrs B,
-                                                        ColPtrs Y) {
-    using M = Mfma<MT>;
-    using AT = typename M::acc;
-    const int l = threadIdx.x & 63;
-    WaveTask wt;
-    if (!wave_task<WAVES, TPW>(n, nr, wt)) return; // whole wavefront
-    const int cell = wt.cell;
-    const int arow = l & 15, ak = l >> 4;
-    int jc[TPW];
-    const double* xp[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        jc[u] = (wt.tb + u) * 16 + (l & 15);
-        xp[u] = (u < wt.nt && jc[u] < nr) ? X.p[jc[u]] : nullptr;
+template <int BS, int CT>
+struct TileBuf {
+    static constexpr int LD = CT + 1; // row pitch (spreads the banks of one row)
+    double v[kMaxCols * BS * LD];
+    __device__ __forceinline__ double& at(int q, int k, int t) { return v[(q * BS + k) * LD + t]; }
+};
+
+// buf(q, k, t) = P_q[k n + src(c0 + t)] with src = the slot's neighbour
+// (nbr[cell]) or the cell itself; zero past the last cell.
+template <int BS, int CT>
+__device__ __forceinline__ void tile_load(TileBuf<BS, CT>& buf, const ColPtrs& P, int nr, int n, int c0,
+                                          const int* __restrict__ nbr) {
+    const int total = nr * BS * CT;
+    for (int e = threadIdx.x; e < total; e += kTileWaves * 64) {
+        const int t = e % CT, k = (e / CT) % BS, q = e / (CT * BS);
+        const int cell = c0 + t;
+        double v = 0.0;
+        if (cell < n) v = P.p[q][(int64_t)k * n + (nbr ? nbr[cell] : cell)];
+        buf.at(q, k, t) = v;
     }
-    AT acc[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) acc[u] = AT{0, 0, 0, 0};
+}
+
+template <int BS, int CT>
+__device__ __forceinline__ void tile_store(TileBuf<BS, CT>& buf, const ColPtrs& P, int nr, int n, int c0) {
+    const int total = nr * BS * CT;
+    for (int e = threadIdx.x; e < total; e += kTileWaves * 64) {
+        const int t = e % CT, k = (e / CT) % BS, q = e / (CT * BS);
+        const int cell = c0 + t;
+        if (cell < n) P.p[q][(int64_t)k * n + cell] = buf.at(q, k, t);
+    }
+}
+
+// acc[q][u] += sum over the block row of A(cell, slot) X(neighbour) for the
+// wavefront's cells q and tiles u (X staged slot by slot through buf).
+template <int BS, typename MT, int CT>
+__device__ __forceinline__ void tile_ax(TileBuf<BS, CT>& buf, typename Mfma<MT>::acc (&acc)[CT / kTileWaves][2],
+                                        int n, int width, const int* __restrict__ col, const MT* __restrict__ Ablk,
+                                        int nr, const ColPtrs& X, int c0) {
+    using M = Mfma<MT>;
+    constexpr int CW = CT / kTileWaves;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int arow = l & 15, ak = l >> 4;
+    const int ntile = (nr + 15) >> 4;
     for (int j = 0; j < width; ++j) {
-        const int c = col[(int64_t)j * n + cell];
-        const MT* ab = Ablk + ((int64_t)cell * width + j) * (BS * BS);
+        __syncthreads(); // the previous slot's operands have been read
+        tile_load<BS, CT>(buf, X, nr, n, c0, col + (int64_t)j * n);
+        __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < (BS + 3) / 4; ++ks) {
-            const int k = ks * 4 + ak;
-            const bool kin = k < BS;
-            const MT a = (arow < BS && kin) ? ab[arow * BS + k] : MT(0);
+        for (int q = 0; q < CW; ++q) {
+            const int t = wv * CW + q, cell = c0 + t;
+            if (cell >= n) continue; // uniform in the wavefront
+            const MT* ab = Ablk + ((int64_t)cell * width + j) * (BS * BS);
 #pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                if (u < wt.nt) {
-                    const MT b = (xp[u] && kin) ? (MT)xp[u][(int64_t)k * n + c] : MT(0);
-                    acc[u] = M::mma(a, b, acc[u]);
+            for (int ks = 0; ks < (BS + 3) / 4; ++ks) {
+                const int k = ks * 4 + ak;
+                const bool kin = k < BS;
+                const MT a = (arow < BS && kin) ? ab[arow * BS + k] : MT(0);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (u < ntile) {
+                        const int cq = u * 16 + (l & 15);
+                        const MT b = (kin && cq < nr) ? (MT)buf.at(cq, k, t) : MT(0);
+                        acc[q][u] = M::mma(a, b, acc[q][u]);
+                    }
                 }
             }
         }
     }
+}
+
+// The results of a wavefront's cells go to its own entries of buf (which
+// only that wavefront reads), so no barrier separates its reads of the
+// staged operands from these writes.
+template <int BS, typename MT>
+__device__ __forceinline__ void tile_put(double& slot, MT v) { slot = (double)v; }
+
+// Y[c] = A X[c], or Y[c] = B[c] - A X[c] when hasB (columns c < nr).
+// Ablk: [n][width][BS][BS] (type MT).
+template <int BS, typename MT, bool hasB, int CT>
+__global__ __launch_bounds__(64 * kTileWaves) void k_spmv_mr(int n, int width, const int* __restrict__ col,
+                                                             const MT* __restrict__ Ablk, int nr, ColPtrs X,
+                                                             ColPtrs B, ColPtrs Y) {
+    using M = Mfma<MT>;
+    using AT = typename M::acc;
+    constexpr int CW = CT / kTileWaves;
+    __shared__ TileBuf<BS, CT> buf;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c0 = tile_of_block() * CT;
+    const int ntile = (nr + 15) >> 4;
+    AT acc[CW][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = M::row(l, i);
-        if (row >= BS) continue;
-        const int64_t o = (int64_t)row * n + cell;
+    for (int q = 0; q < CW; ++q) acc[q][0] = acc[q][1] = AT{0, 0, 0, 0};
+    tile_ax<BS, MT, CT>(buf, acc, n, width, col, Ablk, nr, X, c0);
 #pragma unroll
-        for (int u = 0; u < TPW; ++u)
-            if (xp[u]) Y.p[jc[u]][o] = hasB ? (double)((MT)B.p[jc[u]][o] - acc[u][i]) : (double)acc[u][i];
+    for (int q = 0; q < CW; ++q) {
+        const int t = wv * CW + q;
+        if (c0 + t >= n) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = M::row(l, i);
+            if (row >= BS) continue;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int cq = u * 16 + (l & 15);
+                if (u < ntile && cq < nr) tile_put<BS, MT>(buf.at(cq, row, t), acc[q][u][i]);
+            }
+        }
+    }
+    __syncthreads();
+    // Y = A X, or B - A X with B read on the way out (same order of
+    // operations: the product is exact in buf)
+    const int total = nr * BS * CT;
+    for (int e = threadIdx.x; e < total; e += kTileWaves * 64) {
+        const int t = e % CT, k = (e / CT) % BS, q = e / (CT * BS);
+        const int cell = c0 + t;
+        if (cell >= n) continue;
+        const int64_t o = (int64_t)k * n + cell;
+        const double ax = buf.at(q, k, t);
+        Y.p[q][o] = hasB ? (double)((MT)B.p[q][o] - (MT)ax) : ax;
     }
 }
 
 // X[c] = omega D^-1 R[c] (first block-Jacobi iteration from zero).
-template <int BS, typename MT, int WAVES, int TPW>
-__global__ __launch_bounds__(64 * WAVES) void k_bj_first_mr(int n, const MT* __restrict__ Dblk, MT omega, int nr,
-                                                            ColPtrs R, ColPtrs X) {
+template <int BS, typename MT, int CT>
+__global__ __launch_bounds__(64 * kTileWaves) void k_bj_first_mr(int n, const MT* __restrict__ Dblk, MT omega,
+                                                                 int nr, ColPtrs R, ColPtrs X) {
     using M = Mfma<MT>;
     using AT = typename M::acc;
-    const int l = threadIdx.x & 63;
-    WaveTask wt;
-    if (!wave_task<WAVES, TPW>(n, nr, wt)) return;
-    const int cell = wt.cell;
-    const int arow = l & 15, ak = l >> 4;
-    int jc[TPW];
-    const double* rp[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        jc[u] = (wt.tb + u) * 16 + (l & 15);
-        rp[u] = (u < wt.nt && jc[u] < nr) ? R.p[jc[u]] : nullptr;
-    }
-    const MT* db = Dblk + (int64_t)cell * (BS * BS);
-    AT acc[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) acc[u] = AT{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < (BS + 3) / 4; ++ks) {
-        const int k = ks * 4 + ak;
-        const bool kin = k < BS;
-        const MT a = (arow < BS && kin) ? db[arow * BS + k] : MT(0);
-#pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            if (u < wt.nt) {
-                const MT b = (rp[u] && kin) ? (MT)rp[u][(int64_t)k * n + cell] : MT(0);
-                acc[u] = M::mma(a, b, acc[u]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = M::row(l, i);
-        if (row >= BS) continue;
-        const int64_t o = (int64_t)row * n + cell;
-#pragma unroll
-        for (int u = 0; u < TPW; ++u)
-            if (rp[u]) X.p[jc[u]][o] = (double)(omega * acc[u][i]);
-    }
-}
-
-// Xout[c] = Xin[c] + omega D^-1 (R[c] - A Xin[c]). The residual block moves
-// from the result layout to the B-operand layout through LDS (per wavefront).
-template <int BS, typename MT, int WAVES, int TPW>
-__global__ __launch_bounds__(64 * WAVES) void k_bj_sweep_mr(int n, int width, const int* __restrict__ col,
-                                                            const MT* __restrict__ Ablk,
-                                                            const MT* __restrict__ Dblk, MT omega, int nr,
-                                                            ColPtrs R, ColPtrs Xin, ColPtrs Xout) {
-    using M = Mfma<MT>;
-    using AT = typename M::acc;
-    __shared__ MT tt[WAVES][TPW][16][17];
+    constexpr int CW = CT / kTileWaves;
+    __shared__ TileBuf<BS, CT> buf;
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    WaveTask wt;
-    if (!wave_task<WAVES, TPW>(n, nr, wt)) return; // LDS is private to the wavefront: no block barrier
-    const int cell = wt.cell;
     const int arow = l & 15, ak = l >> 4;
-    int jc[TPW];
-    const double* xp[TPW];
+    const int c0 = tile_of_block() * CT;
+    const int ntile = (nr + 15) >> 4;
+    tile_load<BS, CT>(buf, R, nr, n, c0, nullptr);
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        jc[u] = (wt.tb + u) * 16 + (l & 15);
-        xp[u] = (u < wt.nt && jc[u] < nr) ? Xin.p[jc[u]] : nullptr;
-    }
-    AT acc[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) acc[u] = AT{0, 0, 0, 0};
-    for (int j = 0; j < width; ++j) {
-        const int c = col[(int64_t)j * n + cell];
-        const MT* ab = Ablk + ((int64_t)cell * width + j) * (BS * BS);
+    for (int q = 0; q < CW; ++q) {
+        const int t = wv * CW + q, cell = c0 + t;
+        if (cell >= n) continue;
+        const MT* db = Dblk + (int64_t)cell * (BS * BS);
+        AT acc[2] = {AT{0, 0, 0, 0}, AT{0, 0, 0, 0}};
 #pragma unroll
         for (int ks = 0; ks < (BS + 3) / 4; ++ks) {
             const int k = ks * 4 + ak;
             const bool kin = k < BS;
-            const MT a = (arow < BS && kin) ? ab[arow * BS + k] : MT(0);
+            const MT a = (arow < BS && kin) ? db[arow * BS + k] : MT(0);
 #pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                if (u < wt.nt) {
-                    const MT b = (xp[u] && kin) ? (MT)xp[u][(int64_t)k * n + c] : MT(0);
+            for (int u = 0; u < 2; ++u) {
+                if (u < ntile) {
+                    const int cq = u * 16 + (l & 15);
+                    const MT b = (kin && cq < nr) ? (MT)buf.at(cq, k, t) : MT(0);
                     acc[u] = M::mma(a, b, acc[u]);
                 }
             }
         }
-    }
-    // t = R - A Xin into LDS as [tile][row][column]; rows >= BS are zero
+        // the wavefront has read this cell's R entries (the products above
+        // depend on them) before any lane overwrites them
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = M::row(l, i);
+        for (int i = 0; i < 4; ++i) {
+            const int row = M::row(l, i);
+            if (row >= BS) continue;
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            MT tv = MT(0);
-            if (row < BS && xp[u]) tv = (MT)R.p[jc[u]][(int64_t)row * n + cell] - acc[u][i];
-            tt[wv][u][row][l & 15] = tv;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const MT* db = Dblk + (int64_t)cell * (BS * BS);
-    AT d[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) d[u] = AT{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < (BS + 3) / 4; ++ks) {
-        const int k = ks * 4 + ak;
-        const bool kin = k < BS;
-        const MT a = (arow < BS && kin) ? db[arow * BS + k] : MT(0);
-#pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            if (u < wt.nt) {
-                const MT b = kin ? tt[wv][u][k][l & 15] : MT(0);
-                d[u] = M::mma(a, b, d[u]);
+            for (int u = 0; u < 2; ++u) {
+                const int cq = u * 16 + (l & 15);
+                if (u < ntile && cq < nr) tile_put<BS, MT>(buf.at(cq, row, t), omega * acc[u][i]);
             }
         }
     }
+    __syncthreads();
+    tile_store<BS, CT>(buf, X, nr, n, c0);
+}
+
+// Xout[c] = Xin[c] + omega D^-1 (R[c] - A Xin[c]). The residual block of a
+// (cell, tile) moves from the result layout to the B-operand layout through
+// a per-wavefront LDS square; Xin is read again on the way out.
+template <int BS, typename MT, int CT>
+__global__ __launch_bounds__(64 * kTileWaves) void k_bj_sweep_mr(int n, int width, const int* __restrict__ col,
+                                                                 const MT* __restrict__ Ablk,
+                                                                 const MT* __restrict__ Dblk, MT omega, int nr,
+                                                                 ColPtrs R, ColPtrs Xin, ColPtrs Xout) {
+    using M = Mfma<MT>;
+    using AT = typename M::acc;
+    constexpr int CW = CT / kTileWaves;
+    __shared__ TileBuf<BS, CT> buf;
+    __shared__ MT tt[kTileWaves][16][17];
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int arow = l & 15, ak = l >> 4;
+    const int c0 = tile_of_block() * CT;
+    const int ntile = (nr + 15) >> 4;
+    AT acc[CW][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = M::row(l, i);
-        if (row >= BS) continue;
-        const int64_t o = (int64_t)row * n + cell;
+    for (int q = 0; q < CW; ++q) acc[q][0] = acc[q][1] = AT{0, 0, 0, 0};
+    tile_ax<BS, MT, CT>(buf, acc, n, width, col, Ablk, nr, Xin, c0);
+    __syncthreads();
+    tile_load<BS, CT>(buf, R, nr, n, c0, nullptr);
+    __syncthreads();
 #pragma unroll
-        for (int u = 0; u < TPW; ++u)
-            if (xp[u]) Xout.p[jc[u]][o] = (double)((MT)Xin.p[jc[u]][o] + omega * d[u][i]);
+    for (int q = 0; q < CW; ++q) {
+        const int t = wv * CW + q, cell = c0 + t;
+        if (cell >= n) continue;
+        const MT* db = Dblk + (int64_t)cell * (BS * BS);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u >= ntile) continue;
+            const int cq = u * 16 + (l & 15);
+            // t = R - A Xin of this (cell, tile) into the square as [row][column]
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = M::row(l, i);
+                MT tv = MT(0);
+                if (row < BS && cq < nr) tv = (MT)buf.at(cq, row, t) - acc[q][u][i];
+                tt[wv][row][l & 15] = tv;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            AT d = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < (BS + 3) / 4; ++ks) {
+                const int k = ks * 4 + ak;
+                const bool kin = k < BS;
+                const MT a = (arow < BS && kin) ? db[arow * BS + k] : MT(0);
+                const MT b = kin ? tt[wv][k][l & 15] : MT(0);
+                d = M::mma(a, b, d);
+            }
+            // D^-1 t of this (cell, tile) replaces its R entries in buf
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = M::row(l, i);
+                if (row < BS && cq < nr) tile_put<BS, MT>(buf.at(cq, row, t), d[i]);
+            }
+            // the square is rewritten for the next (cell, tile) only after
+            // every lane has read it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    }
+    __syncthreads();
+    const int total = nr * BS * CT;
+    for (int e = threadIdx.x; e < total; e += kTileWaves * 64) {
+        const int t = e % CT, k = (e / CT) % BS, q = e / (CT * BS);
+        const int cell = c0 + t;
+        if (cell >= n) continue;
+        const int64_t o = (int64_t)k * n + cell;
+        Xout.p[q][o] = (double)((MT)Xin.p[q][o] + omega * (MT)buf.at(q, k, t));
     }
 }
 
@@ -267,17 +337,27 @@ __global__ __launch_bounds__(kThreads) void k_dense_mr(int n, int np, const doub
     const int nk = (n + 3) / 4;                 // k steps of 4
     const int per = (nk + kWaves - 1) / kWaves; // steps per wavefront
     const int s0 = wv * per, s1 = min(nk, s0 + per);
-    const double* arowp = A + (int64_t)min(arow, n - 1) * np;
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    for (int st = s0; st < s1; ++st) {
-        const int k = st * 4 + ak;
-        const bool kin = k < n;
-        const double a = (arow < n && kin) ? arowp[k] : 0.0;
-        const double b0 = (x0 && kin) ? x0[k] : 0.0;
-        acc0 = M::mma(a, b0, acc0);
-        if (two) {
-            const double b1 = (x1 && kin) ? x1[k] : 0.0;
-            acc1 = M::mma(a, b1, acc1);
+    // U k steps per round: their loads are all issued before the products,
+    // so a wavefront keeps 3 U loads in flight (the products run in k order)
+    constexpr int U = 8;
+    for (int st = s0; st < s1; st += U) {
+        double a[U], b0[U], b1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = (st + u) * 4 + ak;
+            const bool kin = st + u < s1 && k < n;
+            // Ainv is symmetric bit for bit (each entry pair is the same sum
+            // of the same products): element (row, k) is read as (k, row), so
+            // the 16 rows of a k step are 128 contiguous bytes
+            a[u] = (arow < n && kin) ? A[(int64_t)k * np + arow] : 0.0;
+            b0[u] = (x0 && kin) ? x0[k] : 0.0;
+            b1[u] = (two && x1 && kin) ? x1[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc0 = M::mma(a[u], b0[u], acc0);
+            if (two) acc1 = M::mma(a[u], b1[u], acc1);
         }
     }
 #pragma unroll
@@ -314,14 +394,11 @@ __global__ void k_to_blocks(int n, int width, int bs, int bsh, const double* __r
     out[t] = (MT)val[((((int64_t)j * bs + r) * bsh + (c >> 1)) * n + i) * 2 + (c & 1)];
 }
 
-// Launch shapes: (wavefronts per block, tiles per wavefront).
-constexpr int kShapes[][2] = {{4, 2}, {2, 2}, {1, 2}, {4, 1}, {2, 1}, {1, 1}};
-constexpr int kNumShapes = 6;
+// Launch shapes: cells per tile (CT).
+constexpr int kShapes[] = {16, 8};
+constexpr int kNumShapes = 2;
 
-static inline unsigned grid_for(int n, int nr, int waves, int tpw) {
-    const int64_t w = (int64_t)n * (tpw == 2 ? 1 : (nr + 15) / 16);
-    return (unsigned)((w + waves - 1) / waves);
-}
+static inline unsigned grid_for(int n, int ct) { return (unsigned)((n + ct - 1) / ct); }
 
 #define OMG_MR_BS(bs, CALL)                            \
     switch (bs) {                                      \
@@ -330,15 +407,11 @@ static inline unsigned grid_for(int n, int nr, int waves, int tpw) {
     case 10: { constexpr int BSV = 10; CALL; } break;  \
     default: return hipErrorInvalidValue;              \
     }
-#define OMG_MR_SHAPE(shape, CALL)                                                    \
-    switch (shape) {                                                                 \
-    case 0: { constexpr int WV = 4, TP = 2; CALL; } break;                           \
-    case 1: { constexpr int WV = 2, TP = 2; CALL; } break;                           \
-    case 2: { constexpr int WV = 1, TP = 2; CALL; } break;                           \
-    case 3: { constexpr int WV = 4, TP = 1; CALL; } break;                           \
-    case 4: { constexpr int WV = 2, TP = 1; CALL; } break;                           \
-    case 5: { constexpr int WV = 1, TP = 1; CALL; } break;                           \
-    default: return hipErrorInvalidValue;                                            \
+#define OMG_MR_SHAPE(shape, CALL)                           \
+    switch (shape) {                                        \
+    case 0: { constexpr int CTV = 16; CALL; } break;        \
+    case 1: { constexpr int CTV = 8; CALL; } break;         \
+    default: return hipErrorInvalidValue;                   \
     }
 
 static inline bool mr_ok(const Level& L, int bs, int nr) {
@@ -348,23 +421,22 @@ static inline bool mr_ok(const Level& L, int bs, int nr) {
 static hipError_t spmv_mr_shape(int shape, const Level& L, int bs, bool fp32, int nr, const ColPtrs& X,
                                 const ColPtrs* B, const ColPtrs& Y, hipStream_t st) {
     const ColPtrs Bv = B ? *B : ColPtrs{};
-    const int wv = kShapes[shape][0], tp = kShapes[shape][1];
-    const dim3 g(grid_for(L.n, nr, wv, tp)), t(64 * wv);
+    const dim3 g(grid_for(L.n, kShapes[shape])), t(64 * kTileWaves);
     if (fp32) {
         if (B) {
-            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, float, true, WV, TP>), g, t, 0, st,
+            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, float, true, CTV>), g, t, 0, st,
                                                                  L.n, L.width, L.col, L.ablk32, nr, X, Bv, Y)))
         } else {
-            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, float, false, WV, TP>), g, t, 0, st,
+            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, float, false, CTV>), g, t, 0, st,
                                                                  L.n, L.width, L.col, L.ablk32, nr, X, Bv, Y)))
         }
     } else {
         if (B) {
-            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, double, true, WV, TP>), g, t, 0,
-                                                                 st, L.n, L.width, L.col, L.ablk, nr, X, Bv, Y)))
+            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, double, true, CTV>), g, t, 0, st,
+                                                                 L.n, L.width, L.col, L.ablk, nr, X, Bv, Y)))
         } else {
-            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, double, false, WV, TP>), g, t, 0,
-                                                                 st, L.n, L.width, L.col, L.ablk, nr, X, Bv, Y)))
+            OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_spmv_mr<BSV, double, false, CTV>), g, t, 0, st,
+                                                                 L.n, L.width, L.col, L.ablk, nr, X, Bv, Y)))
         }
     }
     return hipGetLastError();
@@ -372,13 +444,12 @@ static hipError_t spmv_mr_shape(int shape, const Level& L, int bs, bool fp32, in
 
 static hipError_t bj_first_mr_shape(int shape, const Level& L, int bs, bool fp32, double omega, int nr,
                                     const ColPtrs& R, const ColPtrs& X, hipStream_t st) {
-    const int wv = kShapes[shape][0], tp = kShapes[shape][1];
-    const dim3 g(grid_for(L.n, nr, wv, tp)), t(64 * wv);
+    const dim3 g(grid_for(L.n, kShapes[shape])), t(64 * kTileWaves);
     if (fp32) {
-        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_first_mr<BSV, float, WV, TP>), g, t, 0, st, L.n,
+        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_first_mr<BSV, float, CTV>), g, t, 0, st, L.n,
                                                              L.dblk32, (float)omega, nr, R, X)))
     } else {
-        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_first_mr<BSV, double, WV, TP>), g, t, 0, st, L.n,
+        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_first_mr<BSV, double, CTV>), g, t, 0, st, L.n,
                                                              L.dblk, omega, nr, R, X)))
     }
     return hipGetLastError();
@@ -386,22 +457,21 @@ static hipError_t bj_first_mr_shape(int shape, const Level& L, int bs, bool fp32
 
 static hipError_t bj_sweep_mr_shape(int shape, const Level& L, int bs, bool fp32, double omega, int nr,
                                     const ColPtrs& R, const ColPtrs& Xin, const ColPtrs& Xout, hipStream_t st) {
-    const int wv = kShapes[shape][0], tp = kShapes[shape][1];
-    const dim3 g(grid_for(L.n, nr, wv, tp)), t(64 * wv);
+    const dim3 g(grid_for(L.n, kShapes[shape])), t(64 * kTileWaves);
     if (fp32) {
-        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_sweep_mr<BSV, float, WV, TP>), g, t, 0, st, L.n,
+        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_sweep_mr<BSV, float, CTV>), g, t, 0, st, L.n,
                                                              L.width, L.col, L.ablk32, L.dblk32, (float)omega, nr, R,
                                                              Xin, Xout)))
     } else {
-        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_sweep_mr<BSV, double, WV, TP>), g, t, 0, st, L.n,
+        OMG_MR_SHAPE(shape, OMG_MR_BS(bs, hipLaunchKernelGGL((k_bj_sweep_mr<BSV, double, CTV>), g, t, 0, st, L.n,
                                                              L.width, L.col, L.ablk, L.dblk, omega, nr, R, Xin,
                                                              Xout)))
     }
     return hipGetLastError();
 }
 
-// Tuned shape of (op, precision, tile count) on a level; 0 (4 waves, both
-// tiles per wavefront) until tuned.
+// Tuned shape of (op, precision, tile count) on a level; 0 (16 cells per
+// tile) until tuned.
 static inline int shape_of(const Level& L, int op, bool fp32, int nr) {
     const int s = L.mr_shape[op][fp32 ? 1 : 0][nr > 16 ? 1 : 0];
     return s > 0 ? s - 1 : 0;
@@ -425,7 +495,7 @@ hipError_t launch_bj_sweep_mr(const Level& L, int bs, bool fp32, double omega, i
     return bj_sweep_mr_shape(shape_of(L, 2, fp32, nr), L, bs, fp32, omega, nr, R, Xin, Xout, st);
 }
 
-// Autotuner: time every launch shape of the three multi-RHS operations on
+// Autotuner: time both tile sizes of the three multi-RHS operations on
 // this level for nr columns (both precisions), `reps` launches each between
 // HIP events, and keep the fastest. X, Y, T are nr work vectors of the level
 // (filled here with zeros; the timed launches only read X/T and write Y).

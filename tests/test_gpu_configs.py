@@ -355,7 +355,7 @@ def test_gradient_48p2_finite_differences(grad48, chunk):
     Bound: |fd - adj| <= 1e-5 |fd| + 1e-9 max|adj|. The absolute term is
     the adjoint gradient's own accuracy (forward and adjoint solved to
     1e-12): on the sampled cell with the smallest gradient (2.4e-4 of the
-    largest) the difference is ~6e-14 = 3e-9 of the largest gradient whether
+    largest) the difference is 4-8e-14 (2-3e-9 of the largest gradient) whether
     h is 1e-4, 1e-5 or 1e-6 (1.4e-5, 1.1e-5, 7.8e-6 relative), so it does not
     come from the finite differences."""
     prob, nu, f, ut, u, g_f, g_lognu, s, cells = grad48

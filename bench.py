@@ -462,6 +462,8 @@ def main():
         "batched": batched,
         "roofline": roof,
         "kernel_ms_per_solve": breakdown,
+        "rm_configurations": {f"L{l}": {"config": list(s.level_tuning(l)[1]), "tuner_dropped": s.rm_dropped(l)}
+                              for l in range(prob.n_levels - 1)},
         "cpu_baseline": cpu,
         "cpu_full_solve": cpu_full,
         "cycle_sweep": sweep,

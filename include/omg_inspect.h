@@ -48,7 +48,7 @@ omg_status omg_coarse_solve(omg_solver *s, const double *b, double *x);
  * fp32 = 1 uses the FP32 operator copies (inputs rounded to FP32, FP32
  * arithmetic, results widened to FP64). OMG_EUNSUPPORTED for bs > 16. */
 enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
-/* Launch configurations the autotuners chose on a level, host shapes[18]:
+/* Launch configurations the autotuners chose on a level, host shapes[19]:
  * [0..11] the multi-right-hand-side kernels (tuned on the first batched
  * solve), indexed [op: SpMV, first block-Jacobi iteration, fused iteration]
  * [FP64, FP32][up to 16 columns, 17..32 columns]; shape s in 0..1 is the
@@ -58,7 +58,9 @@ enum { OMG_MR_SPMV = 0, OMG_MR_SMOOTHER = 1, OMG_MR_COARSE = 2 };
  * thread, directions per grid exchange, exchange form (0 all-to-all, 1
  * leader block), compute waves per block of the exchange-wave form (0:
  * plain form), exchanges kept in flight by the lagged form (0: not lagged);
- * -1 if the level does not use it. */
+ * -1 if the level does not use it. [18] the number of RM configurations the
+ * tuner timed on this level and dropped because a bounded wait expired (a
+ * grid that was not resident at once). */
 omg_status omg_level_tuning(const omg_solver *s, int32_t level, int32_t *shapes);
 omg_status omg_level_multi(omg_solver *s, int32_t level, int32_t op, int32_t nrhs, int32_t sweeps, int32_t fp32,
                            const double *X, const double *B, double *Y);

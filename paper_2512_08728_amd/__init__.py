@@ -361,9 +361,16 @@ class Solver:
         """Autotuned launch configurations of level l: (multi-RHS shapes
         [op][fp32][two tiles], (RM blocks, entries per thread, MGS block, leader exchange,
         compute waves of the exchange-wave form or 0, exchanges in flight of the lagged form or 0))."""
-        out = np.zeros(18, dtype=np.int32)
+        out = np.zeros(19, dtype=np.int32)
         _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
-        return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:])
+        return out[:12].reshape(3, 2, 2), tuple(int(v) for v in out[12:18])
+
+    def rm_dropped(self, l):
+        """RM launch configurations the tuner dropped on level l because a
+        bounded wait expired (their grid was not resident at once)."""
+        out = np.zeros(19, dtype=np.int32)
+        _check(lib().omg_level_tuning(self._h, l, out.ctypes.data), "level_tuning")
+        return int(out[18])
 
     def rm_configs(self, l=0):
         """Co-resident launch configurations of level l's persistent RM kernel."""

@@ -863,6 +863,7 @@ extern "C" omg_status omg_level_tuning(const omg_solver* s, int32_t level, int32
     shapes[q++] = L.persist ? L.rmc.lead : -1;
     shapes[q++] = L.persist ? L.rmc.cw : -1;
     shapes[q++] = L.persist ? L.rmc.lag : -1;
+    shapes[q++] = L.rm_dropped;
     return OMG_OK;
 }
 

@@ -185,6 +185,7 @@ struct Level {
     // autotuned launch shape + 1 of the multi-RHS kernels [op: spmv, bj_first,
     // bj_sweep][FP64, FP32][one tile, two tiles]; 0 = not tuned
     int mr_shape[3][2][2] = {};
+    int rm_dropped = 0; // RM configurations the tuner dropped (bounded waits expired)
 
     // work vectors (SoA, N each)
     double *b = nullptr, *r = nullptr, *x = nullptr, *z = nullptr, *w = nullptr;

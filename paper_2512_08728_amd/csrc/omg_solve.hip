@@ -555,6 +555,7 @@ static omg_status tune_rm(omg_solver* s, int l) {
             if (hipMemcpy(flags, L.bar, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess) res = OMG_EHIP;
             if (res == OMG_OK && flags[1]) {
                 if (log) std::fprintf(stderr, "[omg] RM tuning: configuration %d aborted\n", q);
+                L.rm_dropped++;
                 tbest = 1e30f;
                 L.slot_G = 0; // words in unknown state: reset before the next launch
                 if (hipMemset(L.bar + 1, 0, sizeof(unsigned)) != hipSuccess) res = OMG_EHIP;

@@ -136,6 +136,11 @@ def test_fullsize_rm_step_every_configuration(big):
     say(f"64^3 P2 finest level: {len(configs)} co-resident RM configurations, "
         f"grids {sorted(set(c[0] for c in configs))}")
     assert any(c[0] > 256 for c in configs)
+    # the tuner reports configurations it dropped for an expired wait (none
+    # here: every candidate below also completes its bounded waits)
+    dropped = [g.rm_dropped(l) for l in range(prob.n_levels - 1)]
+    say(f"RM configurations dropped by the tuner per level: {dropped}")
+    assert all(d == 0 for d in dropped)
     Wall = np.linalg.qr(rng.standard_normal((N, 64)))[0].T.copy()
     Wdev = cuda(Wall)
     for k in (0, 1, 40, 64):

@@ -1410,6 +1410,9 @@ static omg_status check_rm_abort(omg_solver* s) {
         unsigned f = 0;
         HIP_OK(hipMemcpy(&f, L.bar + 1, sizeof(unsigned), hipMemcpyDeviceToHost));
         if (f) {
+            if (std::getenv("OMG_RM_TUNE_LOG"))
+                std::fprintf(stderr, "[omg] level %d: a bounded wait of the persistent RM expired\n",
+                             (int)(&L - s->lev.data()));
             HIP_OK(hipMemset(L.bar + 1, 0, sizeof(unsigned)));
             L.slot_G = -1;
             st = OMG_EHIP;

@@ -318,14 +318,15 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_bj_sweep_mr(int n, int widt
     }
 }
 
-constexpr int kWaves = kThreads / 64;
-
 // Y[c] = Ainv X[c] for the coarsest level: Ainv [np][np] row-major (n used).
-// One block per 16 rows; the four wavefronts split the k range and their
-// partial products are summed in a fixed order through LDS.
-__global__ __launch_bounds__(kThreads) void k_dense_mr(int n, int np, const double* __restrict__ A, int nr,
-                                                       ColPtrs X, ColPtrs Y) {
+// One block per 16 rows; its sixteen wavefronts split the k range (a few
+// hundred blocks would leave too few loads in flight) and their partial
+// products are summed in a fixed order through LDS.
+constexpr int kDenseWaves = 16;
+__global__ __launch_bounds__(64 * kDenseWaves) void k_dense_mr(int n, int np, const double* __restrict__ A, int nr,
+                                                               ColPtrs X, ColPtrs Y) {
     using M = Mfma<double>;
+    constexpr int kWaves = kDenseWaves;
     __shared__ double red[kWaves][2][4][64];
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row0 = blockIdx.x * 16;
@@ -549,8 +550,8 @@ hipError_t tune_mr(Level& L, int bs, int nr, const ColPtrs& X, const ColPtrs& Y,
 hipError_t launch_dense_mr(const Level& L, int nr, const ColPtrs& X, const ColPtrs& Y, hipStream_t st) {
     const int n = (int)L.N;
     if (nr < 1 || nr > kMaxCols || !L.ainv || n < 1 || L.np < n) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dense_mr, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), 0, st, n, L.np, L.ainv, nr, X,
-                       Y);
+    hipLaunchKernelGGL(k_dense_mr, dim3((unsigned)((n + 15) / 16)), dim3(64 * kDenseWaves), 0, st, n, L.np, L.ainv,
+                       nr, X, Y);
     return hipGetLastError();
 }
 

@@ -59,9 +59,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        # OMG_ORACLE_LIB: another build of the same source (the sanitizer
+        # test loads an AddressSanitizer/UBSan build this way)
+        path = os.environ.get("OMG_ORACLE_LIB")
+        if not path:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            path = _LIB
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i, d, i64 = ctypes.c_int, ctypes.c_double, ctypes.c_int64
         L.oracle_setup.argtypes = [P, P, P, i64, i, i, i, i, i, P, ctypes.POINTER(P)]

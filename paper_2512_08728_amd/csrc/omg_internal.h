@@ -154,6 +154,7 @@ struct Level {
     int np = 0;                        // padded dense order
     double* atile = nullptr;           // coarsest: lower-triangle 64x64 tiles of ainv (symmetric GEMV)
     double* spart = nullptr;           // [ntile][ntile][64] partial products of the symmetric GEMV
+    double* mrpart = nullptr;          // [k tile][N][32] partial products of the multi-column product (built on first use)
     int ntile = 0;
 
     std::vector<int> hcol;             // host copy of col (Galerkin symbolic phase)

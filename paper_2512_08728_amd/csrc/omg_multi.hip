@@ -318,68 +318,68 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_bj_sweep_mr(int n, int widt
     }
 }
 
-// Y[c] = Ainv X[c] for the coarsest level: Ainv [np][np] row-major (n used).
-// One block per 16 rows; its sixteen wavefronts split the k range (a few
-// hundred blocks would leave too few loads in flight) and their partial
-// products are summed in a fixed order through LDS.
-constexpr int kDenseWaves = 16;
-__global__ __launch_bounds__(64 * kDenseWaves) void k_dense_mr(int n, int np, const double* __restrict__ A, int nr,
-                                                               ColPtrs X, ColPtrs Y) {
+// Y[c] = Ainv X[c] for the coarsest level: Ainv [np][np] row-major (n used),
+// symmetric bit for bit (each entry pair is the same sum of the same
+// products), so element (row, k) is read as (k, row) and the 16 rows of a k
+// step are 128 contiguous bytes. Tiles of 64 rows x 256 k: a block of four
+// wavefronts stages the tile's k range of every column in LDS (coalesced
+// along each column), each wavefront forms 16 rows for all columns on the
+// FP64 matrix cores in k order with 16 k steps of loads in flight, and the
+// tile's products go to part[k tile][row][column]; k_dense_mr_sum adds the
+// k tiles in order. At 5,120 rows that is 1,600 blocks, each streaming its
+// own 128 KB of the inverse once.
+constexpr int kDenseRows = 64, kDenseK = 256, kDenseU = 16;
+__global__ __launch_bounds__(kDenseK) void k_dense_mr(int n, int np, const double* __restrict__ A, int nr, ColPtrs X,
+                                                      double* __restrict__ part) {
     using M = Mfma<double>;
-    constexpr int kWaves = kDenseWaves;
-    __shared__ double red[kWaves][2][4][64];
+    __shared__ double xs[kMaxCols][kDenseK + 2];
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * 16;
-    const int arow = row0 + (l & 15), ak = l >> 4;
-    const int j0 = l & 15, j1 = 16 + (l & 15);
+    const int k0 = blockIdx.y * kDenseK, kn = min(kDenseK, n - k0);
     const bool two = nr > 16;
-    const double* x0 = j0 < nr ? X.p[j0] : nullptr;
-    const double* x1 = (two && j1 < nr) ? X.p[j1] : nullptr;
-    const int nk = (n + 3) / 4;                 // k steps of 4
-    const int per = (nk + kWaves - 1) / kWaves; // steps per wavefront
-    const int s0 = wv * per, s1 = min(nk, s0 + per);
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    // U k steps per round: their loads are all issued before the products,
-    // so a wavefront keeps 3 U loads in flight (the products run in k order)
-    constexpr int U = 8;
-    for (int st = s0; st < s1; st += U) {
-        double a[U], b0[U], b1[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = (st + u) * 4 + ak;
-            const bool kin = st + u < s1 && k < n;
-            // Ainv is symmetric bit for bit (each entry pair is the same sum
-            // of the same products): element (row, k) is read as (k, row), so
-            // the 16 rows of a k step are 128 contiguous bytes
-            a[u] = (arow < n && kin) ? A[(int64_t)k * np + arow] : 0.0;
-            b0[u] = (x0 && kin) ? x0[k] : 0.0;
-            b1[u] = (two && x1 && kin) ? x1[k] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            acc0 = M::mma(a[u], b0[u], acc0);
-            if (two) acc1 = M::mma(a[u], b1[u], acc1);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        red[wv][0][i][l] = acc0[i];
-        red[wv][1][i][l] = acc1[i];
+    const int nq = two ? kMaxCols : 16;
+    for (int q = 0; q < nq; ++q) {
+        const double* xq = q < nr ? X.p[q] : nullptr;
+        xs[q][threadIdx.x] = (xq && (int)threadIdx.x < kn) ? xq[k0 + threadIdx.x] : 0.0;
     }
     __syncthreads();
-    if (wv != 0) return;
+    const int r0 = blockIdx.x * kDenseRows + wv * 16;
+    const int row = r0 + (l & 15), kk = l >> 4, c = l & 15;
+    const bool rin = row < n;
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const int ns = (kn + 3) / 4; // k steps of 4; entries past kn are zero on both sides
+    for (int s0 = 0; s0 < ns; s0 += kDenseU) {
+        double a[kDenseU];
+#pragma unroll
+        for (int u = 0; u < kDenseU; ++u) {
+            const int kl = (s0 + u) * 4 + kk;
+            a[u] = (rin && kl < kn) ? A[(int64_t)(k0 + kl) * np + row] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kDenseU; ++u) {
+            const int kl = (s0 + u) * 4 + kk; // < kDenseK: s0 + u < 64
+            acc0 = M::mma(a[u], xs[c][kl], acc0);
+            if (two) acc1 = M::mma(a[u], xs[16 + c][kl], acc1);
+        }
+    }
+    double* pb = part + (size_t)blockIdx.y * n * kMaxCols;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int row = row0 + M::row(l, i);
-        if (row >= n) continue;
-        double s0v = red[0][0][i][l], s1v = red[0][1][i][l];
-        for (int w = 1; w < kWaves; ++w) {
-            s0v += red[w][0][i][l];
-            s1v += red[w][1][i][l];
-        }
-        if (j0 < nr) Y.p[j0][row] = s0v;
-        if (two && j1 < nr) Y.p[j1][row] = s1v;
+        const int r = r0 + M::row(l, i);
+        if (r >= n) continue;
+        pb[(size_t)r * kMaxCols + c] = acc0[i];
+        if (two) pb[(size_t)r * kMaxCols + 16 + c] = acc1[i];
     }
+}
+
+// Y[c][row] = sum over k tiles (in order) of part[k tile][row][c].
+__global__ void k_dense_mr_sum(int n, int nr, int nkt, const double* __restrict__ part, ColPtrs Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = (int)(t % kMaxCols);
+    const int64_t row = t / kMaxCols;
+    if (row >= n || q >= nr) return;
+    double s = 0.0;
+    for (int kt = 0; kt < nkt; ++kt) s += part[((size_t)kt * n + row) * kMaxCols + q];
+    Y.p[q][row] = s;
 }
 
 // Block-contiguous copy of the column-pair ELL layout: out[i][j][r][c].
@@ -549,9 +549,13 @@ hipError_t tune_mr(Level& L, int bs, int nr, const ColPtrs& X, const ColPtrs& Y,
 
 hipError_t launch_dense_mr(const Level& L, int nr, const ColPtrs& X, const ColPtrs& Y, hipStream_t st) {
     const int n = (int)L.N;
-    if (nr < 1 || nr > kMaxCols || !L.ainv || n < 1 || L.np < n) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dense_mr, dim3((unsigned)((n + 15) / 16)), dim3(64 * kDenseWaves), 0, st, n, L.np, L.ainv,
-                       nr, X, Y);
+    if (nr < 1 || nr > kMaxCols || !L.ainv || !L.mrpart || n < 1 || L.np < n) return hipErrorInvalidValue;
+    const int nkt = (n + kDenseK - 1) / kDenseK;
+    hipLaunchKernelGGL(k_dense_mr, dim3((unsigned)((n + kDenseRows - 1) / kDenseRows), (unsigned)nkt), dim3(kDenseK),
+                       0, st, n, L.np, L.ainv, nr, X, L.mrpart);
+    const int64_t tot = (int64_t)n * kMaxCols;
+    hipLaunchKernelGGL(k_dense_mr_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nr, nkt, L.mrpart,
+                       Y);
     return hipGetLastError();
 }
 
@@ -559,6 +563,11 @@ hipError_t launch_dense_mr(const Level& L, int nr, const ColPtrs& X, const ColPt
 // Levels without a stored operator (a coarsest level below the finest keeps
 // only its dense inverse) get none; the inverses exist below the coarsest.
 hipError_t build_blocks(Level& L, int bs, int bsh, hipStream_t st) {
+    if (L.ainv && !L.mrpart) { // partial products of the coarsest multi-column product
+        const int64_t nkt = (L.N + kDenseK - 1) / kDenseK;
+        const hipError_t e = hipMalloc((void**)&L.mrpart, sizeof(double) * (size_t)(nkt * L.N * kMaxCols));
+        if (e != hipSuccess) return e;
+    }
     if (L.ablk || !L.val || L.width < 1) return hipSuccess;
     const int64_t na = (int64_t)L.n * L.width * bs * bs, nd = (int64_t)L.n * bs * bs;
     hipError_t e;

@@ -103,6 +103,7 @@ static void free_level(Level& L) {
         hipFree(L.dslot);
         hipFree(L.ablk);
         hipFree(L.ablk32);
+        hipFree(L.mrpart);
         hipFree(L.dblk);
         hipFree(L.as_cells);
         hipFree(L.as_rev);

@@ -324,10 +324,11 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_bj_sweep_mr(int n, int widt
 // step are 128 contiguous bytes. Tiles of 64 rows x 256 k: a block of four
 // wavefronts stages the tile's k range of every column in LDS (coalesced
 // along each column), each wavefront forms 16 rows for all columns on the
-// FP64 matrix cores in k order with 16 k steps of loads in flight, and the
-// tile's products go to part[k tile][row][column]; k_dense_mr_sum adds the
-// k tiles in order. At 5,120 rows that is 1,600 blocks, each streaming its
-// own 128 KB of the inverse once.
+// FP64 matrix cores in k order with the next 16 k steps of loads in flight
+// (the first while the columns are staged), and the tile's products go to
+// part[k tile][row][column]; k_dense_mr_sum adds the k tiles in order. At
+// 5,120 rows that is 1,600 blocks, each streaming its own 128 KB of the
+// inverse once.
 constexpr int kDenseRows = 64, kDenseK = 256, kDenseU = 16;
 __global__ __launch_bounds__(kDenseK) void k_dense_mr(int n, int np, const double* __restrict__ A, int nr, ColPtrs X,
                                                       double* __restrict__ part) {
@@ -336,31 +337,50 @@ __global__ __launch_bounds__(kDenseK) void k_dense_mr(int n, int np, const doubl
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k0 = blockIdx.y * kDenseK, kn = min(kDenseK, n - k0);
     const bool two = nr > 16;
-    const int nq = two ? kMaxCols : 16;
-    for (int q = 0; q < nq; ++q) {
-        const double* xq = q < nr ? X.p[q] : nullptr;
-        xs[q][threadIdx.x] = (xq && (int)threadIdx.x < kn) ? xq[k0 + threadIdx.x] : 0.0;
-    }
-    __syncthreads();
     const int r0 = blockIdx.x * kDenseRows + wv * 16;
     const int row = r0 + (l & 15), kk = l >> 4, c = l & 15;
     const bool rin = row < n;
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    const int ns = (kn + 3) / 4; // k steps of 4; entries past kn are zero on both sides
-    for (int s0 = 0; s0 < ns; s0 += kDenseU) {
-        double a[kDenseU];
+    // the tile's 64 k steps of 4 in four rounds of kDenseU; entries past kn
+    // are zero on both sides (exact), so every tile runs the same rounds and
+    // the next round's loads are always issued before this round's products
+    auto load = [&](double (&a)[kDenseU], int s0) {
 #pragma unroll
         for (int u = 0; u < kDenseU; ++u) {
             const int kl = (s0 + u) * 4 + kk;
             a[u] = (rin && kl < kn) ? A[(int64_t)(k0 + kl) * np + row] : 0.0;
         }
+    };
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    auto mma = [&](const double (&a)[kDenseU], int s0) {
 #pragma unroll
         for (int u = 0; u < kDenseU; ++u) {
-            const int kl = (s0 + u) * 4 + kk; // < kDenseK: s0 + u < 64
+            const int kl = (s0 + u) * 4 + kk;
             acc0 = M::mma(a[u], xs[c][kl], acc0);
             if (two) acc1 = M::mma(a[u], xs[16 + c][kl], acc1);
         }
+    };
+    double a0[kDenseU], a1[kDenseU];
+    load(a0, 0); // in flight together with the column loads
+    {
+        // every column load is issued before the first is waited for (a
+        // column past nr reads column 0 again, an entry past kn the last
+        // one; both are stored as zero)
+        const int kt = min((int)threadIdx.x, kn - 1);
+        double xv[kMaxCols];
+#pragma unroll
+        for (int q = 0; q < kMaxCols; ++q) xv[q] = X.p[q < nr ? q : 0][k0 + kt];
+#pragma unroll
+        for (int q = 0; q < kMaxCols; ++q) xs[q][threadIdx.x] = (q < nr && (int)threadIdx.x < kn) ? xv[q] : 0.0;
     }
+    __syncthreads();
+    static_assert(kDenseK == 4 * 4 * kDenseU, "four rounds per tile");
+    load(a1, kDenseU);
+    mma(a0, 0);
+    load(a0, 2 * kDenseU);
+    mma(a1, kDenseU);
+    load(a1, 3 * kDenseU);
+    mma(a0, 2 * kDenseU);
+    mma(a1, 3 * kDenseU);
     double* pb = part + (size_t)blockIdx.y * n * kMaxCols;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
